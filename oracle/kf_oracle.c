@@ -1,0 +1,249 @@
+/*
+ * Oracle for the volumetric integration of arXiv 1602.06645 (Sec. III, Sec. IV.A-B).
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain CPU implementation used by the tests, the smoke
+ * check and the benchmark's CPU-baseline leg.  The product library never links or calls
+ * it.  Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math), so that
+ * every multiply, add, fma, division and square root is the IEEE operation written.
+ *
+ * The FP32 instance is the parity reference: its masks and weights are exact targets.
+ * The FP64 instance and the adjoint serve the finite-difference and closed-form checks.
+ */
+#include "kf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- per-frame constants, double precision (Eq. 3 and Eq. 5 folded into affine maps) */
+
+/* 4x4 row-major rigid transform -> R (3x3) and t (3). */
+static void split_rt(const double* T, double* R, double* t)
+{
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = T[4 * r + c];
+        t[r] = T[4 * r + 3];
+    }
+}
+
+/* Voxel index (i,j,k) -> R (origin + (idx + 1/2) s) + t, as A idx + b with A = R diag(s). */
+static void fold_voxel_map(const double* R, const double* t, const double* origin,
+                           const double* s, double* A, double* b)
+{
+    double c0 = origin[0] + 0.5 * s[0];
+    double c1 = origin[1] + 0.5 * s[1];
+    double c2 = origin[2] + 0.5 * s[2];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) A[3 * r + c] = R[3 * r + c] * s[c];
+        b[r] = ((R[3 * r + 0] * c0 + R[3 * r + 1] * c1) + R[3 * r + 2] * c2) + t[r];
+    }
+}
+
+void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc64* out)
+{
+    double Rwc[9], twc[3], Rcw[9], tcw[3];
+    split_rt(fr->T_world_from_cam + 16 * (size_t)frame, Rwc, twc);
+    /* (R_n, t_n) of Eq. 5 maps world (first-frame) coordinates into the current depth
+     * camera: the inverse of the camera pose. */
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) Rcw[3 * r + c] = Rwc[3 * c + r];
+        tcw[r] = -((Rwc[0 + r] * twc[0] + Rwc[3 + r] * twc[1]) + Rwc[6 + r] * twc[2]);
+    }
+    /* Eq. 3: HD camera coordinates = R_calib * depth camera coordinates + t_calib. */
+    double Rrd[9], trd[3], Rhw[9], thw[3];
+    split_rt(fr->T_rgb_from_d, Rrd, trd);
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            Rhw[3 * r + c] = (Rrd[3 * r + 0] * Rcw[0 + c] + Rrd[3 * r + 1] * Rcw[3 + c])
+                             + Rrd[3 * r + 2] * Rcw[6 + c];
+        thw[r] = ((Rrd[3 * r + 0] * tcw[0] + Rrd[3 * r + 1] * tcw[1]) + Rrd[3 * r + 2] * tcw[2])
+                 + trd[r];
+    }
+    double sg[3], sc[3];
+    for (int a = 0; a < 3; ++a) {
+        sg[a] = vol->extent[a] / (double)vol->gdim[a];
+        sc[a] = vol->extent[a] / (double)vol->cdim[a];
+    }
+    fold_voxel_map(Rcw, tcw, vol->origin, sg, out->Ag, out->bg);
+    fold_voxel_map(Rcw, tcw, vol->origin, sc, out->Ac, out->bc);
+    fold_voxel_map(Rhw, thw, vol->origin, sc, out->Ah, out->bh);
+    out->fx = fr->K_d[0];
+    out->fy = fr->K_d[4];
+    out->cx = fr->K_d[2];
+    out->cy = fr->K_d[5];
+    out->inv_fx = 1.0 / fr->K_d[0];
+    out->inv_fy = 1.0 / fr->K_d[4];
+    out->fxr = fr->K_rgb[0];
+    out->fyr = fr->K_rgb[4];
+    out->cxr = fr->K_rgb[2];
+    out->cyr = fr->K_rgb[5];
+    out->trunc = fr->trunc;
+    out->inv_trunc = 1.0 / fr->trunc;
+    out->w_max = fr->w_max;
+    out->sigma2 = vol->sigma * vol->sigma;
+    out->gate = vol->gate;
+}
+
+static or_fc64* all_consts(const or_volume* vol, const or_frames* fr)
+{
+    int n = fr->n_frames > 0 ? fr->n_frames : 1;
+    or_fc64* fc = (or_fc64*)calloc((size_t)n, sizeof(or_fc64));
+    for (int f = 0; f < fr->n_frames; ++f) or_frame_consts(vol, fr, f, &fc[f]);
+    return fc;
+}
+
+/* ---- the per-voxel steps, instantiated in single and double precision */
+
+#define REAL float
+#define SFX _f32
+#define FMA fmaf
+#define SQRT sqrtf
+#define RINT rintf
+#define FLOOR floorf
+#define FMIN fminf
+#include "kf_oracle_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef SQRT
+#undef RINT
+#undef FLOOR
+#undef FMIN
+
+#define REAL double
+#define SFX _f64
+#define FMA fma
+#define SQRT sqrt
+#define RINT rint
+#define FLOOR floor
+#define FMIN fmin
+#include "kf_oracle_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef SQRT
+#undef RINT
+#undef FLOOR
+#undef FMIN
+
+void or_integrate_f32(const or_volume* vol, const or_frames* fr, float* tsdf, float* wg,
+                      float* r, float* g, float* b, float* wc, int gz0, int gz1, int cz0,
+                      int cz1, int frames_per_pass, int apply, uint8_t* gstatus,
+                      uint8_t* cstatus, int64_t* counters)
+{
+    or_fc64* fc = all_consts(vol, fr);
+    integrate__f32(vol, fr, fc, tsdf, wg, r, g, b, wc, gz0, gz1, cz0, cz1, frames_per_pass,
+                   apply, gstatus, cstatus, counters);
+    free(fc);
+}
+
+void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, double* wg,
+                      double* r, double* g, double* b, double* wc, int gz0, int gz1, int cz0,
+                      int cz1, int frames_per_pass, int apply, uint8_t* gstatus,
+                      uint8_t* cstatus, int64_t* counters)
+{
+    or_fc64* fc = all_consts(vol, fr);
+    integrate__f64(vol, fr, fc, tsdf, wg, r, g, b, wc, gz0, gz1, cz0, cz1, frames_per_pass,
+                   apply, gstatus, cstatus, counters);
+    free(fc);
+}
+
+/* ---- adjoint of the colour update (FP64)
+ *
+ * Eq. 9 is C_n = (1 - alpha_n) C_{n-1} + alpha_n s_n with alpha_n = W / (W_pre + W) in
+ * frames that update the voxel (0 otherwise), and Eq. 10 makes the weights independent
+ * of the HD image.  Hence C_N = sum_n beta_n s_n + prod_n (1 - alpha_n) C_0 with
+ * beta_n = alpha_n prod_{m>n} (1 - alpha_m); s_n is the bilinear HD sample at the
+ * projection (Eq. 2-4) of the voxel centre, which depends on T_rgb_from_d = (R_calib,
+ * t_calib).  The weights depend on T_rgb_from_d only through the HD bounds test.
+ */
+void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
+                     const double* g, int cz0, int cz1, double* d_rgb, double* d_xi)
+{
+    int n = fr->n_frames;
+    or_fc64* fc64 = all_consts(vol, fr);
+    or_fc__f64* fc = (or_fc__f64*)malloc(sizeof(or_fc__f64) * (size_t)(n > 0 ? n : 1));
+    for (int f = 0; f < n; ++f) round_consts__f64(&fc64[f], &fc[f]);
+    size_t dpix = (size_t)fr->dw * (size_t)fr->dh;
+    size_t cpix = (size_t)fr->cw * (size_t)fr->ch * 3;
+    memset(d_rgb, 0, sizeof(double) * cpix * (size_t)(n > 0 ? n : 0));
+    double xi0 = 0, xi1 = 0, xi2 = 0, xi3 = 0, xi4 = 0, xi5 = 0;
+    int CX = vol->cdim[0], CY = vol->cdim[1];
+    size_t nslab = (size_t)CX * (size_t)CY * (size_t)(cz1 - cz0);
+
+    #pragma omp parallel reduction(+:xi0,xi1,xi2,xi3,xi4,xi5)
+    {
+        or_ceval__f64* ev = (or_ceval__f64*)malloc(sizeof(or_ceval__f64) * (size_t)(n > 0 ? n : 1));
+        double* alpha = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        #pragma omp for schedule(static)
+        for (int k = cz0; k < cz1; ++k) {
+            for (int j = 0; j < CY; ++j) {
+                for (int i = 0; i < CX; ++i) {
+                    size_t idx = ((size_t)(k - cz0) * (size_t)CY + (size_t)j) * (size_t)CX + (size_t)i;
+                    double gv[3] = {g[idx], g[nslab + idx], g[2 * nslab + idx]};
+                    if (gv[0] == 0.0 && gv[1] == 0.0 && gv[2] == 0.0) continue;
+                    /* forward replay: which frames update the voxel, and alpha_n */
+                    double W = wc0 ? wc0[idx] : 0.0;
+                    for (int f = 0; f < n; ++f) {
+                        colour_eval__f64(&fc[f], fr->depth + (size_t)f * dpix, fr->dw, fr->dh,
+                                         fr->cw, fr->ch, i, j, k, W, &ev[f]);
+                        alpha[f] = 0.0;
+                        if (ev[f].status == OR_ST_UPDATED) {
+                            alpha[f] = ev[f].w / (W + ev[f].w);
+                            W = fma(ev[f].w, 1.0 - W, W);
+                        }
+                    }
+                    /* reverse sweep: beta_n = alpha_n prod_{m>n} (1 - alpha_m) */
+                    double tail = 1.0;
+                    for (int f = n - 1; f >= 0; --f) {
+                        if (ev[f].status != OR_ST_UPDATED) continue;
+                        double beta = alpha[f] * tail;
+                        tail *= 1.0 - alpha[f];
+                        const or_ceval__f64* e = &ev[f];
+                        const float* img = fr->rgbf + (size_t)f * cpix;
+                        double* dimg = d_rgb + (size_t)f * cpix;
+                        double ax = e->ax, ay = e->ay;
+                        double wts[4] = {(1 - ax) * (1 - ay), ax * (1 - ay), (1 - ax) * ay, ax * ay};
+                        size_t px[4];
+                        px[0] = ((size_t)e->y0 * (size_t)fr->cw + (size_t)e->x0) * 3;
+                        px[1] = px[0] + 3;
+                        px[2] = px[0] + (size_t)fr->cw * 3;
+                        px[3] = px[2] + 3;
+                        double iqz = 1.0 / e->q[2];
+                        double a[3] = {0, 0, 0};
+                        for (int ch = 0; ch < 3; ++ch) {
+                            double gb = gv[ch] * beta;
+                            if (gb == 0.0) continue;
+                            for (int q = 0; q < 4; ++q) {
+                                #pragma omp atomic
+                                dimg[px[q] + (size_t)ch] += gb * wts[q];
+                            }
+                            double p00 = img[px[0] + ch], p10 = img[px[1] + ch];
+                            double p01 = img[px[2] + ch], p11 = img[px[3] + ch];
+                            double dsx = (1 - ay) * (p10 - p00) + ay * (p11 - p01);
+                            double dsy = (1 - ax) * (p01 - p00) + ax * (p11 - p10);
+                            /* chain through the pinhole projection (Eq. 4 / z) */
+                            a[0] += gb * dsx * fc[f].fxr * iqz;
+                            a[1] += gb * dsy * fc[f].fyr * iqz;
+                            a[2] += -gb * (dsx * fc[f].fxr * e->q[0] + dsy * fc[f].fyr * e->q[1])
+                                    * iqz * iqz;
+                        }
+                        /* dq/d(rho, phi) = [I | -[q]x]  =>  d(phi) += q x a */
+                        xi0 += a[0];
+                        xi1 += a[1];
+                        xi2 += a[2];
+                        xi3 += e->q[1] * a[2] - e->q[2] * a[1];
+                        xi4 += e->q[2] * a[0] - e->q[0] * a[2];
+                        xi5 += e->q[0] * a[1] - e->q[1] * a[0];
+                    }
+                }
+            }
+        }
+        free(ev);
+        free(alpha);
+    }
+    d_xi[0] = xi0; d_xi[1] = xi1; d_xi[2] = xi2;
+    d_xi[3] = xi3; d_xi[4] = xi4; d_xi[5] = xi5;
+    free(fc);
+    free(fc64);
+}

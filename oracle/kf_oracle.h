@@ -1,0 +1,105 @@
+/*
+ * Oracle for the per-frame volumetric integration of "Creating Simplified 3D Models
+ * with High Quality Textures" (arXiv 1602.06645): the TSDF geometry volume of Sec. III
+ * and the asymmetric colour volume of Sec. IV.B (Eq. 5-10) with the depth-to-HD-RGB
+ * mapping of Sec. IV.A (Eq. 1-4), plus the adjoint of the colour update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow CPU implementation that the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg compare the GPU library
+ * against.  Nothing in the product library links, includes or calls it, and it shares
+ * no code with the GPU path.
+ *
+ * Conventions (all arrays host memory, row-major):
+ *   - volumes are dense, x fastest: index = x + X*(y + Y*z); voxel centres sit at
+ *     origin + (i + 1/2) * extent/dim on each axis; geometry and colour volumes share
+ *     origin and extent and differ in dimension (Sec. IV.B, asymmetric volume);
+ *   - depth is float metres [n][H][W], 0 (or any non-positive / non-finite value) marks
+ *     a hole; RGB is [n][CH][CW][3], either uint8 or float in [0,1];
+ *   - K matrices are 3x3 with zero skew; poses are 4x4 rigid transforms:
+ *     T_world_from_cam per frame, T_rgb_from_d = (R_calib | t_calib) of Eq. 3.
+ */
+#ifndef KF_ORACLE_H
+#define KF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Per-voxel outcome of one frame, in the order the tests are made. */
+enum {
+    OR_ST_FRUSTUM = 0,  /* behind the camera or projects outside the depth image    */
+    OR_ST_NODEPTH = 1,  /* the depth pixel is a hole                                */
+    OR_ST_BAND = 2,     /* geometry: farther than trunc behind the surface;
+                           colour: farther than sigma from the back-projected point */
+    OR_ST_NORMAL = 3,   /* colour: no normal (neighbour missing or degenerate)       */
+    OR_ST_GATE = 4,     /* colour: W does not exceed gate * W_pre                   */
+    OR_ST_HD = 5,       /* colour: the HD sample falls outside the HD image         */
+    OR_ST_UPDATED = 6
+};
+
+typedef struct {
+    int32_t gdim[3], cdim[3];
+    double origin[3], extent[3];
+    double sigma;  /* colour distance threshold in metres (paper: 20 mm) */
+    double gate;   /* colour weight gate factor (paper: 0.8)             */
+} or_volume;
+
+typedef struct {
+    int32_t n_frames, dw, dh, cw, ch;
+    const float* depth;            /* [n][dh][dw]                           */
+    const uint8_t* rgb8;           /* [n][ch][cw][3] or NULL                */
+    const float* rgbf;             /* [n][ch][cw][3] or NULL                */
+    const double* K_d;             /* [9]                                   */
+    const double* K_rgb;           /* [9]                                   */
+    const double* T_rgb_from_d;    /* [16]                                  */
+    const double* T_world_from_cam;/* [n][16]                               */
+    double trunc, w_max;
+} or_frames;
+
+/* The per-frame constants in double, before rounding (exposed for tests). */
+typedef struct {
+    double Ag[9], bg[3], Ac[9], bc[3], Ah[9], bh[3];
+    double fx, fy, cx, cy, inv_fx, inv_fy;
+    double fxr, fyr, cxr, cyr;
+    double trunc, inv_trunc, w_max, sigma2, gate;
+} or_fc64;
+
+void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc64* out);
+
+/*
+ * Forward integration in FP32 (or_integrate_f32) or FP64 (or_integrate_f64).
+ * State arrays cover geometry z-slabs [gz0,gz1) and colour z-slabs [cz0,cz1) only.
+ * apply = 0 leaves the state untouched (status-only).  gstatus/cstatus (optional)
+ * receive the OR_ST_* code of the last frame for each voxel.  counters (optional,
+ * int64[6], accumulated):
+ *   [0] geometry updates (voxel-frames)
+ *   [1] geometry voxels updated at least once per pass of frames_per_pass frames
+ *   [2] colour voxel-frames reaching the gate (the colour weight is read)
+ *   [3] colour voxels reaching the gate at least once per pass
+ *   [4] colour updates (voxel-frames)
+ *   [5] colour voxels updated at least once per pass
+ */
+void or_integrate_f32(const or_volume* vol, const or_frames* fr, float* tsdf, float* wg,
+                      float* r, float* g, float* b, float* wc, int gz0, int gz1, int cz0,
+                      int cz1, int frames_per_pass, int apply, uint8_t* gstatus,
+                      uint8_t* cstatus, int64_t* counters);
+void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, double* wg,
+                      double* r, double* g, double* b, double* wc, int gz0, int gz1, int cz0,
+                      int cz1, int frames_per_pass, int apply, uint8_t* gstatus,
+                      uint8_t* cstatus, int64_t* counters);
+
+/*
+ * Adjoint of the colour volume after all frames, in FP64, for the functional
+ * L = sum_v sum_ch g[ch][v] * C_N(v)_ch over colour z-slabs [cz0,cz1) (g covers those
+ * slabs only).  Starts from colour weights wc0 (NULL = zero).  Requires fr->rgbf.
+ * Writes dL/dRGB into d_rgb ([n][ch][cw][3], overwritten) and dL/dxi into d_xi[6],
+ * xi = (rho, phi) a left perturbation T_rgb_from_d <- exp(xi^) T_rgb_from_d at xi = 0.
+ */
+void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
+                     const double* g, int cz0, int cz1, double* d_rgb, double* d_xi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,199 @@
+"""ctypes wrapper of the C oracle (kf_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU-baseline
+leg use this module to compute the reference results of the volumetric integration of
+arXiv 1602.06645 (Sec. III TSDF volume; Sec. IV.B colour volume, Eq. 5-10; Sec. IV.A
+depth-to-HD mapping, Eq. 1-4).  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# The mutation tests point this at a copy of the oracle built with a planted mistake.
+LIB_PATH = os.environ.get("KF_ORACLE_LIB", DEFAULT_LIB_PATH)
+
+ST_FRUSTUM, ST_NODEPTH, ST_BAND, ST_NORMAL, ST_GATE, ST_HD, ST_UPDATED = range(7)
+
+
+def build(force: bool = True, src_dir: str = HERE, out: str = DEFAULT_LIB_PATH) -> str:
+    """Compile liboracle.so with plain IEEE arithmetic (no contraction, no fast-math)."""
+    if force or not os.path.exists(out):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-std=c11", "-Wall", "-shared", "-fPIC",
+               "-o", out + ".tmp", os.path.join(src_dir, "kf_oracle.c"), "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(out + ".tmp", out)
+    return out
+
+
+class _Volume(C.Structure):
+    _fields_ = [("gdim", C.c_int32 * 3), ("cdim", C.c_int32 * 3),
+                ("origin", C.c_double * 3), ("extent", C.c_double * 3),
+                ("sigma", C.c_double), ("gate", C.c_double)]
+
+
+class _Frames(C.Structure):
+    _fields_ = [("n_frames", C.c_int32), ("dw", C.c_int32), ("dh", C.c_int32),
+                ("cw", C.c_int32), ("ch", C.c_int32),
+                ("depth", C.c_void_p), ("rgb8", C.c_void_p), ("rgbf", C.c_void_p),
+                ("K_d", C.c_void_p), ("K_rgb", C.c_void_p),
+                ("T_rgb_from_d", C.c_void_p), ("T_world_from_cam", C.c_void_p),
+                ("trunc", C.c_double), ("w_max", C.c_double)]
+
+
+class _FC64(C.Structure):
+    _fields_ = [(n, C.c_double * 9) if n.startswith("A") else
+                (n, C.c_double * 3) if n.startswith("b") else (n, C.c_double)
+                for n in ["Ag", "bg", "Ac", "bc", "Ah", "bh", "fx", "fy", "cx", "cy",
+                          "inv_fx", "inv_fy", "fxr", "fyr", "cxr", "cyr", "trunc",
+                          "inv_trunc", "w_max", "sigma2", "gate"]]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False, out=LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        p = C.c_void_p
+        L.or_frame_consts.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames), C.c_int,
+                                      C.POINTER(_FC64)]
+        for name in ("or_integrate_f32", "or_integrate_f64"):
+            fn = getattr(L, name)
+            fn.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames)] + [p] * 6 + \
+                [C.c_int] * 6 + [p, p, p]
+            fn.restype = None
+        L.or_backward_f64.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames), p, p,
+                                      C.c_int, C.c_int, p, p]
+        L.or_backward_f64.restype = None
+        _lib = L
+    return _lib
+
+
+def _vol(vol) -> _Volume:
+    v = _Volume()
+    v.gdim[:] = [int(a) for a in vol.gdim]
+    v.cdim[:] = [int(a) for a in vol.cdim]
+    v.origin[:] = [float(a) for a in vol.origin]
+    v.extent[:] = [float(a) for a in vol.extent]
+    v.sigma = float(vol.sigma)
+    v.gate = float(vol.gate)
+    return v
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _frames(fr, keep: list) -> _Frames:
+    f = _Frames()
+    depth = _c(fr.depth, np.float32)
+    f.n_frames = depth.shape[0]
+    f.dh, f.dw = depth.shape[1], depth.shape[2]
+    f.depth = depth.ctypes.data
+    keep.append(depth)
+    f.rgb8 = f.rgbf = None
+    if fr.rgb.dtype == np.uint8:
+        rgb = _c(fr.rgb, np.uint8)
+        f.rgb8 = rgb.ctypes.data
+    else:
+        rgb = _c(fr.rgb, np.float32)
+        f.rgbf = rgb.ctypes.data
+    keep.append(rgb)
+    f.ch, f.cw = rgb.shape[1], rgb.shape[2]
+    for name in ("K_d", "K_rgb", "T_rgb_from_d", "T_world_from_cam"):
+        a = _c(getattr(fr, name), np.float64)
+        keep.append(a)
+        setattr(f, name, a.ctypes.data)
+    f.trunc = float(fr.trunc)
+    f.w_max = float(fr.w_max)
+    return f
+
+
+def frame_consts(vol, fr, frame: int) -> dict:
+    keep: list = []
+    out = _FC64()
+    lib().or_frame_consts(C.byref(_vol(vol)), C.byref(_frames(fr, keep)), frame, C.byref(out))
+    return {n: (np.array(getattr(out, n)) if isinstance(getattr(out, n), C.Array)
+                else getattr(out, n)) for n, _ in _FC64._fields_}
+
+
+class State:
+    """Host copy of the six SoA arrays for z-slabs [gz0,gz1) and [cz0,cz1)."""
+
+    def __init__(self, vol, dtype=np.float32, gz=None, cz=None):
+        gz = gz or (0, vol.gdim[2])
+        cz = cz or (0, vol.cdim[2])
+        self.gz, self.cz = (int(gz[0]), int(gz[1])), (int(cz[0]), int(cz[1]))
+        ng = vol.gdim[0] * vol.gdim[1] * (self.gz[1] - self.gz[0])
+        nc = vol.cdim[0] * vol.cdim[1] * (self.cz[1] - self.cz[0])
+        self.tsdf = np.zeros(ng, dtype)
+        self.wg = np.zeros(ng, dtype)
+        self.r = np.zeros(nc, dtype)
+        self.g = np.zeros(nc, dtype)
+        self.b = np.zeros(nc, dtype)
+        self.wc = np.zeros(nc, dtype)
+
+    @property
+    def dtype(self):
+        return self.tsdf.dtype
+
+    def arrays(self):
+        return [self.tsdf, self.wg, self.r, self.g, self.b, self.wc]
+
+
+def integrate(vol, fr, state: State, frames_per_pass: int = 1, apply: bool = True,
+              want_status: bool = False):
+    """Apply every frame of `fr` to `state` in order; return counters (and statuses).
+
+    Counters: [geometry updates, geometry voxels touched per pass, colour gate
+    evaluations, colour voxels reaching the gate per pass, colour updates, colour voxels
+    updated per pass].  Statuses are those of the last frame (OR_ST_* codes).
+    """
+    keep: list = []
+    f = _frames(fr, keep)
+    cnt = np.zeros(6, np.int64)
+    gst = cst = None
+    if want_status:
+        gst = np.zeros(state.tsdf.size, np.uint8)
+        cst = np.zeros(state.r.size, np.uint8)
+    fn = lib().or_integrate_f32 if state.dtype == np.float32 else lib().or_integrate_f64
+    fn(C.byref(_vol(vol)), C.byref(f), *[a.ctypes.data for a in state.arrays()],
+       state.gz[0], state.gz[1], state.cz[0], state.cz[1], int(frames_per_pass), int(apply),
+       None if gst is None else gst.ctypes.data, None if cst is None else cst.ctypes.data,
+       cnt.ctypes.data)
+    if want_status:
+        return cnt, gst, cst
+    return cnt
+
+
+def status(vol, fr, state: State, frame: int):
+    """Per-voxel status codes of one frame against the current state (no update)."""
+    sub = fr.select(frame)
+    _, gst, cst = integrate(vol, sub, state, apply=False, want_status=True)
+    return gst, cst
+
+
+def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None):
+    """FP64 adjoint: d L / d RGB ([n][ch][cw][3]) and d L / d xi (6) for
+    L = sum g[ch][v] C_N(v)_ch over colour slabs cz; g has shape (3, n_slab_voxels)."""
+    keep: list = []
+    f = _frames(fr, keep)
+    cz = cz or (0, vol.cdim[2])
+    g = _c(g, np.float64)
+    d_rgb = np.zeros((f.n_frames, f.ch, f.cw, 3), np.float64)
+    d_xi = np.zeros(6, np.float64)
+    w0 = None if wc0 is None else _c(wc0, np.float64)
+    lib().or_backward_f64(C.byref(_vol(vol)), C.byref(f),
+                          None if w0 is None else w0.ctypes.data, g.ctypes.data,
+                          int(cz[0]), int(cz[1]), d_rgb.ctypes.data, d_xi.ctypes.data)
+    return d_rgb, d_xi

@@ -1,0 +1,92 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each mutant is a copy of the oracle's C source with one plausible mistake (a wrong sign,
+a swapped index, a dropped term, a wrong rounding rule, a transposed operand).  The
+copy is compiled into a temporary library and the pin suites are run against it in a
+subprocess; every mutant must make them fail.  This is how the pins are shown to pin
+the oracle rather than merely agree with it.
+"""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+ORACLE = os.path.join(ROOT, "oracle")
+BODY, MAIN = "kf_oracle_body.h", "kf_oracle.c"
+
+# (name, file, original text, mutated text)
+MUTANTS = [
+    ("cx_for_x_uses_cy", BODY, "REAL x = FMA(c->fx, p[0] * iz, c->cx);", "REAL x = FMA(c->fx, p[0] * iz, c->cy);"),
+    ("fy_for_y_uses_fx", BODY, "REAL y = FMA(c->fy, p[1] * iz, c->cy);", "REAL y = FMA(c->fx, p[1] * iz, c->cy);"),
+    ("round_by_floor", BODY, "*u = RINT(x);", "*u = FLOOR(x);"),
+    ("frustum_off_by_one", BODY, "*u <= (REAL)(W - 1)", "*u <= (REAL)W"),
+    ("affine_drops_z_column", BODY, "FMA(A[3 * r + 2], fk, FMA(", "(0 * fk) + (FMA("),
+    ("trunc_sign", BODY, "if (sdf < -c->trunc) return OR_ST_BAND;", "if (sdf < c->trunc) return OR_ST_BAND;"),
+    ("tsdf_no_clamp", BODY, "REAL t = FMIN((REAL)1, sdf * c->inv_trunc);", "REAL t = sdf * c->inv_trunc;"),
+    ("tsdf_wrong_average", BODY, "*F = *F + (t - *F) / wn;", "*F = *F + (t - *F) / *Wg;"),
+    ("no_weight_cap", BODY, "*Wg = FMIN(wn, c->w_max);", "*Wg = wn;"),
+    ("backproject_y_uses_fx", BODY, "P[1] = ((v - c->cy) * c->inv_fy) * d;", "P[1] = ((v - c->cy) * c->inv_fx) * d;"),
+    ("sigma_not_squared", BODY, "if (dist2 > c->sigma2) return;", "if (dist2 > c->sigma2 * c->sigma2 * 4) return;"),
+    ("normal_operands_swapped", BODY, "REAL Nz = FMA(e1x, e2y, -(e1y * e2x));", "REAL Nz = FMA(e1y, e2x, -(e1x * e2y));"),
+    ("normal_neighbour_v_instead_of_u", BODY, "REAL d1 = (REAL)D[iv * (size_t)W + iu + 1];", "REAL d1 = (REAL)D[(iv + 1) * (size_t)W + iu];"),
+    ("weight_not_normalised", BODY, "e->w = dp / SQRT(nn * pp);", "e->w = dp / SQRT(pp);"),
+    ("gate_without_factor", BODY, "if (!(e->w > c->gate * Wc)) return;", "if (!(e->w > Wc)) return;"),
+    ("hd_ignores_extrinsic", BODY, "OR_FN(affine_)(c->Ah, c->bh, i, j, k, e->q);", "OR_FN(affine_)(c->Ac, c->bc, i, j, k, e->q);"),
+    ("hd_uses_depth_intrinsics", BODY, "e->xh = FMA(c->fxr, e->q[0] * iqz, c->cxr);", "e->xh = FMA(c->fx, e->q[0] * iqz, c->cx);"),
+    ("bilinear_wrong_fraction", BODY, "OR_FN(lerp_)(p00, p10, e->ax), OR_FN(lerp_)(p01, p11, e->ax), e->ay);", "OR_FN(lerp_)(p00, p10, e->ay), OR_FN(lerp_)(p01, p11, e->ax), e->ay);"),
+    ("colour_alpha_wrong", BODY, "REAL alpha = e->w / (*Wc + e->w);", "REAL alpha = e->w / ((REAL)1 + e->w);"),
+    ("eq10_dropped_factor", BODY, "*Wc = FMA(e->w, (REAL)1 - *Wc, *Wc);", "*Wc = *Wc + e->w;"),
+    ("rgb8_scale_wrong", BODY, "(REAL)rgb8[idx] * (REAL)(1.0 / 255.0)", "(REAL)rgb8[idx] * (REAL)(1.0 / 256.0)"),
+    ("pose_not_inverted", MAIN, "for (int c = 0; c < 3; ++c) Rcw[3 * r + c] = Rwc[3 * c + r];", "for (int c = 0; c < 3; ++c) Rcw[3 * r + c] = Rwc[3 * r + c];"),
+    ("translation_sign", MAIN, "tcw[r] = -((Rwc[0 + r] * twc[0]", "tcw[r] = +((Rwc[0 + r] * twc[0]"),
+    ("no_half_voxel_offset", MAIN, "double c0 = origin[0] + 0.5 * s[0];", "double c0 = origin[0];"),
+    ("extrinsic_composed_backwards", MAIN, "thw[r] = ((Rrd[3 * r + 0] * tcw[0] + Rrd[3 * r + 1] * tcw[1]) + Rrd[3 * r + 2] * tcw[2])\n                 + trd[r];", "thw[r] = tcw[r] + trd[r];"),
+    ("adjoint_beta_without_tail", MAIN, "double beta = alpha[f] * tail;", "double beta = alpha[f];"),
+    ("adjoint_dsy_wrong", MAIN, "double dsy = (1 - ax) * (p01 - p00) + ax * (p11 - p10);", "double dsy = (1 - ay) * (p01 - p00) + ay * (p11 - p10);"),
+    ("adjoint_rotation_sign", MAIN, "xi4 += e->q[2] * a[0] - e->q[0] * a[2];", "xi4 += e->q[0] * a[2] - e->q[2] * a[0];"),
+    ("adjoint_projection_z_term", MAIN, "a[2] += -gb * (dsx * fc[f].fxr * e->q[0] + dsy * fc[f].fyr * e->q[1])", "a[2] += -gb * (dsx * fc[f].fxr * e->q[0])"),
+]
+
+PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py")]
+
+
+def _run_mutant(m, workdir):
+    name, fname, old, new = m
+    src = os.path.join(workdir, name)
+    os.makedirs(src)
+    for f in (BODY, MAIN, "kf_oracle.h"):
+        shutil.copy(os.path.join(ORACLE, f), src)
+    path = os.path.join(src, fname)
+    text = open(path).read()
+    assert text.count(old) >= 1, f"mutant {name}: pattern not found"
+    open(path, "w").write(text.replace(old, new, 1))
+    lib = os.path.join(src, "liboracle.so")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c11",
+                           "-shared", "-fPIC", "-o", lib, os.path.join(src, MAIN), "-lm"])
+    env = dict(os.environ, KF_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=900)
+    return name, r.returncode
+
+
+def test_every_planted_mistake_is_caught():
+    names = [m[0] for m in MUTANTS]
+    assert len(set(names)) == len(names)
+    # control: an unmodified copy built and run the same way must pass every pin
+    control = ("control_unmodified", BODY, "static REAL OR_FN(lerp_)", "static REAL OR_FN(lerp_)")
+    with tempfile.TemporaryDirectory() as tmp:
+        with cf.ThreadPoolExecutor(max_workers=4) as ex:
+            results = list(ex.map(lambda m: _run_mutant(m, tmp), [control] + MUTANTS))
+    assert results[0] == ("control_unmodified", 0), "the unmodified oracle copy fails its pins"
+    results = results[1:]
+    survivors = [n for n, rc in results if rc == 0]
+    errors = [(n, rc) for n, rc in results if rc not in (0, 1)]
+    assert not errors, f"pin suite crashed (not a clean failure) for {errors}"
+    assert not survivors, f"planted mistakes not caught by any pin: {survivors}"
