@@ -1,0 +1,193 @@
+/*
+ * libkfvol: per-frame volumetric integration for RGB-D scanning with an HD colour
+ * camera, on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the integration step of "Creating Simplified 3D Models with High Quality
+ * Textures" (arXiv 1602.06645):
+ *   - the TSDF geometry volume the method inherits from KinectFusion (Sec. III): every
+ *     voxel is projected into the depth map and its truncated signed distance and weight
+ *     are updated by running average;
+ *   - the asymmetric colour volume of Sec. IV.B (Eq. 5-10): a volume over the same cube
+ *     with more voxels per axis; every colour voxel near the observed surface is weighted
+ *     by the cosine between the surface normal (Eq. 8) and the viewing ray, gated against
+ *     its previous weight, and blended with the HD image sample found through the
+ *     depth-to-HD calibration of Sec. IV.A (Eq. 1-4).
+ *
+ * Arithmetic: every decision is taken in IEEE single precision with a fixed sequence of
+ * operations (fused multiply-adds where written, correctly rounded division and square
+ * root, round-half-to-even pixel rounding), so masks and weights are reproducible
+ * bit for bit on any IEEE machine.
+ *
+ * Memory: every image and volume pointer below is a DEVICE pointer owned by the caller;
+ * it must stay valid until the work enqueued on `stream` has completed.  Matrices and
+ * poses are HOST arrays of doubles, row-major, read during the call.  `stream` is a
+ * hipStream_t (NULL = the null stream).  All calls are asynchronous unless stated
+ * otherwise: argument errors are returned before anything is enqueued; launch errors
+ * return KF_E_DEVICE; faults inside kernels surface at the caller's synchronisation.
+ * A volume handle may be used by one stream at a time.  Per voxel, frames are applied in
+ * call order and, within a batch, in array order.
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KF_OK = 0,
+    KF_E_ARG = 1,          /* NULL pointer, non-finite or out-of-domain parameter        */
+    KF_E_SHAPE = 2,        /* inconsistent or unsupported sizes                          */
+    KF_E_RANGE = 3,        /* sizes beyond what the library indexes (e.g. > 2^31 voxels) */
+    KF_E_DEVICE = 4,       /* a HIP call failed; see kf_last_error()                     */
+    KF_E_UNSUPPORTED = 5   /* valid request the library does not implement              */
+} kf_status;
+
+typedef enum {
+    KF_RGB8 = 0,   /* uint8 HWC, value / 255 is the colour in [0,1]          */
+    KF_RGBF32 = 1  /* float32 HWC, colour in [0,1] (any finite value works)  */
+} kf_pixfmt;
+
+/* Volume description.  Both volumes cover the same axis-aligned box (Sec. IV.B: the
+ * colour volume has a higher dimension but the same size); voxel (i,j,k) has its centre
+ * at origin + (i+1/2, j+1/2, k+1/2) * extent / dim; storage is x fastest. */
+typedef struct {
+    int32_t geom_dim[3];    /* geometry voxels per axis (x, y, z), each >= 1             */
+    int32_t colour_dim[3];  /* colour voxels per axis, each >= 1                          */
+    double origin[3];       /* world coordinates of the box's minimum corner (metres)    */
+    double extent[3];       /* box size (metres), each > 0                                */
+    double colour_band;     /* sigma: max distance from the measured surface point (m);
+                               the paper uses 20 mm (Sec. IV.B)                           */
+    double colour_gate;     /* update only if W > colour_gate * W_pre; paper: 0.8         */
+} kf_volume_desc;
+
+/* Six caller-owned device arrays of float32 (structure of arrays):
+ * tsdf, w_geom: geometry volume, prod(geom_dim) each;
+ * r, g, b, w_col: colour volume, prod(colour_dim) each.  A fresh volume is all zeros. */
+typedef struct {
+    float *tsdf, *w_geom, *r, *g, *b, *w_col;
+} kf_volume_buffers;
+
+typedef struct kf_volume kf_volume;
+
+/* Bytes of each of the six arrays (host-only, no device work). */
+kf_status kf_volume_buffer_bytes(const kf_volume_desc* desc, size_t out_bytes[6]);
+
+/* Validate `desc` and borrow `bufs` (not copied, not freed).  Host-only. */
+kf_status kf_volume_create(const kf_volume_desc* desc, const kf_volume_buffers* bufs,
+                           kf_volume** out);
+
+/* Zero all six arrays on `stream` (by a fill kernel, safe inside stream capture). */
+kf_status kf_volume_reset(kf_volume* vol, void* stream);
+
+/* Release the handle (the arrays stay with the caller). */
+void kf_volume_destroy(kf_volume* vol);
+
+/*
+ * Integrate one frame (Sec. III and Sec. IV.B).
+ *   depth: [dh][dw] float32 metres; 0, negative, NaN or infinite = no measurement.
+ *   rgb:   [ch][cw][3] in `fmt`; cw, ch >= 2.
+ *   K_d, K_rgb: 3x3 intrinsics (K_c, K_hd of Eq. 1-4), zero skew, last row (0,0,1),
+ *          positive focal lengths.
+ *   T_rgb_from_d: 4x4 rigid transform (R_calib, t_calib) of Eq. 3.
+ *   T_world_from_cam: 4x4 rigid pose of the depth camera; Eq. 5 uses its inverse.
+ *   trunc_m: truncation distance in metres (> 0); w_max: cap of the geometry weight (>= 1).
+ * Rigid transforms must have last row (0,0,0,1) and |R^T R - I| <= 1e-6.
+ */
+kf_status kf_integrate(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                       const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                       const double K_d[9], const double K_rgb[9],
+                       const double T_rgb_from_d[16], const double T_world_from_cam[16],
+                       double trunc_m, double w_max, void* stream);
+
+/* One scan for kf_integrate_batch: n_frames frames stored back to back. */
+typedef struct {
+    kf_volume* vol;
+    int32_t n_frames;
+    const float* depth;              /* device, [n][dh][dw]                          */
+    const void* rgb;                 /* device, [n][ch][cw][3]                       */
+    kf_pixfmt fmt;
+    int32_t dw, dh, cw, ch;
+    const double* K_d;               /* host [9]                                     */
+    const double* K_rgb;             /* host [9]                                     */
+    const double* T_rgb_from_d;      /* host [16]                                    */
+    const double* T_world_from_cam;  /* host [n][16]                                 */
+    double trunc_m, w_max;
+} kf_scene;
+
+/*
+ * Integrate several independent scans (different volumes, sizes and frame counts).
+ * Each voxel keeps its state in registers for frames_per_pass (K >= 1) consecutive
+ * frames of its scan, so a voxel's state is read and written once per pass instead of
+ * once per frame; all scans advance together in one persistent launch per pass that
+ * takes (scan, slab) work items from a queue.  The result equals integrating each scan
+ * frame by frame with kf_integrate.  use_graph != 0 records the passes into a HIP graph
+ * the first time a given batch (same pointers, sizes and matrices) is seen and replays
+ * it afterwards.  The volumes of the batch must be distinct.
+ */
+kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
+                             int32_t frames_per_pass, int32_t use_graph, void* stream);
+
+/*
+ * Byte accounting for kf_integrate_batch with the same arguments: performs the same
+ * integration and adds into counters (device, uint64[6], not cleared):
+ *   [0] geometry voxel updates        [1] geometry voxels updated at least once per pass
+ *   [2] colour voxel-frames reaching the weight gate
+ *   [3] colour voxels reaching the gate at least once per pass
+ *   [4] colour voxel updates          [5] colour voxels updated at least once per pass
+ * Slower than kf_integrate_batch; for measurement only.
+ */
+kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
+                                     int32_t frames_per_pass, unsigned long long* counters,
+                                     void* stream);
+
+/*
+ * Per-voxel outcome of one frame against the volume's current state, without updating
+ * it (same kernel as kf_integrate).  Codes: 0 outside the depth frustum, 1 no depth,
+ * 2 outside the band (geometry: more than trunc behind the surface; colour: more than
+ * colour_band from the back-projected depth pixel), 3 no normal, 4 weight gate failed,
+ * 5 HD sample outside the HD image, 6 updated.  geom_status / colour_status: device
+ * uint8 arrays of prod(geom_dim) / prod(colour_dim) elements.
+ */
+kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                          const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                          const double K_d[9], const double K_rgb[9],
+                          const double T_rgb_from_d[16], const double T_world_from_cam[16],
+                          double trunc_m, double w_max, uint8_t* geom_status,
+                          uint8_t* colour_status, void* stream);
+
+/*
+ * Adjoint of the colour volume with respect to the HD images and the RGB extrinsic
+ * (Eq. 9-10 with Eq. 2-4 differentiated through bilinear sampling and projection).
+ * For L = sum_v sum_c grad_rgb_vol[c][v] * C_N(v)_c, where C_N is the colour volume
+ * after integrating the n_frames frames (float32 images in [0,1]) starting from colour
+ * weights w_col0 (device, prod(colour_dim) floats, or NULL for zeros), writes
+ *   d_rgb: device float32 [n][ch][cw][3], overwritten with dL/dRGB;
+ *   d_xi:  device float64 [6], overwritten with dL/dxi, xi = (rho, phi) the se(3) left
+ *          perturbation T_rgb_from_d <- exp(xi^) T_rgb_from_d at xi = 0.
+ * The per-frame blending weights are recomputed from the depth maps (nothing from the
+ * forward is stored).  The geometry volume and the colour weights do not depend on the
+ * HD images or the extrinsic (except where a sample leaves the HD image), so they have no
+ * adjoint here.  Uses a workspace allocated on `stream` with the stream-ordered allocator.
+ */
+kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
+                                int32_t n_frames, const float* depth, const float* rgb_f32,
+                                int32_t dw, int32_t dh, int32_t cw, int32_t ch,
+                                const double K_d[9], const double K_rgb[9],
+                                const double T_rgb_from_d[16], const double* T_world_from_cam,
+                                const float* grad_rgb_vol, float* d_rgb,
+                                double* d_xi, void* stream);
+
+/* Message for a status code (static string). */
+const char* kf_status_str(kf_status s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* kf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KF_H */

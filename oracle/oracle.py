@@ -102,11 +102,12 @@ def _frames(fr, keep: list) -> _Frames:
     f.depth = depth.ctypes.data
     keep.append(depth)
     f.rgb8 = f.rgbf = None
-    if fr.rgb.dtype == np.uint8:
-        rgb = _c(fr.rgb, np.uint8)
+    rgb_in = np.asarray(fr.rgb)
+    if rgb_in.dtype == np.uint8:
+        rgb = _c(rgb_in, np.uint8)
         f.rgb8 = rgb.ctypes.data
     else:
-        rgb = _c(fr.rgb, np.float32)
+        rgb = _c(rgb_in, np.float32)
         f.rgbf = rgb.ctypes.data
     keep.append(rgb)
     f.ch, f.cw = rgb.shape[1], rgb.shape[2]

@@ -1,0 +1,80 @@
+"""ctypes declarations of the C ABI in include/kf.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkfvol.so")
+
+KF_OK, KF_E_ARG, KF_E_SHAPE, KF_E_RANGE, KF_E_DEVICE, KF_E_UNSUPPORTED = range(6)
+KF_RGB8, KF_RGBF32 = 0, 1
+
+
+class KfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class VolumeDesc(C.Structure):
+    _fields_ = [("geom_dim", C.c_int32 * 3), ("colour_dim", C.c_int32 * 3),
+                ("origin", C.c_double * 3), ("extent", C.c_double * 3),
+                ("colour_band", C.c_double), ("colour_gate", C.c_double)]
+
+
+class VolumeBuffers(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("tsdf", "w_geom", "r", "g", "b", "w_col")]
+
+
+class Scene(C.Structure):
+    _fields_ = [("vol", C.c_void_p), ("n_frames", C.c_int32), ("depth", C.c_void_p),
+                ("rgb", C.c_void_p), ("fmt", C.c_int32), ("dw", C.c_int32), ("dh", C.c_int32),
+                ("cw", C.c_int32), ("ch", C.c_int32), ("K_d", C.c_void_p),
+                ("K_rgb", C.c_void_p), ("T_rgb_from_d", C.c_void_p),
+                ("T_world_from_cam", C.c_void_p), ("trunc_m", C.c_double),
+                ("w_max", C.c_double)]
+
+
+_P = C.c_void_p
+_I = C.c_int32
+_D = C.c_double
+SIGNATURES = {
+    "kf_volume_buffer_bytes": (C.c_int, [C.POINTER(VolumeDesc), C.POINTER(C.c_size_t)]),
+    "kf_volume_create": (C.c_int, [C.POINTER(VolumeDesc), C.POINTER(VolumeBuffers), C.POINTER(C.c_void_p)]),
+    "kf_volume_reset": (C.c_int, [_P, _P]),
+    "kf_volume_destroy": (None, [_P]),
+    "kf_integrate": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P]),
+    "kf_integrate_batch": (C.c_int, [C.POINTER(Scene), _I, _I, _I, _P]),
+    "kf_integrate_batch_counted": (C.c_int, [C.POINTER(Scene), _I, _I, _P, _P]),
+    "kf_debug_status": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P, _P, _P]),
+    "kf_integrate_backward": (C.c_int, [C.POINTER(VolumeDesc), _P, _I, _P, _P, _I, _I, _I, _I,
+                                        _P, _P, _P, _P, _P, _P, _P, _P]),
+    "kf_status_str": (C.c_char_p, [C.c_int]),
+    "kf_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libkfvol.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1602_06645_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != KF_OK:
+        L = load()
+        msg = L.kf_last_error().decode() or L.kf_status_str(status).decode()
+        raise KfError(status, msg)

@@ -1,0 +1,214 @@
+"""Python face of libkfvol: torch tensors in, C ABI calls out.
+
+Every step of the integration runs in the HIP library; this module only checks tensor
+devices, dtypes and shapes, turns matrices into float64 host arrays, and passes pointers
+and torch's current HIP stream to the C functions of include/kf.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mat(a, shape) -> np.ndarray:
+    m = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if m.shape != shape:
+        raise ValueError(f"expected a matrix of shape {shape}, got {m.shape}")
+    return m
+
+
+def _ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, ndim: int | None = None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _rgb_fmt(rgb: torch.Tensor) -> int:
+    if rgb.dtype == torch.uint8:
+        return L.KF_RGB8
+    if rgb.dtype == torch.float32:
+        return L.KF_RGBF32
+    raise ValueError("rgb must be uint8 or float32")
+
+
+def volume_desc(spec) -> L.VolumeDesc:
+    d = L.VolumeDesc()
+    d.geom_dim[:] = [int(x) for x in spec.gdim]
+    d.colour_dim[:] = [int(x) for x in spec.cdim]
+    d.origin[:] = [float(x) for x in spec.origin]
+    d.extent[:] = [float(x) for x in spec.extent]
+    d.colour_band = float(spec.sigma)
+    d.colour_gate = float(spec.gate)
+    return d
+
+
+class Volume:
+    """A geometry volume and its asymmetric colour volume in six float32 device arrays
+    (tsdf, w_geom over geom_dim; r, g, b, w_col over colour_dim; x fastest), all zero."""
+
+    def __init__(self, spec, device="cuda"):
+        self.spec = spec
+        dev = torch.device(device)
+        ng = int(np.prod(spec.gdim))
+        nc = int(np.prod(spec.cdim))
+        z = lambda n: torch.zeros(n, dtype=torch.float32, device=dev)
+        self.tsdf, self.w_geom = z(ng), z(ng)
+        self.r, self.g, self.b, self.w_col = z(nc), z(nc), z(nc), z(nc)
+        self._desc = volume_desc(spec)
+        bufs = L.VolumeBuffers(*[t.data_ptr() for t in self.arrays()])
+        h = C.c_void_p()
+        L.check(L.load().kf_volume_create(C.byref(self._desc), C.byref(bufs), C.byref(h)))
+        self._h = h
+
+    def arrays(self):
+        return [self.tsdf, self.w_geom, self.r, self.g, self.b, self.w_col]
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.load().kf_volume_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def reset(self) -> None:
+        L.check(L.load().kf_volume_reset(self._h, _stream()))
+
+    def integrate(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam,
+                  trunc: float, w_max: float) -> None:
+        """One frame: depth [H,W] float32 metres, rgb [CH,CW,3] uint8 or float32."""
+        depth = _dev(depth, torch.float32, "depth", 2)
+        rgb = _dev(rgb, rgb.dtype, "rgb", 3)
+        Kd, Kr = _mat(K_d, (3, 3)), _mat(K_rgb, (3, 3))
+        Trd, Twc = _mat(T_rgb_from_d, (4, 4)), _mat(T_world_from_cam, (4, 4))
+        L.check(L.load().kf_integrate(
+            self._h, C.c_void_p(depth.data_ptr()), depth.shape[1], depth.shape[0],
+            C.c_void_p(rgb.data_ptr()), _rgb_fmt(rgb), rgb.shape[1], rgb.shape[0],
+            _ptr(Kd), _ptr(Kr), _ptr(Trd), _ptr(Twc), float(trunc), float(w_max), _stream()))
+
+    def status(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
+        """Per-voxel outcome codes of one frame (no update): (geometry, colour) uint8."""
+        depth = _dev(depth, torch.float32, "depth", 2)
+        rgb = _dev(rgb, rgb.dtype, "rgb", 3)
+        gs = torch.empty(self.tsdf.numel(), dtype=torch.uint8, device=self.tsdf.device)
+        cs = torch.empty(self.r.numel(), dtype=torch.uint8, device=self.r.device)
+        Kd, Kr = _mat(K_d, (3, 3)), _mat(K_rgb, (3, 3))
+        Trd, Twc = _mat(T_rgb_from_d, (4, 4)), _mat(T_world_from_cam, (4, 4))
+        L.check(L.load().kf_debug_status(
+            self._h, C.c_void_p(depth.data_ptr()), depth.shape[1], depth.shape[0],
+            C.c_void_p(rgb.data_ptr()), _rgb_fmt(rgb), rgb.shape[1], rgb.shape[0],
+            _ptr(Kd), _ptr(Kr), _ptr(Trd), _ptr(Twc), float(trunc), float(w_max),
+            C.c_void_p(gs.data_ptr()), C.c_void_p(cs.data_ptr()), _stream()))
+        return gs, cs
+
+
+class Scan:
+    """n frames for the batch call: depth [n,H,W] float32, rgb [n,CH,CW,3], one pose per
+    frame (T_world_from_cam [n,4,4]); K_d, K_rgb 3x3; T_rgb_from_d 4x4."""
+
+    def __init__(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
+        self.depth = _dev(depth, torch.float32, "depth", 3)
+        self.rgb = _dev(rgb, rgb.dtype, "rgb", 4)
+        self.fmt = _rgb_fmt(self.rgb)
+        n = self.depth.shape[0]
+        if self.rgb.shape[0] != n:
+            raise ValueError("depth and rgb hold different numbers of frames")
+        self.K_d, self.K_rgb = _mat(K_d, (3, 3)), _mat(K_rgb, (3, 3))
+        self.T_rgb_from_d = _mat(T_rgb_from_d, (4, 4))
+        self.T_world_from_cam = _mat(T_world_from_cam, (n, 4, 4))
+        self.trunc, self.w_max = float(trunc), float(w_max)
+
+    @staticmethod
+    def from_frames(fr) -> "Scan":
+        return Scan(fr.depth, fr.rgb, fr.K_d, fr.K_rgb, fr.T_rgb_from_d, fr.T_world_from_cam,
+                    fr.trunc, fr.w_max)
+
+    def scene(self, vol: Volume) -> L.Scene:
+        s = L.Scene()
+        s.vol = vol.handle.value
+        s.n_frames = self.depth.shape[0]
+        s.depth = self.depth.data_ptr()
+        s.rgb = self.rgb.data_ptr()
+        s.fmt = self.fmt
+        s.dh, s.dw = self.depth.shape[1], self.depth.shape[2]
+        s.ch, s.cw = self.rgb.shape[1], self.rgb.shape[2]
+        s.K_d = self.K_d.ctypes.data
+        s.K_rgb = self.K_rgb.ctypes.data
+        s.T_rgb_from_d = self.T_rgb_from_d.ctypes.data
+        s.T_world_from_cam = self.T_world_from_cam.ctypes.data
+        s.trunc_m, s.w_max = self.trunc, self.w_max
+        return s
+
+
+def _scenes(pairs):
+    arr = (L.Scene * max(1, len(pairs)))()
+    for q, (vol, scan) in enumerate(pairs):
+        arr[q] = scan.scene(vol)
+    return arr
+
+
+def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) -> None:
+    """Integrate [(Volume, Scan), ...]: every scan into its own volume, all together."""
+    arr = _scenes(pairs)
+    L.check(L.load().kf_integrate_batch(arr, len(pairs), int(frames_per_pass), int(use_graph),
+                                        _stream()))
+
+
+def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:
+    """Same as integrate_batch, and return the six byte-accounting counters (include/kf.h)."""
+    arr = _scenes(pairs)
+    dev = pairs[0][0].tsdf.device if pairs else torch.device("cuda")
+    cnt = torch.zeros(6, dtype=torch.int64, device=dev)
+    L.check(L.load().kf_integrate_batch_counted(arr, len(pairs), int(frames_per_pass),
+                                                C.c_void_p(cnt.data_ptr()), _stream()))
+    return cnt.cpu().numpy()
+
+
+def integrate_backward(spec, scan: Scan, grad: torch.Tensor, w_col0: torch.Tensor | None = None):
+    """dL/dRGB [n,CH,CW,3] float32 and dL/dxi [6] float64 (device) for
+    L = sum grad[c][v] C_N(v)_c; scan.rgb must be float32."""
+    if scan.fmt != L.KF_RGBF32:
+        raise ValueError("the adjoint takes float32 images")
+    nc = int(np.prod(spec.cdim))
+    grad = _dev(grad, torch.float32, "grad", 2)
+    if tuple(grad.shape) != (3, nc):
+        raise ValueError(f"grad must have shape (3, {nc})")
+    if w_col0 is not None:
+        w_col0 = _dev(w_col0, torch.float32, "w_col0", 1)
+        if w_col0.numel() != nc:
+            raise ValueError(f"w_col0 must hold {nc} weights")
+    n = scan.depth.shape[0]
+    d_rgb = torch.empty_like(scan.rgb)
+    d_xi = torch.empty(6, dtype=torch.float64, device=scan.rgb.device)
+    desc = volume_desc(spec)
+    L.check(L.load().kf_integrate_backward(
+        C.byref(desc), None if w_col0 is None else C.c_void_p(w_col0.data_ptr()), n,
+        C.c_void_p(scan.depth.data_ptr()), C.c_void_p(scan.rgb.data_ptr()),
+        scan.depth.shape[2], scan.depth.shape[1], scan.rgb.shape[2], scan.rgb.shape[1],
+        _ptr(scan.K_d), _ptr(scan.K_rgb), _ptr(scan.T_rgb_from_d), _ptr(scan.T_world_from_cam),
+        C.c_void_p(grad.data_ptr()), C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_xi.data_ptr()),
+        _stream()))
+    return d_rgb, d_xi

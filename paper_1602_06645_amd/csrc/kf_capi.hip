@@ -1,0 +1,734 @@
+// C ABI of libkfvol (declared in include/kf.h): argument validation, per-frame constants,
+// work decomposition, launch and graph management.  No arithmetic of the integration
+// itself happens here beyond the per-frame constants of Eq. 3 and Eq. 5, which are
+// composed in double precision and rounded once to single precision.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <list>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kf.h"
+#include "kf_device.h"
+#include "kf_launch.h"
+
+struct kf_volume {
+    kf_volume_desc desc;
+    kf_volume_buffers bufs;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+kf_status fail(kf_status s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+kf_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(KF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define KF_HIP(call, what)                         \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------------------- validation
+
+bool finite_all(const double* p, int n)
+{
+    for (int q = 0; q < n; ++q)
+        if (!isfinite(p[q])) return false;
+    return true;
+}
+
+kf_status check_K(const double* K, const char* name)
+{
+    if (!K) return fail(KF_E_ARG, "%s is NULL", name);
+    if (!finite_all(K, 9)) return fail(KF_E_ARG, "%s has a non-finite entry", name);
+    if (K[1] != 0.0 || K[3] != 0.0 || K[6] != 0.0 || K[7] != 0.0 || K[8] != 1.0)
+        return fail(KF_E_ARG, "%s must be [[fx,0,cx],[0,fy,cy],[0,0,1]]", name);
+    if (!(K[0] > 0.0) || !(K[4] > 0.0)) return fail(KF_E_ARG, "%s focal lengths must be > 0", name);
+    return KF_OK;
+}
+
+kf_status check_rigid(const double* T, const char* name)
+{
+    if (!T) return fail(KF_E_ARG, "%s is NULL", name);
+    if (!finite_all(T, 16)) return fail(KF_E_ARG, "%s has a non-finite entry", name);
+    if (T[12] != 0.0 || T[13] != 0.0 || T[14] != 0.0 || T[15] != 1.0)
+        return fail(KF_E_ARG, "%s last row must be (0,0,0,1)", name);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + r] * T[4 * k + c];
+            if (fabs(s - (r == c ? 1.0 : 0.0)) > 1e-6)
+                return fail(KF_E_ARG, "%s rotation is not orthonormal", name);
+        }
+    return KF_OK;
+}
+
+kf_status check_desc(const kf_volume_desc* d)
+{
+    if (!d) return fail(KF_E_ARG, "volume description is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->geom_dim[a] < 1 || d->colour_dim[a] < 1)
+            return fail(KF_E_SHAPE, "volume dimensions must be >= 1");
+        if (d->geom_dim[a] > 65536 || d->colour_dim[a] > 65536)
+            return fail(KF_E_RANGE, "volume dimension above 65536");
+        if (!isfinite(d->origin[a]) || !isfinite(d->extent[a]) || !(d->extent[a] > 0.0))
+            return fail(KF_E_ARG, "origin must be finite and extent > 0");
+    }
+    const double ng = (double)d->geom_dim[0] * d->geom_dim[1] * d->geom_dim[2];
+    const double nc = (double)d->colour_dim[0] * d->colour_dim[1] * d->colour_dim[2];
+    if (ng > 2147483647.0 || nc > 2147483647.0)
+        return fail(KF_E_RANGE, "a volume holds more than 2^31-1 voxels");
+    if (!isfinite(d->colour_band) || !(d->colour_band > 0.0))
+        return fail(KF_E_ARG, "colour_band must be finite and > 0");
+    if (!isfinite(d->colour_gate) || d->colour_gate < 0.0)
+        return fail(KF_E_ARG, "colour_gate must be finite and >= 0");
+    return KF_OK;
+}
+
+kf_status check_images(const float* depth, int32_t dw, int32_t dh, const void* rgb,
+                       int32_t fmt, int32_t cw, int32_t ch)
+{
+    if (dw < 1 || dh < 1) return fail(KF_E_SHAPE, "depth image must be at least 1x1");
+    if (cw < 2 || ch < 2) return fail(KF_E_SHAPE, "HD image must be at least 2x2");
+    if ((double)dw * dh > 2147483647.0 || (double)cw * ch * 3.0 > 2147483647.0)
+        return fail(KF_E_RANGE, "image too large");
+    if (fmt != KF_RGB8 && fmt != KF_RGBF32) return fail(KF_E_ARG, "unknown pixel format");
+    if (!depth || !rgb) return fail(KF_E_ARG, "image pointer is NULL");
+    return KF_OK;
+}
+
+kf_status check_scalars(double trunc_m, double w_max)
+{
+    if (!isfinite(trunc_m) || !(trunc_m > 0.0)) return fail(KF_E_ARG, "trunc_m must be finite and > 0");
+    if (!isfinite(w_max) || !(w_max >= 1.0)) return fail(KF_E_ARG, "w_max must be finite and >= 1");
+    return KF_OK;
+}
+
+kf_status check_volume(const kf_volume* v)
+{
+    if (!v) return fail(KF_E_ARG, "volume handle is NULL");
+    return KF_OK;
+}
+
+// ------------------------------------------------------------------ per-frame constants
+
+// Voxel index -> R (origin + (idx + 1/2) s) + t as A idx + b, A = R diag(s); double.
+void fold(const double R[9], const double t[3], const double origin[3], const double s[3],
+          double A[9], double b[3])
+{
+    const double c0 = origin[0] + 0.5 * s[0];
+    const double c1 = origin[1] + 0.5 * s[1];
+    const double c2 = origin[2] + 0.5 * s[2];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) A[3 * r + c] = R[3 * r + c] * s[c];
+        b[r] = ((R[3 * r + 0] * c0 + R[3 * r + 1] * c1) + R[3 * r + 2] * c2) + t[r];
+    }
+}
+
+void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_rgb,
+                  const double* T_rd, const double* T_wc, double trunc_m, double w_max,
+                  const float* depth, int32_t dw, int32_t dh, const void* rgb, int32_t cw,
+                  int32_t ch, kf::FrameConsts* out)
+{
+    // (R_n, t_n) of Eq. 5: world -> current depth camera, the inverse of the pose.
+    double Rcw[9], tcw[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) Rcw[3 * r + c] = T_wc[4 * c + r];
+        tcw[r] = -((T_wc[0 * 4 + r] * T_wc[3] + T_wc[1 * 4 + r] * T_wc[7]) + T_wc[2 * 4 + r] * T_wc[11]);
+    }
+    // Eq. 3 composed with Eq. 5: world -> HD camera.
+    double Rhw[9], thw[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            Rhw[3 * r + c] = (T_rd[4 * r + 0] * Rcw[0 + c] + T_rd[4 * r + 1] * Rcw[3 + c])
+                             + T_rd[4 * r + 2] * Rcw[6 + c];
+        thw[r] = ((T_rd[4 * r + 0] * tcw[0] + T_rd[4 * r + 1] * tcw[1]) + T_rd[4 * r + 2] * tcw[2])
+                 + T_rd[4 * r + 3];
+    }
+    double sg[3], sc[3];
+    for (int a = 0; a < 3; ++a) {
+        sg[a] = vd.extent[a] / (double)vd.geom_dim[a];
+        sc[a] = vd.extent[a] / (double)vd.colour_dim[a];
+    }
+    double Ag[9], bg[3], Ac[9], bc[3], Ah[9], bh[3];
+    fold(Rcw, tcw, vd.origin, sg, Ag, bg);
+    fold(Rcw, tcw, vd.origin, sc, Ac, bc);
+    fold(Rhw, thw, vd.origin, sc, Ah, bh);
+    for (int q = 0; q < 9; ++q) {
+        out->Ag[q] = (float)Ag[q];
+        out->Ac[q] = (float)Ac[q];
+        out->Ah[q] = (float)Ah[q];
+    }
+    for (int q = 0; q < 3; ++q) {
+        out->bg[q] = (float)bg[q];
+        out->bc[q] = (float)bc[q];
+        out->bh[q] = (float)bh[q];
+    }
+    out->fx = (float)K_d[0];
+    out->fy = (float)K_d[4];
+    out->cx = (float)K_d[2];
+    out->cy = (float)K_d[5];
+    out->inv_fx = (float)(1.0 / K_d[0]);
+    out->inv_fy = (float)(1.0 / K_d[4]);
+    out->fxr = (float)K_rgb[0];
+    out->fyr = (float)K_rgb[4];
+    out->cxr = (float)K_rgb[2];
+    out->cyr = (float)K_rgb[5];
+    out->trunc = (float)trunc_m;
+    out->inv_trunc = (float)(1.0 / trunc_m);
+    out->w_max = (float)w_max;
+    out->sigma2 = (float)(vd.colour_band * vd.colour_band);
+    out->gate = (float)vd.colour_gate;
+    out->wm1 = (float)(dw - 1);
+    out->hm1 = (float)(dh - 1);
+    out->cwm2 = (float)(cw - 2);
+    out->chm2 = (float)(ch - 2);
+    out->dw = dw;
+    out->dh = dh;
+    out->cw = cw;
+    out->ch = ch;
+    out->depth = depth;
+    out->rgb = rgb;
+}
+
+uint32_t ceil_div(int32_t a, int32_t b) { return (uint32_t)((a + b - 1) / b); }
+
+void scene_dev(const kf_volume* v, int32_t fmt, kf::SceneDev* s)
+{
+    memset(s, 0, sizeof *s);
+    s->tsdf = v->bufs.tsdf;
+    s->wg = v->bufs.w_geom;
+    s->r = v->bufs.r;
+    s->g = v->bufs.g;
+    s->b = v->bufs.b;
+    s->wc = v->bufs.w_col;
+    for (int a = 0; a < 3; ++a) {
+        s->gdim[a] = v->desc.geom_dim[a];
+        s->cdim[a] = v->desc.colour_dim[a];
+    }
+    s->gtiles[0] = (int32_t)ceil_div(s->gdim[0], kf::TX);
+    s->gtiles[1] = (int32_t)ceil_div(s->gdim[1], kf::TY);
+    s->gtiles[2] = (int32_t)ceil_div(s->gdim[2], kf::ZS);
+    s->ctiles[0] = (int32_t)ceil_div(s->cdim[0], kf::TX);
+    s->ctiles[1] = (int32_t)ceil_div(s->cdim[1], kf::TY);
+    s->ctiles[2] = (int32_t)ceil_div(s->cdim[2], kf::ZS);
+    s->geom_items = (uint32_t)s->gtiles[0] * (uint32_t)s->gtiles[1] * (uint32_t)s->gtiles[2];
+    s->colour_items = (uint32_t)s->ctiles[0] * (uint32_t)s->ctiles[1] * (uint32_t)s->ctiles[2];
+    s->fmt = fmt;
+}
+
+kf_status check_frame_args(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                           const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                           const double* K_d, const double* K_rgb, const double* T_rd,
+                           const double* T_wc, double trunc_m, double w_max)
+{
+    kf_status s;
+    if ((s = check_volume(vol)) != KF_OK) return s;
+    if ((s = check_images(depth, dw, dh, rgb, fmt, cw, ch)) != KF_OK) return s;
+    if ((s = check_K(K_d, "K_d")) != KF_OK) return s;
+    if ((s = check_K(K_rgb, "K_rgb")) != KF_OK) return s;
+    if ((s = check_rigid(T_rd, "T_rgb_from_d")) != KF_OK) return s;
+    if ((s = check_rigid(T_wc, "T_world_from_cam")) != KF_OK) return s;
+    return check_scalars(trunc_m, w_max);
+}
+
+// --------------------------------------------------------------- pinned staging buffer
+
+struct Staging {
+    std::mutex mu;
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+Staging g_stage;
+
+// Copy `bytes` from host memory `src` to device `dst` on `stream` through a pinned buffer
+// that is reused once the previous copy has completed.
+kf_status staged_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(g_stage.mu);
+    if (g_stage.pending) {
+        KF_HIP(hipEventSynchronize(g_stage.ev), "hipEventSynchronize");
+        g_stage.pending = false;
+    }
+    if (!g_stage.ev) KF_HIP(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming), "hipEventCreate");
+    if (bytes > g_stage.cap) {
+        if (g_stage.host) KF_HIP(hipHostFree(g_stage.host), "hipHostFree");
+        g_stage.host = nullptr;
+        size_t cap = bytes < 65536 ? 65536 : bytes * 2;
+        KF_HIP(hipHostMalloc(&g_stage.host, cap, hipHostMallocDefault), "hipHostMalloc");
+        g_stage.cap = cap;
+    }
+    memcpy(g_stage.host, src, bytes);
+    KF_HIP(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync");
+    KF_HIP(hipEventRecord(g_stage.ev, stream), "hipEventRecord");
+    g_stage.pending = true;
+    return KF_OK;
+}
+
+// -------------------------------------------------------------------- batch planning
+
+struct BatchPlan {
+    std::vector<kf::FrameConsts> frames;            // every frame of every scene
+    std::vector<std::vector<kf::SceneDev>> passes;  // scenes with frames in each pass
+    std::vector<uint32_t> pass_items;
+};
+
+kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchPlan* plan)
+{
+    if (!scenes && n_scenes > 0) return fail(KF_E_ARG, "scenes is NULL");
+    if (n_scenes < 0) return fail(KF_E_ARG, "n_scenes < 0");
+    if (K < 1) return fail(KF_E_ARG, "frames_per_pass must be >= 1");
+    std::vector<int32_t> first(n_scenes);
+    int32_t max_frames = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        const kf_scene& sc = scenes[s];
+        kf_status st;
+        if ((st = check_volume(sc.vol)) != KF_OK) return st;
+        for (int t = 0; t < s; ++t)
+            if (scenes[t].vol == sc.vol) return fail(KF_E_ARG, "a volume appears twice in one batch");
+        if (sc.n_frames < 0) return fail(KF_E_ARG, "n_frames < 0");
+        if (sc.n_frames == 0) { first[s] = (int32_t)plan->frames.size(); continue; }
+        if ((st = check_images(sc.depth, sc.dw, sc.dh, sc.rgb, sc.fmt, sc.cw, sc.ch)) != KF_OK) return st;
+        if ((st = check_K(sc.K_d, "K_d")) != KF_OK) return st;
+        if ((st = check_K(sc.K_rgb, "K_rgb")) != KF_OK) return st;
+        if ((st = check_rigid(sc.T_rgb_from_d, "T_rgb_from_d")) != KF_OK) return st;
+        if (!sc.T_world_from_cam) return fail(KF_E_ARG, "T_world_from_cam is NULL");
+        for (int f = 0; f < sc.n_frames; ++f)
+            if ((st = check_rigid(sc.T_world_from_cam + 16 * (size_t)f, "T_world_from_cam")) != KF_OK) return st;
+        if ((st = check_scalars(sc.trunc_m, sc.w_max)) != KF_OK) return st;
+        first[s] = (int32_t)plan->frames.size();
+        const size_t dpix = (size_t)sc.dw * sc.dh;
+        const size_t cbytes = (size_t)sc.cw * sc.ch * 3 * (sc.fmt == KF_RGB8 ? 1 : 4);
+        for (int f = 0; f < sc.n_frames; ++f) {
+            kf::FrameConsts fc;
+            frame_consts(sc.vol->desc, sc.K_d, sc.K_rgb, sc.T_rgb_from_d,
+                         sc.T_world_from_cam + 16 * (size_t)f, sc.trunc_m, sc.w_max,
+                         sc.depth + dpix * f, sc.dw, sc.dh,
+                         (const uint8_t*)sc.rgb + cbytes * f, sc.cw, sc.ch, &fc);
+            plan->frames.push_back(fc);
+        }
+        if (sc.n_frames > max_frames) max_frames = sc.n_frames;
+    }
+    if ((double)plan->frames.size() > 1e7) return fail(KF_E_RANGE, "too many frames in one batch");
+    for (int32_t f0 = 0; f0 < max_frames; f0 += K) {
+        std::vector<kf::SceneDev> pass;
+        uint64_t items = 0;
+        for (int s = 0; s < n_scenes; ++s) {
+            const int32_t nf = scenes[s].n_frames - f0;
+            if (nf <= 0) continue;
+            kf::SceneDev d;
+            scene_dev(scenes[s].vol, scenes[s].fmt, &d);
+            d.frame_begin = first[s] + f0;
+            d.n_frames = nf < K ? nf : K;
+            d.item_begin = (uint32_t)items;
+            items += (uint64_t)d.geom_items + d.colour_items;
+            if (items > 2147483647ull) return fail(KF_E_RANGE, "too many work items in one pass");
+            pass.push_back(d);
+        }
+        plan->passes.push_back(pass);
+        plan->pass_items.push_back((uint32_t)items);
+    }
+    return KF_OK;
+}
+
+// Device image of a plan: [frames][pass0 scenes][pass1 scenes]...[queue counters]
+struct DeviceTables {
+    std::vector<unsigned char> host;
+    size_t frames_off = 0, queue_off = 0;
+    std::vector<size_t> pass_off;
+};
+
+void layout_tables(const BatchPlan& p, DeviceTables* t)
+{
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t off = 0;
+    t->frames_off = off;
+    off = align(off + p.frames.size() * sizeof(kf::FrameConsts));
+    for (const auto& pass : p.passes) {
+        t->pass_off.push_back(off);
+        off = align(off + pass.size() * sizeof(kf::SceneDev));
+    }
+    t->queue_off = off;
+    off = align(off + (p.passes.size() + 1) * sizeof(uint32_t));
+    t->host.assign(off, 0);
+    if (!p.frames.empty())
+        memcpy(t->host.data() + t->frames_off, p.frames.data(), p.frames.size() * sizeof(kf::FrameConsts));
+    for (size_t q = 0; q < p.passes.size(); ++q)
+        if (!p.passes[q].empty())
+            memcpy(t->host.data() + t->pass_off[q], p.passes[q].data(), p.passes[q].size() * sizeof(kf::SceneDev));
+}
+
+kf_status resident_grid(int mode, uint32_t* grid)
+{
+    int device = 0;
+    KF_HIP(hipGetDevice(&device), "hipGetDevice");
+    KF_HIP(kf::persistent_grid(mode, device, grid), "occupancy query");
+    return KF_OK;
+}
+
+// Enqueue the passes of a plan whose tables live at `dev`; `grid` blocks per persistent
+// launch (resident_grid).
+kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
+                         unsigned long long* counters, uint32_t grid, hipStream_t stream)
+{
+    uint32_t* queues = (uint32_t*)(dev + t.queue_off);
+    KF_HIP(kf::launch_fill_u32(queues, p.passes.size() + 1, 0u, stream), "queue reset");
+    for (size_t q = 0; q < p.passes.size(); ++q) {
+        if (p.pass_items[q] == 0) continue;
+        kf::IntegrateArgs a;
+        memset(&a, 0, sizeof a);
+        a.scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
+        a.frames = (const kf::FrameConsts*)(dev + t.frames_off);
+        a.n_scenes = (int32_t)p.passes[q].size();
+        a.n_items = p.pass_items[q];
+        a.queue = queues + q;
+        a.counters = counters;
+        const uint32_t g = grid < a.n_items ? grid : a.n_items;
+        KF_HIP(kf::launch_integrate(mode, false, a, g, stream), "integrate launch");
+    }
+    return KF_OK;
+}
+
+// ------------------------------------------------------------------------ graph cache
+
+struct GraphEntry {
+    std::string key;
+    int device = 0;
+    unsigned char* dev = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::list<GraphEntry> lru;
+    hipStream_t capture[64] = {};
+};
+GraphCache g_graphs;
+constexpr size_t kMaxGraphs = 8;
+
+std::string batch_key(const kf_scene* scenes, int32_t n_scenes, int32_t K, int device)
+{
+    std::string k;
+    auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
+    put(&device, sizeof device);
+    put(&n_scenes, sizeof n_scenes);
+    put(&K, sizeof K);
+    for (int s = 0; s < n_scenes; ++s) {
+        const kf_scene& sc = scenes[s];
+        put(&sc.vol->desc, sizeof sc.vol->desc);
+        put(&sc.vol->bufs, sizeof sc.vol->bufs);
+        put(&sc.n_frames, sizeof sc.n_frames);
+        put(&sc.depth, sizeof sc.depth);
+        put(&sc.rgb, sizeof sc.rgb);
+        put(&sc.fmt, sizeof sc.fmt);
+        put(&sc.dw, 4 * sizeof(int32_t));
+        if (sc.n_frames > 0) {
+            put(sc.K_d, 9 * sizeof(double));
+            put(sc.K_rgb, 9 * sizeof(double));
+            put(sc.T_rgb_from_d, 16 * sizeof(double));
+            put(sc.T_world_from_cam, 16 * sizeof(double) * (size_t)sc.n_frames);
+        }
+        put(&sc.trunc_m, sizeof sc.trunc_m);
+        put(&sc.w_max, sizeof sc.w_max);
+    }
+    return k;
+}
+
+void drop_entry(GraphEntry& e)
+{
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.dev) (void)hipFree(e.dev);
+    e.exec = nullptr;
+    e.dev = nullptr;
+}
+
+kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStream_t stream)
+{
+    int device = 0;
+    KF_HIP(hipGetDevice(&device), "hipGetDevice");
+    if (device < 0 || device >= 64) return fail(KF_E_UNSUPPORTED, "device index above 63");
+    const std::string key = batch_key(scenes, n_scenes, K, device);
+    std::lock_guard<std::mutex> lock(g_graphs.mu);
+    for (auto it = g_graphs.lru.begin(); it != g_graphs.lru.end(); ++it) {
+        if (it->key == key) {
+            g_graphs.lru.splice(g_graphs.lru.begin(), g_graphs.lru, it);
+            KF_HIP(hipGraphLaunch(it->exec, stream), "hipGraphLaunch");
+            return KF_OK;
+        }
+    }
+    BatchPlan plan;
+    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    if (st != KF_OK) return st;
+    DeviceTables t;
+    layout_tables(plan, &t);
+    GraphEntry e;
+    e.key = key;
+    e.device = device;
+    KF_HIP(hipMalloc(&e.dev, t.host.size()), "hipMalloc");
+    hipError_t he = hipMemcpy(e.dev, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
+    if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipMemcpy"); }
+    uint32_t grid = 0;
+    if ((st = resident_grid(kf::MODE_INTEGRATE, &grid)) != KF_OK) { drop_entry(e); return st; }
+    hipStream_t& cs = g_graphs.capture[device];
+    if (!cs) {
+        he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamCreate"); }
+    }
+    he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamBeginCapture"); }
+    st = enqueue_passes(plan, t, e.dev, kf::MODE_INTEGRATE, nullptr, grid, cs);
+    hipGraph_t graph = nullptr;
+    he = hipStreamEndCapture(cs, &graph);
+    if (st != KF_OK) { if (graph) (void)hipGraphDestroy(graph); drop_entry(e); return st; }
+    if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamEndCapture"); }
+    he = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipGraphInstantiate"); }
+    he = hipGraphLaunch(e.exec, stream);
+    if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipGraphLaunch"); }
+    g_graphs.lru.push_front(e);
+    while (g_graphs.lru.size() > kMaxGraphs) {
+        drop_entry(g_graphs.lru.back());
+        g_graphs.lru.pop_back();
+    }
+    return KF_OK;
+}
+
+kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mode,
+                    unsigned long long* counters, hipStream_t stream)
+{
+    BatchPlan plan;
+    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    if (st != KF_OK) return st;
+    if (plan.passes.empty()) return KF_OK;
+    DeviceTables t;
+    layout_tables(plan, &t);
+    uint32_t grid = 0;
+    if ((st = resident_grid(mode, &grid)) != KF_OK) return st;
+    unsigned char* dev = nullptr;
+    KF_HIP(hipMallocAsync((void**)&dev, t.host.size(), stream), "hipMallocAsync");
+    st = staged_copy(dev, t.host.data(), t.host.size(), stream);
+    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream);
+    hipError_t he = hipFreeAsync(dev, stream);
+    if (st != KF_OK) return st;
+    if (he != hipSuccess) return hip_fail(he, "hipFreeAsync");
+    return KF_OK;
+}
+
+}  // namespace
+
+// =========================================================================== C ABI
+
+extern "C" {
+
+const char* kf_status_str(kf_status s)
+{
+    switch (s) {
+    case KF_OK: return "ok";
+    case KF_E_ARG: return "invalid argument";
+    case KF_E_SHAPE: return "invalid or unsupported shape";
+    case KF_E_RANGE: return "size out of range";
+    case KF_E_DEVICE: return "device error";
+    case KF_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* kf_last_error(void) { return g_err; }
+
+kf_status kf_volume_buffer_bytes(const kf_volume_desc* desc, size_t out_bytes[6])
+{
+    kf_status s = check_desc(desc);
+    if (s != KF_OK) return s;
+    if (!out_bytes) return fail(KF_E_ARG, "out_bytes is NULL");
+    const size_t ng = (size_t)desc->geom_dim[0] * desc->geom_dim[1] * desc->geom_dim[2];
+    const size_t nc = (size_t)desc->colour_dim[0] * desc->colour_dim[1] * desc->colour_dim[2];
+    for (int q = 0; q < 6; ++q) out_bytes[q] = (q < 2 ? ng : nc) * sizeof(float);
+    return KF_OK;
+}
+
+kf_status kf_volume_create(const kf_volume_desc* desc, const kf_volume_buffers* bufs,
+                           kf_volume** out)
+{
+    kf_status s = check_desc(desc);
+    if (s != KF_OK) return s;
+    if (!bufs || !out) return fail(KF_E_ARG, "buffers or output handle is NULL");
+    if (!bufs->tsdf || !bufs->w_geom || !bufs->r || !bufs->g || !bufs->b || !bufs->w_col)
+        return fail(KF_E_ARG, "a volume buffer is NULL");
+    kf_volume* v = new (std::nothrow) kf_volume;
+    if (!v) return fail(KF_E_DEVICE, "out of host memory");
+    v->desc = *desc;
+    v->bufs = *bufs;
+    *out = v;
+    return KF_OK;
+}
+
+void kf_volume_destroy(kf_volume* vol) { delete vol; }
+
+kf_status kf_volume_reset(kf_volume* vol, void* stream)
+{
+    kf_status s = check_volume(vol);
+    if (s != KF_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const kf_volume_desc& d = vol->desc;
+    const size_t ng = (size_t)d.geom_dim[0] * d.geom_dim[1] * d.geom_dim[2];
+    const size_t nc = (size_t)d.colour_dim[0] * d.colour_dim[1] * d.colour_dim[2];
+    float* arrays[6] = {vol->bufs.tsdf, vol->bufs.w_geom, vol->bufs.r, vol->bufs.g, vol->bufs.b, vol->bufs.w_col};
+    for (int q = 0; q < 6; ++q)
+        KF_HIP(kf::launch_fill_f32(arrays[q], q < 2 ? ng : nc, 0.0f, st), "volume reset");
+    return KF_OK;
+}
+
+static kf_status integrate_one(int mode, kf_volume* vol, const float* depth, int32_t dw,
+                               int32_t dh, const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                               const double* K_d, const double* K_rgb, const double* T_rd,
+                               const double* T_wc, double trunc_m, double w_max,
+                               uint8_t* gstatus, uint8_t* cstatus, void* stream)
+{
+    kf_status s = check_frame_args(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb, T_rd, T_wc,
+                                   trunc_m, w_max);
+    if (s != KF_OK) return s;
+    kf::IntegrateArgs a;
+    memset(&a, 0, sizeof a);
+    scene_dev(vol, fmt, &a.scene0);
+    a.scene0.n_frames = 1;
+    frame_consts(vol->desc, K_d, K_rgb, T_rd, T_wc, trunc_m, w_max, depth, dw, dh, rgb, cw, ch,
+                 &a.frame0);
+    a.n_scenes = 1;
+    a.n_items = a.scene0.geom_items + a.scene0.colour_items;
+    a.gstatus = gstatus;
+    a.cstatus = cstatus;
+    KF_HIP(kf::launch_integrate(mode, true, a, 0, (hipStream_t)stream), "integrate launch");
+    return KF_OK;
+}
+
+kf_status kf_integrate(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                       const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                       const double K_d[9], const double K_rgb[9],
+                       const double T_rgb_from_d[16], const double T_world_from_cam[16],
+                       double trunc_m, double w_max, void* stream)
+{
+    return integrate_one(kf::MODE_INTEGRATE, vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
+                         T_rgb_from_d, T_world_from_cam, trunc_m, w_max, nullptr, nullptr, stream);
+}
+
+kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                          const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                          const double K_d[9], const double K_rgb[9],
+                          const double T_rgb_from_d[16], const double T_world_from_cam[16],
+                          double trunc_m, double w_max, uint8_t* geom_status,
+                          uint8_t* colour_status, void* stream)
+{
+    if (!geom_status || !colour_status) return fail(KF_E_ARG, "status output is NULL");
+    return integrate_one(kf::MODE_STATUS, vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
+                         T_rgb_from_d, T_world_from_cam, trunc_m, w_max, geom_status,
+                         colour_status, stream);
+}
+
+kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t frames_per_pass,
+                             int32_t use_graph, void* stream)
+{
+    if (use_graph) {
+        // validate before looking at the cache, so errors never depend on its state
+        BatchPlan probe;
+        kf_status s = plan_batch(scenes, n_scenes, frames_per_pass, &probe);
+        if (s != KF_OK) return s;
+        if (probe.passes.empty()) return KF_OK;
+        return run_graph(scenes, n_scenes, frames_per_pass, (hipStream_t)stream);
+    }
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
+                     (hipStream_t)stream);
+}
+
+kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
+                                     int32_t frames_per_pass, unsigned long long* counters,
+                                     void* stream)
+{
+    if (!counters) return fail(KF_E_ARG, "counters is NULL");
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_COUNT, counters,
+                     (hipStream_t)stream);
+}
+
+kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
+                                int32_t n_frames, const float* depth, const float* rgb_f32,
+                                int32_t dw, int32_t dh, int32_t cw, int32_t ch,
+                                const double K_d[9], const double K_rgb[9],
+                                const double T_rgb_from_d[16], const double* T_world_from_cam,
+                                const float* grad_rgb_vol, float* d_rgb, double* d_xi,
+                                void* stream)
+{
+    kf_status s = check_desc(desc);
+    if (s != KF_OK) return s;
+    if (n_frames < 0) return fail(KF_E_ARG, "n_frames < 0");
+    if (n_frames > 64) return fail(KF_E_UNSUPPORTED, "the adjoint replays at most 64 frames per call");
+    if (!grad_rgb_vol || !d_xi || (n_frames > 0 && !d_rgb))
+        return fail(KF_E_ARG, "gradient pointer is NULL");
+    if (n_frames > 0) {
+        if ((s = check_images(depth, dw, dh, rgb_f32, KF_RGBF32, cw, ch)) != KF_OK) return s;
+        if ((s = check_K(K_d, "K_d")) != KF_OK) return s;
+        if ((s = check_K(K_rgb, "K_rgb")) != KF_OK) return s;
+        if ((s = check_rigid(T_rgb_from_d, "T_rgb_from_d")) != KF_OK) return s;
+        if (!T_world_from_cam) return fail(KF_E_ARG, "T_world_from_cam is NULL");
+        for (int f = 0; f < n_frames; ++f)
+            if ((s = check_rigid(T_world_from_cam + 16 * (size_t)f, "T_world_from_cam")) != KF_OK) return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    kf::BackwardArgs a;
+    memset(&a, 0, sizeof a);
+    for (int q = 0; q < 3; ++q) a.cdim[q] = desc->colour_dim[q];
+    a.ctiles[0] = (int32_t)ceil_div(a.cdim[0], kf::TX);
+    a.ctiles[1] = (int32_t)ceil_div(a.cdim[1], kf::TY);
+    a.ctiles[2] = (int32_t)ceil_div(a.cdim[2], kf::ZS);
+    a.n_items = (uint32_t)a.ctiles[0] * (uint32_t)a.ctiles[1] * (uint32_t)a.ctiles[2];
+    a.n_frames = n_frames;
+    a.wc0 = w_col0;
+    a.grad = grad_rgb_vol;
+    a.d_rgb = d_rgb;
+    std::vector<kf::FrameConsts> fc((size_t)(n_frames > 0 ? n_frames : 1));
+    const size_t dpix = (size_t)dw * dh, cvals = (size_t)cw * ch * 3;
+    for (int f = 0; f < n_frames; ++f)
+        frame_consts(*desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam + 16 * (size_t)f, 1.0, 1.0,
+                     depth + dpix * f, dw, dh, rgb_f32 + cvals * f, cw, ch, &fc[f]);
+    const size_t fbytes = fc.size() * sizeof(kf::FrameConsts);
+    const size_t pbytes = (size_t)(a.n_items > 0 ? a.n_items : 1) * 6 * sizeof(double);
+    unsigned char* ws = nullptr;
+    KF_HIP(hipMallocAsync((void**)&ws, fbytes + pbytes, st), "hipMallocAsync");
+    a.frames = (const kf::FrameConsts*)ws;
+    a.partials = (double*)(ws + fbytes);
+    s = staged_copy(ws, fc.data(), fbytes, st);
+    if (s == KF_OK && n_frames > 0) {
+        hipError_t e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st);
+        if (e != hipSuccess) s = hip_fail(e, "gradient reset");
+    }
+    if (s == KF_OK) {
+        hipError_t e = kf::launch_backward(a, d_xi, st);
+        if (e != hipSuccess) s = hip_fail(e, "backward launch");
+    }
+    hipError_t fe = hipFreeAsync(ws, st);
+    if (s != KF_OK) return s;
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+    return KF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads, exports every
+function declared in include/kf.h, and rejects bad arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1602_06645_amd import _lib as L
+from paper_1602_06645_amd.api import volume_desc
+from kf_synth.scenes import VolumeSpec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/kf.h but not exported"
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def _desc(**kw):
+    spec = VolumeSpec.cube(16, 2, 1.0)
+    d = volume_desc(spec)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_status_strings():
+    lib = L.load()
+    assert lib.kf_status_str(0) == b"ok"
+    assert lib.kf_status_str(4) == b"device error"
+    assert lib.kf_status_str(99) == b"unknown status"
+
+
+def test_buffer_bytes_and_desc_validation():
+    lib = L.load()
+    out = (C.c_size_t * 6)()
+    assert lib.kf_volume_buffer_bytes(C.byref(_desc()), out) == L.KF_OK
+    assert list(out) == [16 ** 3 * 4] * 2 + [32 ** 3 * 4] * 4
+    bad = _desc()
+    bad.geom_dim[1] = 0
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_SHAPE
+    assert b"dimension" in lib.kf_last_error()
+    bad = _desc()
+    bad.extent[2] = -1.0
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_ARG
+    bad = _desc(colour_band=float("nan"))
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_ARG
+    bad = _desc()
+    bad.colour_dim[:] = [2048, 2048, 1024]
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_RANGE
+    assert lib.kf_volume_buffer_bytes(None, out) == L.KF_E_ARG
+
+
+def _volume():
+    lib = L.load()
+    bufs = L.VolumeBuffers(*([0x1000] * 6))   # never dereferenced by these host-only calls
+    h = C.c_void_p()
+    assert lib.kf_volume_create(C.byref(_desc()), C.byref(bufs), C.byref(h)) == L.KF_OK
+    return h
+
+
+def test_create_rejects_null_buffers():
+    lib = L.load()
+    bufs = L.VolumeBuffers(0x1000, 0x1000, 0, 0x1000, 0x1000, 0x1000)
+    h = C.c_void_p()
+    assert lib.kf_volume_create(C.byref(_desc()), C.byref(bufs), C.byref(h)) == L.KF_E_ARG
+
+
+def _call_integrate(h, **over):
+    lib = L.load()
+    K = np.array([[525.0, 0, 319.5], [0, 525.0, 239.5], [0, 0, 1]])
+    Kr = np.array([[1050.0, 0, 959.5], [0, 1050.0, 539.5], [0, 0, 1]])
+    T = np.eye(4)
+    args = dict(depth=0x2000, dw=640, dh=480, rgb=0x3000, fmt=0, cw=1920, ch=1080, K_d=K,
+                K_rgb=Kr, T_rd=T, T_wc=T, trunc=0.01, w_max=128.0)
+    args.update(over)
+    keep = [np.ascontiguousarray(args[k], np.float64) for k in ("K_d", "K_rgb", "T_rd", "T_wc")]
+    return lib.kf_integrate(h, C.c_void_p(args["depth"]), args["dw"], args["dh"],
+                            C.c_void_p(args["rgb"]), args["fmt"], args["cw"], args["ch"],
+                            *[C.c_void_p(a.ctypes.data) for a in keep], args["trunc"],
+                            args["w_max"], None)
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(depth=0), L.KF_E_ARG),
+    (dict(dw=0), L.KF_E_SHAPE),
+    (dict(cw=1), L.KF_E_SHAPE),
+    (dict(fmt=7), L.KF_E_ARG),
+    (dict(trunc=0.0), L.KF_E_ARG),
+    (dict(trunc=float("inf")), L.KF_E_ARG),
+    (dict(w_max=0.5), L.KF_E_ARG),
+    (dict(K_d=np.array([[525.0, 1.0, 319.5], [0, 525.0, 239.5], [0, 0, 1]])), L.KF_E_ARG),
+    (dict(K_rgb=np.array([[-5.0, 0, 9.0], [0, 5.0, 5.0], [0, 0, 1]])), L.KF_E_ARG),
+    (dict(K_d=np.array([[525.0, 0, 319.5], [0, 525.0, 239.5], [0, 0, 2.0]])), L.KF_E_ARG),
+    (dict(T_wc=np.diag([1.0, 1.0, 1.1, 1.0])), L.KF_E_ARG),
+    (dict(T_rd=np.array([[1.0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0.1, 1]])), L.KF_E_ARG),
+    (dict(T_wc=np.full((4, 4), np.nan)), L.KF_E_ARG),
+    (dict(cw=50000, ch=50000), L.KF_E_RANGE),
+])
+def test_integrate_rejects_bad_arguments(over, code):
+    h = _volume()
+    try:
+        assert _call_integrate(h, **over) == code
+        assert L.load().kf_last_error() != b""
+    finally:
+        L.load().kf_volume_destroy(h)
+
+
+def test_null_handles():
+    lib = L.load()
+    assert lib.kf_volume_reset(None, None) == L.KF_E_ARG
+    lib.kf_volume_destroy(None)
+    assert _call_integrate(None) == L.KF_E_ARG
+
+
+def test_batch_rejects_bad_arguments():
+    lib = L.load()
+    h = _volume()
+    try:
+        assert lib.kf_integrate_batch(None, 1, 1, 0, None) == L.KF_E_ARG
+        sc = (L.Scene * 2)()
+        for q in range(2):
+            sc[q].vol = h.value
+            sc[q].n_frames = 0
+        assert lib.kf_integrate_batch(sc, 2, 1, 0, None) == L.KF_E_ARG   # same volume twice
+        assert b"twice" in lib.kf_last_error()
+        assert lib.kf_integrate_batch(sc, 1, 0, 0, None) == L.KF_E_ARG   # K < 1
+        sc[0].n_frames = -1
+        assert lib.kf_integrate_batch(sc, 1, 1, 0, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_counted(sc, 1, 1, None, None) == L.KF_E_ARG
+    finally:
+        lib.kf_volume_destroy(h)
+
+
+def test_backward_rejects_bad_arguments():
+    lib = L.load()
+    d = _desc()
+    args = [C.byref(d), None, 65, C.c_void_p(0x1), C.c_void_p(0x1), 640, 480, 1920, 1080,
+            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None]
+    assert lib.kf_integrate_backward(*args) == L.KF_E_UNSUPPORTED
+    args[2] = 4
+    assert lib.kf_integrate_backward(*args) == L.KF_E_ARG     # K_d is NULL
+    args[2] = -1
+    assert lib.kf_integrate_backward(*args) == L.KF_E_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        L.load()
