@@ -157,13 +157,43 @@ void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, d
  * projection (Eq. 2-4) of the voxel centre, which depends on T_rgb_from_d = (R_calib,
  * t_calib).  The weights depend on T_rgb_from_d only through the HD bounds test.
  */
+/* FP64 values of one colour update whose integer decisions (depth pixel (u,v), bilinear
+ * cell (x0,y0)) were taken elsewhere: the weight W of Eq. 8 and the HD-camera point q
+ * with its image coordinates (Eq. 2-5). */
+static void colour_values_f64(const or_fc__f64* c, const float* D, int W, int u, int v,
+                              int i, int j, int k, or_ceval__f64* e)
+{
+    double P[3], P1[3], P2[3];
+    size_t pix = (size_t)v * (size_t)W + (size_t)u;
+    backproject__f64(c, (double)u, (double)v, (double)D[pix], P);
+    backproject__f64(c, (double)u + 1.0, (double)v, (double)D[pix + 1], P1);
+    backproject__f64(c, (double)u, (double)v + 1.0, (double)D[pix + (size_t)W], P2);
+    double e1[3] = {P1[0] - P[0], P1[1] - P[1], P1[2] - P[2]};
+    double e2[3] = {P2[0] - P[0], P2[1] - P[1], P2[2] - P[2]};
+    double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                   e1[0] * e2[1] - e1[1] * e2[0]};
+    double nn = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+    double pp = P[0] * P[0] + P[1] * P[1] + P[2] * P[2];
+    e->w = (N[0] * P[0] + N[1] * P[1] + N[2] * P[2]) / sqrt(nn * pp);
+    affine__f64(c->Ah, c->bh, i, j, k, e->q);
+    e->xh = c->fxr * (e->q[0] / e->q[2]) + c->cxr;
+    e->yh = c->fyr * (e->q[1] / e->q[2]) + c->cyr;
+    e->ax = e->xh - (double)e->x0;
+    e->ay = e->yh - (double)e->y0;
+}
+
 void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
-                     const double* g, int cz0, int cz1, double* d_rgb, double* d_xi)
+                     const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
+                     double* d_xi)
 {
     int n = fr->n_frames;
     or_fc64* fc64 = all_consts(vol, fr);
     or_fc__f64* fc = (or_fc__f64*)malloc(sizeof(or_fc__f64) * (size_t)(n > 0 ? n : 1));
-    for (int f = 0; f < n; ++f) round_consts__f64(&fc64[f], &fc[f]);
+    or_fc__f32* fc32 = (or_fc__f32*)malloc(sizeof(or_fc__f32) * (size_t)(n > 0 ? n : 1));
+    for (int f = 0; f < n; ++f) {
+        round_consts__f64(&fc64[f], &fc[f]);
+        round_consts__f32(&fc64[f], &fc32[f]);
+    }
     size_t dpix = (size_t)fr->dw * (size_t)fr->dh;
     size_t cpix = (size_t)fr->cw * (size_t)fr->ch * 3;
     memset(d_rgb, 0, sizeof(double) * cpix * (size_t)(n > 0 ? n : 0));
@@ -184,9 +214,25 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
                     if (gv[0] == 0.0 && gv[1] == 0.0 && gv[2] == 0.0) continue;
                     /* forward replay: which frames update the voxel, and alpha_n */
                     double W = wc0 ? wc0[idx] : 0.0;
+                    float W32 = (float)W;
                     for (int f = 0; f < n; ++f) {
-                        colour_eval__f64(&fc[f], fr->depth + (size_t)f * dpix, fr->dw, fr->dh,
-                                         fr->cw, fr->ch, i, j, k, W, &ev[f]);
+                        const float* Df = fr->depth + (size_t)f * dpix;
+                        if (decide_f32) {
+                            /* the decisions of the single-precision forward */
+                            or_ceval__f32 e32;
+                            colour_eval__f32(&fc32[f], Df, fr->dw, fr->dh, fr->cw, fr->ch, i, j, k,
+                                             W32, &e32);
+                            ev[f].status = e32.status;
+                            if (e32.status == OR_ST_UPDATED) {
+                                W32 = fmaf(e32.w, 1.0f - W32, W32);
+                                ev[f].x0 = e32.x0;
+                                ev[f].y0 = e32.y0;
+                                colour_values_f64(&fc[f], Df, fr->dw, e32.u, e32.v, i, j, k, &ev[f]);
+                            }
+                        } else {
+                            colour_eval__f64(&fc[f], Df, fr->dw, fr->dh, fr->cw, fr->ch, i, j, k,
+                                             W, &ev[f]);
+                        }
                         alpha[f] = 0.0;
                         if (ev[f].status == OR_ST_UPDATED) {
                             alpha[f] = ev[f].w / (W + ev[f].w);
@@ -245,5 +291,6 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
     d_xi[0] = xi0; d_xi[1] = xi1; d_xi[2] = xi2;
     d_xi[3] = xi3; d_xi[4] = xi4; d_xi[5] = xi5;
     free(fc);
+    free(fc32);
     free(fc64);
 }

@@ -95,9 +95,13 @@ void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, d
  * slabs only).  Starts from colour weights wc0 (NULL = zero).  Requires fr->rgbf.
  * Writes dL/dRGB into d_rgb ([n][ch][cw][3], overwritten) and dL/dxi into d_xi[6],
  * xi = (rho, phi) a left perturbation T_rgb_from_d <- exp(xi^) T_rgb_from_d at xi = 0.
+ * decide_f32 = 0: every step in FP64 (the adjoint of the FP64 forward).
+ * decide_f32 = 1: the integer decisions (depth pixel, the tests of Sec. IV.B, the
+ * bilinear cell) are those of the FP32 forward; the values stay FP64.
  */
 void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
-                     const double* g, int cz0, int cz1, double* d_rgb, double* d_xi);
+                     const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
+                     double* d_xi);
 
 #ifdef __cplusplus
 }

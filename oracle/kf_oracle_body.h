@@ -121,6 +121,7 @@ static void OR_FN(backproject_)(const OR_T(or_fc_)* c, REAL u, REAL v, REAL d, R
  * state, plus where it samples the HD image.  Filled by colour_eval_. */
 typedef struct {
     int status;       /* OR_ST_* (OR_ST_UPDATED when every test passes)         */
+    int u, v;         /* nearest depth pixel (valid from OR_ST_NODEPTH on)       */
     REAL w;           /* normal-times-view weight W (Sec. IV.B, Eq. 8)           */
     REAL q[3];        /* voxel centre in HD camera coordinates (Eq. 5 then 3)    */
     REAL xh, yh;      /* HD image coordinates (Eq. 4 with perspective division) */
@@ -139,6 +140,8 @@ static void OR_FN(colour_eval_)(const OR_T(or_fc_)* c, const float* D, int W, in
     OR_FN(affine_)(c->Ac, c->bc, i, j, k, p);
     if (!OR_FN(project_depth_)(c, p, W, H, &u, &v)) return;
     size_t iu = (size_t)(int)u, iv = (size_t)(int)v;
+    e->u = (int)u;
+    e->v = (int)v;
     REAL d = (REAL)D[iv * (size_t)W + iu];
     e->status = OR_ST_NODEPTH;
     if (!OR_FN(valid_depth_)(d)) return;

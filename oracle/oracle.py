@@ -73,7 +73,7 @@ def lib():
                 [C.c_int] * 6 + [p, p, p]
             fn.restype = None
         L.or_backward_f64.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames), p, p,
-                                      C.c_int, C.c_int, p, p]
+                                      C.c_int, C.c_int, C.c_int, p, p]
         L.or_backward_f64.restype = None
         _lib = L
     return _lib
@@ -184,9 +184,12 @@ def status(vol, fr, state: State, frame: int):
     return gst, cst
 
 
-def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None):
+def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None,
+             decide_f32: bool = False):
     """FP64 adjoint: d L / d RGB ([n][ch][cw][3]) and d L / d xi (6) for
-    L = sum g[ch][v] C_N(v)_ch over colour slabs cz; g has shape (3, n_slab_voxels)."""
+    L = sum g[ch][v] C_N(v)_ch over colour slabs cz; g has shape (3, n_slab_voxels).
+    decide_f32: take the integer decisions (pixel, masks, gate, bilinear cell) of the
+    FP32 forward, as the GPU kernel does; otherwise everything is FP64."""
     keep: list = []
     f = _frames(fr, keep)
     cz = cz or (0, vol.cdim[2])
@@ -196,5 +199,6 @@ def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None):
     w0 = None if wc0 is None else _c(wc0, np.float64)
     lib().or_backward_f64(C.byref(_vol(vol)), C.byref(f),
                           None if w0 is None else w0.ctypes.data, g.ctypes.data,
-                          int(cz[0]), int(cz[1]), d_rgb.ctypes.data, d_xi.ctypes.data)
+                          int(cz[0]), int(cz[1]), int(decide_f32), d_rgb.ctypes.data,
+                          d_xi.ctypes.data)
     return d_rgb, d_xi

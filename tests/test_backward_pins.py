@@ -168,3 +168,17 @@ def test_backward_from_nonzero_initial_weights(oracle):
         rgb[f, y, x, c] = np.float32(old + 0.25)
         delta = np.float64(rgb[f, y, x, c]) - old
         assert (loss(rgb) - L0) / delta == pytest.approx(d_rgb[f, y, x, c], rel=1e-9, abs=1e-12)
+
+
+def test_fp32_decision_mode_agrees_away_from_ties(oracle):
+    """The adjoint with the FP32 forward's integer decisions equals the all-FP64 adjoint
+    on voxels whose decisions are not within rounding of a threshold in any frame."""
+    vol, fr = _scan(n=5, g=24, ratio=2)
+    amb = brute.colour(vol, fr, brute.FP32_MARGINS)["ambiguous"]
+    g = np.random.default_rng(12).standard_normal((3, vol.n_colour))
+    g[:, amb] = 0.0
+    r64, x64 = oracle.backward(vol, fr, g)
+    r32, x32 = oracle.backward(vol, fr, g, decide_f32=True)
+    assert np.abs(x64).max() > 1e-2
+    np.testing.assert_allclose(x32, x64, rtol=1e-3, atol=1e-3 * np.abs(x64).max())
+    np.testing.assert_allclose(r32, r64, rtol=1e-3, atol=1e-3 * np.abs(r64).max())

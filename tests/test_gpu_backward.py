@@ -35,7 +35,7 @@ def test_backward_matches_oracle_adjoint(oracle, scan):
     say("backward: tiny, 6 frames")
     g = configs.gradient_weights(spec.n_colour)
     d_rgb, d_xi = kf.integrate_backward(spec, kf.Scan.from_frames(fr.to(DEV)), g.to(DEV))
-    want_rgb, want_xi = oracle.backward(spec, fr, g.numpy().astype(np.float64))
+    want_rgb, want_xi = oracle.backward(spec, fr, g.numpy().astype(np.float64), decide_f32=True)
     torch.cuda.synchronize()
     _close(d_rgb.cpu().numpy(), want_rgb)
     _close(d_xi.cpu().numpy(), want_xi)
@@ -69,7 +69,7 @@ def test_backward_with_initial_weights(oracle, scan):
     g = configs.gradient_weights(spec.n_colour)
     d_rgb, d_xi = kf.integrate_backward(spec, kf.Scan.from_frames(fr.to(DEV)), g.to(DEV),
                                         torch.as_tensor(w0, device=DEV))
-    want_rgb, want_xi = oracle.backward(spec, fr, g.numpy().astype(np.float64), wc0=w0.astype(np.float64))
+    want_rgb, want_xi = oracle.backward(spec, fr, g.numpy().astype(np.float64), wc0=w0.astype(np.float64), decide_f32=True)
     torch.cuda.synchronize()
     _close(d_rgb.cpu().numpy(), want_rgb)
     _close(d_xi.cpu().numpy(), want_xi)
@@ -144,7 +144,7 @@ def test_backward_full_size_sampled_slabs(oracle):
     frn = fr.numpy()
     for z0, part in gsl:
         say(f"  oracle adjoint on colour slab z[{z0},{z0 + 4})")
-        r, x = oracle.backward(spec, frn, part, cz=(z0, z0 + 4))
+        r, x = oracle.backward(spec, frn, part, cz=(z0, z0 + 4), decide_f32=True)
         want_rgb = want_rgb + r
         want_xi = want_xi + x
     torch.cuda.synchronize()
