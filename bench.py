@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-frame volumetric integration (TSDF geometry volume + asymmetric
+colour volume, arXiv 1602.06645 Sec. III and IV.B) on one MI355X.
+
+Workload (synthetic, seeded): geometry 256^3 + colour 512^3 over a 0.75 m cube, a
+300-frame orbit of 640x480 float depth (noisy, 1 % holes) and 1920x1080 RGB8 images of
+3 spheres and 2 boxes on a plane; trunc = 4 geometry voxels, w_max = 128.
+
+One step = one whole scan: reset the volume, then integrate all 300 frames in passes of
+K frames (each pass one persistent launch replayed from a HIP graph).  The metric counts
+every voxel of both volumes once per frame (the swept voxel updates of KinectFusion-style
+integration).  Besides the headline line the JSON carries: the plain frame-by-frame path
+and the fused/plain speedup, forward + backward time of the differentiable form on the
+first 32 frames, the HBM roofline of the dominant kernel from algorithmic bytes counted by
+the kernel's counting instantiation, and the CPU oracle timed on a sample.
+
+Usage: python bench.py [--steps K] [--warmup W] [--frames N] [--frames-per-pass K]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel updates/s (geometry+colour) & % HBM roofline; fused-vs-plain; fwd+bwd ms"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("kinect-like scan: geometry 256^3 + colour 512^3 (2x per axis) over 0.75 m, "
+            "300 frames of 640x480 float32 depth + 1920x1080 RGB8")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def default_frames_per_pass() -> int:
+    path = os.path.join(ROOT, "paper_1602_06645_amd", "tuning.json")
+    try:
+        with open(path) as f:
+            return int(json.load(f)["kinect"]["frames_per_pass"])
+    except (OSError, KeyError, ValueError):
+        return 8
+
+
+def pass_scans(kf, fr, K):
+    out = []
+    for p in range(0, fr.n, K):
+        q = min(fr.n, p + K)
+        out.append(kf.Scan(fr.depth[p:q], fr.rgb[p:q], fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
+                           fr.T_world_from_cam[p:q], fr.trunc, fr.w_max))
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=300)
+    ap.add_argument("--frames-per-pass", type=int, default=0, help="0: tuned default")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the fused scan (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the integration runs on one GPU per process)",
+              file=sys.stderr, flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1602_06645_amd as kf
+    from kf_synth import configs
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        return 1
+    torch.cuda.set_device(0)
+    K = args.frames_per_pass or default_frames_per_pass()
+
+    t = time.perf_counter()
+    spec, fr = configs.kinect(device="cuda", n_frames=args.frames)
+    torch.cuda.synchronize()
+    log(f"generated {fr.n} frames on the GPU in {time.perf_counter() - t:.1f} s")
+    n_vox = spec.n_geom + spec.n_colour
+    vol = kf.Volume(spec)
+    passes = pass_scans(kf, fr, K)
+    frame_bytes = fr.depth[0].numel() * 4 + fr.rgb[0].numel()
+
+    # ---- algorithmic bytes of the fused scan (counting instantiation, not timed)
+    vol.reset()
+    cnt = kf.integrate_batch_counted([(vol, kf.Scan.from_frames(fr))], frames_per_pass=K)
+    alg_bytes = 16 * int(cnt[1]) + 4 * int(cnt[3]) + 28 * int(cnt[5]) + fr.n * frame_bytes
+    log(f"counters {list(map(int, cnt))}; algorithmic bytes per scan {alg_bytes / 1e9:.3f} GB")
+
+    # ---- fused scan: warmup, then the timed steps
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(len(passes) * args.steps)]
+
+    def scan_step(events=None):
+        vol.reset()
+        for q, ps in enumerate(passes):
+            if events is not None:
+                events[q][0].record(stream)
+            kf.integrate_batch([(vol, ps)], frames_per_pass=K, use_graph=True)
+            if events is not None:
+                events[q][1].record(stream)
+
+    for _ in range(args.warmup):
+        scan_step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} scans, K={K}, {len(passes)} passes per scan)")
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        scan_step(ev[s * len(passes):(s + 1) * len(passes)])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_step = 1e3 * wall / args.steps
+    value = n_vox * fr.n * args.steps / wall
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, pass {launch_ms:.3f} ms")
+    per_launch_bytes = alg_bytes / len(passes)
+    achieved = per_launch_bytes / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "frames": fr.n, "frames_per_pass": K,
+                   "geometry_dim": list(spec.gdim), "colour_dim": list(spec.cdim),
+                   "depth": [fr.depth.shape[2], fr.depth.shape[1]],
+                   "rgb": [fr.rgb.shape[2], fr.rgb.shape[1]], "rgb_format": "u8",
+                   "trunc_m": fr.trunc, "w_max": fr.w_max, "sigma_m": spec.sigma,
+                   "gate": spec.gate},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "integrate_kernel (persistent fused pass)",
+                     "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
+        "counters": {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
+                     "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),
+                     "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5])},
+        "effective_voxel_updates_per_s": (int(cnt[0]) + int(cnt[4])) * args.steps / wall,
+    }
+
+    if not args.no_extras:
+        # ---- plain frame-by-frame path over the same scan
+        def plain_step():
+            vol.reset()
+            for f in range(fr.n):
+                vol.integrate(fr.depth[f], fr.rgb[f], fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
+                              fr.T_world_from_cam[f], fr.trunc, fr.w_max)
+        plain_step()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        n_plain = max(1, min(args.steps, 3))
+        for _ in range(n_plain):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_wall = (time.perf_counter() - tp) / n_plain
+        out["plain_ms_per_step"] = 1e3 * plain_wall
+        out["plain_voxel_updates_per_s"] = n_vox * fr.n / plain_wall
+        out["fused_vs_plain"] = plain_wall / (wall / args.steps)
+        log(f"plain: {1e3 * plain_wall:.2f} ms per scan; fused speedup {out['fused_vs_plain']:.2f}x")
+
+        # ---- differentiable form: first 32 frames as float images, forward + backward
+        nb = min(32, fr.n)
+        rgbf = fr.rgb[:nb].to(torch.float32) * torch.tensor(np.float32(1.0 / 255.0), device="cuda")
+        scan32 = kf.Scan(fr.depth[:nb], rgbf.contiguous(), fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
+                         fr.T_world_from_cam[:nb], fr.trunc, fr.w_max)
+        g = configs.gradient_weights(spec.n_colour, device="cuda")
+
+        def fwd_bwd():
+            vol.reset()
+            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
+            return kf.integrate_backward(spec, scan32, g)
+        fwd_bwd()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        out["fwd_bwd_ms"] = 1e3 * (time.perf_counter() - tb) / reps
+        out["fwd_bwd_config"] = f"first {nb} frames, float32 RGB, full volume, g ~ N(0,1) on every colour voxel"
+        log(f"forward+backward ({nb} frames): {out['fwd_bwd_ms']:.2f} ms")
+        del rgbf, scan32, g
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        n_cpu = min(6, fr.n)
+        sub = fr.select(slice(0, n_cpu)).numpy()
+        st = O.State(spec, np.float32)
+        tc = time.perf_counter()
+        O.integrate(spec, sub, st)
+        t_cpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": n_vox * n_cpu / t_cpu, "unit": "voxel updates/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"frames 0-{n_cpu - 1} of the same scan, whole volume "
+                                         f"(plain C oracle, OpenMP over z), {t_cpu:.1f} s"}
+        log(f"cpu oracle: {out['cpu_baseline']['value']:.4g} voxel updates/s on {O.num_threads()} threads")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -12,8 +12,11 @@
 #include "kf_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ---- per-frame constants, double precision (Eq. 3 and Eq. 5 folded into affine maps) */
 

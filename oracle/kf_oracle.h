@@ -67,6 +67,9 @@ typedef struct {
 
 void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc64* out);
 
+/* Threads the OpenMP loops of this library use. */
+int or_num_threads(void);
+
 /*
  * Forward integration in FP32 (or_integrate_f32) or FP64 (or_integrate_f64).
  * State arrays cover geometry z-slabs [gz0,gz1) and colour z-slabs [cz0,cz1) only.

@@ -120,6 +120,13 @@ def _frames(fr, keep: list) -> _Frames:
     return f
 
 
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    L = lib()
+    L.or_num_threads.restype = C.c_int
+    return int(L.or_num_threads())
+
+
 def frame_consts(vol, fr, frame: int) -> dict:
     keep: list = []
     out = _FC64()

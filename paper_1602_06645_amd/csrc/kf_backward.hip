@@ -100,7 +100,7 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
     const uint32_t rest = li / (uint32_t)a.ctiles[0];
     const uint32_t ty = rest % (uint32_t)a.ctiles[1];
     const uint32_t tz = rest / (uint32_t)a.ctiles[1];
-    const int i = (int)tx * TX + lane, j = (int)ty * TY + wave, k0 = (int)tz * ZS;
+    const int i = (int)tx * BWD_TX + lane, j = (int)ty * BWD_TY + wave, k0 = (int)tz * ZS;
     const size_t nvox = (size_t)X * (size_t)Y * (size_t)Z;
     double xi[6] = {0, 0, 0, 0, 0, 0};
     float* hist = s_alpha + threadIdx.x;

@@ -198,6 +198,7 @@ void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_r
     out->w_max = (float)w_max;
     out->sigma2 = (float)(vd.colour_band * vd.colour_band);
     out->gate = (float)vd.colour_gate;
+    out->sigma = (float)vd.colour_band;
     out->wm1 = (float)(dw - 1);
     out->hm1 = (float)(dh - 1);
     out->cwm2 = (float)(cw - 2);
@@ -208,6 +209,25 @@ void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_r
     out->ch = ch;
     out->depth = depth;
     out->rgb = rgb;
+    // the depth pyramid: 8x8-pixel tiles, halved until one tile covers the image
+    out->pyr = nullptr;
+    out->pyr_w0 = (dw + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
+    out->pyr_h0 = (dh + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
+    int32_t levels = 1, w = out->pyr_w0, h = out->pyr_h0;
+    while (w > 1 || h > 1) {
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+        ++levels;
+    }
+    out->pyr_levels = levels;
+}
+
+// float2 entries of a frame's depth pyramid.
+size_t pyramid_entries(const kf::FrameConsts& c)
+{
+    int32_t w, h, off;
+    kf::pyr_level_dims(c.pyr_w0, c.pyr_h0, c.pyr_levels, &w, &h, &off);
+    return (size_t)off;
 }
 
 uint32_t ceil_div(int32_t a, int32_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -225,15 +245,23 @@ void scene_dev(const kf_volume* v, int32_t fmt, kf::SceneDev* s)
         s->gdim[a] = v->desc.geom_dim[a];
         s->cdim[a] = v->desc.colour_dim[a];
     }
-    s->gtiles[0] = (int32_t)ceil_div(s->gdim[0], kf::TX);
-    s->gtiles[1] = (int32_t)ceil_div(s->gdim[1], kf::TY);
-    s->gtiles[2] = (int32_t)ceil_div(s->gdim[2], kf::ZS);
-    s->ctiles[0] = (int32_t)ceil_div(s->cdim[0], kf::TX);
-    s->ctiles[1] = (int32_t)ceil_div(s->cdim[1], kf::TY);
-    s->ctiles[2] = (int32_t)ceil_div(s->cdim[2], kf::ZS);
-    s->geom_items = (uint32_t)s->gtiles[0] * (uint32_t)s->gtiles[1] * (uint32_t)s->gtiles[2];
-    s->colour_items = (uint32_t)s->ctiles[0] * (uint32_t)s->ctiles[1] * (uint32_t)s->ctiles[2];
+    s->gbricks[0] = (int32_t)ceil_div(s->gdim[0], kf::GBX);
+    s->gbricks[1] = (int32_t)ceil_div(s->gdim[1], kf::GBY);
+    s->gbricks[2] = (int32_t)ceil_div(s->gdim[2], kf::ZS);
+    s->cbricks[0] = (int32_t)ceil_div(s->cdim[0], kf::CBX);
+    s->cbricks[1] = (int32_t)ceil_div(s->cdim[1], kf::CBY);
+    s->cbricks[2] = (int32_t)ceil_div(s->cdim[2], kf::ZS);
+    s->geom_items = (uint32_t)s->gbricks[0] * (uint32_t)s->gbricks[1] * (uint32_t)s->gbricks[2];
+    s->colour_items = (uint32_t)s->cbricks[0] * (uint32_t)s->cbricks[1] * (uint32_t)s->cbricks[2];
     s->fmt = fmt;
+}
+
+// KF_DISABLE_CULL=1 in the environment makes every brick live in every frame (the
+// results are identical; only the work grows).
+bool cull_disabled()
+{
+    const char* v = getenv("KF_DISABLE_CULL");
+    return v && v[0] == '1';
 }
 
 kf_status check_frame_args(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
@@ -253,36 +281,45 @@ kf_status check_frame_args(kf_volume* vol, const float* depth, int32_t dw, int32
 
 // --------------------------------------------------------------- pinned staging buffer
 
-struct Staging {
-    std::mutex mu;
+// A ring of pinned buffers: a slot is reused once the copy that last read it has run, so
+// the host can run a few calls ahead of the device.
+struct StagingSlot {
     void* host = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
+constexpr int kStagingSlots = 8;
+struct Staging {
+    std::mutex mu;
+    StagingSlot slot[kStagingSlots];
+    int next = 0;
+};
 Staging g_stage;
 
-// Copy `bytes` from host memory `src` to device `dst` on `stream` through a pinned buffer
-// that is reused once the previous copy has completed.
+// Copy `bytes` from host memory `src` to device `dst` on `stream` through a pinned slot.
 kf_status staged_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
 {
     std::lock_guard<std::mutex> lock(g_stage.mu);
-    if (g_stage.pending) {
-        KF_HIP(hipEventSynchronize(g_stage.ev), "hipEventSynchronize");
-        g_stage.pending = false;
+    StagingSlot& s = g_stage.slot[g_stage.next];
+    g_stage.next = (g_stage.next + 1) % kStagingSlots;
+    if (s.pending) {
+        KF_HIP(hipEventSynchronize(s.ev), "hipEventSynchronize");
+        s.pending = false;
     }
-    if (!g_stage.ev) KF_HIP(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming), "hipEventCreate");
-    if (bytes > g_stage.cap) {
-        if (g_stage.host) KF_HIP(hipHostFree(g_stage.host), "hipHostFree");
-        g_stage.host = nullptr;
-        size_t cap = bytes < 65536 ? 65536 : bytes * 2;
-        KF_HIP(hipHostMalloc(&g_stage.host, cap, hipHostMallocDefault), "hipHostMalloc");
-        g_stage.cap = cap;
+    if (!s.ev) KF_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "hipEventCreate");
+    if (bytes > s.cap) {
+        if (s.host) KF_HIP(hipHostFree(s.host), "hipHostFree");
+        s.host = nullptr;
+        s.cap = 0;
+        const size_t cap = bytes < 65536 ? 65536 : bytes * 2;
+        KF_HIP(hipHostMalloc(&s.host, cap, hipHostMallocDefault), "hipHostMalloc");
+        s.cap = cap;
     }
-    memcpy(g_stage.host, src, bytes);
-    KF_HIP(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync");
-    KF_HIP(hipEventRecord(g_stage.ev, stream), "hipEventRecord");
-    g_stage.pending = true;
+    memcpy(s.host, src, bytes);
+    KF_HIP(hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync");
+    KF_HIP(hipEventRecord(s.ev, stream), "hipEventRecord");
+    s.pending = true;
     return KF_OK;
 }
 
@@ -294,11 +331,15 @@ struct BatchPlan {
     std::vector<uint32_t> pass_items;
 };
 
+// Frames a pass can hold: one bit per frame in a brick's live mask.
+constexpr int32_t kMaxFramesPerPass = 32;
+
 kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchPlan* plan)
 {
     if (!scenes && n_scenes > 0) return fail(KF_E_ARG, "scenes is NULL");
     if (n_scenes < 0) return fail(KF_E_ARG, "n_scenes < 0");
     if (K < 1) return fail(KF_E_ARG, "frames_per_pass must be >= 1");
+    if (K > kMaxFramesPerPass) K = kMaxFramesPerPass;
     std::vector<int32_t> first(n_scenes);
     int32_t max_frames = 0;
     for (int s = 0; s < n_scenes; ++s) {
@@ -352,11 +393,13 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
     return KF_OK;
 }
 
-// Device image of a plan: [frames][pass0 scenes][pass1 scenes]...[queue counters]
+// Device image of a plan:
+//   [frame table][scene table of each pass][n_live, queue per pass][live list][pyramids]
 struct DeviceTables {
     std::vector<unsigned char> host;
-    size_t frames_off = 0, queue_off = 0;
-    std::vector<size_t> pass_off;
+    size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
+    std::vector<size_t> pass_off, frame_pyr_off;
+    int32_t max_tiles0 = 0;
 };
 
 void layout_tables(const BatchPlan& p, DeviceTables* t)
@@ -369,11 +412,31 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
         t->pass_off.push_back(off);
         off = align(off + pass.size() * sizeof(kf::SceneDev));
     }
-    t->queue_off = off;
-    off = align(off + (p.passes.size() + 1) * sizeof(uint32_t));
-    t->host.assign(off, 0);
-    if (!p.frames.empty())
-        memcpy(t->host.data() + t->frames_off, p.frames.data(), p.frames.size() * sizeof(kf::FrameConsts));
+    t->counters_off = off;
+    off = align(off + 2 * (p.passes.size() + 1) * sizeof(uint32_t));
+    uint32_t max_items = 0;
+    for (uint32_t n : p.pass_items) max_items = n > max_items ? n : max_items;
+    t->live_off = off;
+    off = align(off + (size_t)max_items * sizeof(uint2));
+    t->pyr_off = off;
+    for (const auto& fc : p.frames) {
+        t->frame_pyr_off.push_back(off);
+        off += pyramid_entries(fc) * sizeof(float2);
+        const int32_t tiles = fc.pyr_w0 * fc.pyr_h0;
+        t->max_tiles0 = tiles > t->max_tiles0 ? tiles : t->max_tiles0;
+    }
+    t->bytes = align(off);
+}
+
+// Fill the host image for device base address `dev` (the frames point at their pyramids).
+void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
+{
+    t->host.assign(t->pyr_off, 0);   // the pyramids are written on the device
+    std::vector<kf::FrameConsts> frames = p.frames;
+    for (size_t f = 0; f < frames.size(); ++f)
+        frames[f].pyr = (float2*)(dev + t->frame_pyr_off[f]);
+    if (!frames.empty())
+        memcpy(t->host.data() + t->frames_off, frames.data(), frames.size() * sizeof(kf::FrameConsts));
     for (size_t q = 0; q < p.passes.size(); ++q)
         if (!p.passes[q].empty())
             memcpy(t->host.data() + t->pass_off[q], p.passes[q].data(), p.passes[q].size() * sizeof(kf::SceneDev));
@@ -387,25 +450,40 @@ kf_status resident_grid(int mode, uint32_t* grid)
     return KF_OK;
 }
 
-// Enqueue the passes of a plan whose tables live at `dev`; `grid` blocks per persistent
-// launch (resident_grid).
+// Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`
+// blocks per persistent launch (resident_grid).
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
                          unsigned long long* counters, uint32_t grid, hipStream_t stream)
 {
-    uint32_t* queues = (uint32_t*)(dev + t.queue_off);
-    KF_HIP(kf::launch_fill_u32(queues, p.passes.size() + 1, 0u, stream), "queue reset");
+    const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
+    KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
+    uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
+    KF_HIP(kf::launch_fill_u32(cnt, 2 * (p.passes.size() + 1), 0u, stream), "counter reset");
+    uint2* live = (uint2*)(dev + t.live_off);
+    const int disable = cull_disabled() ? 1 : 0;
     for (size_t q = 0; q < p.passes.size(); ++q) {
         if (p.pass_items[q] == 0) continue;
+        const kf::SceneDev* scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
+        kf::CullArgs c;
+        memset(&c, 0, sizeof c);
+        c.scenes = scenes;
+        c.frames = frames;
+        c.n_scenes = (int32_t)p.passes[q].size();
+        c.n_items = p.pass_items[q];
+        c.disable = disable;
+        c.live = live;
+        c.n_live = cnt + 2 * q;
+        KF_HIP(kf::launch_cull(c, stream), "cull launch");
         kf::IntegrateArgs a;
         memset(&a, 0, sizeof a);
-        a.scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
-        a.frames = (const kf::FrameConsts*)(dev + t.frames_off);
-        a.n_scenes = (int32_t)p.passes[q].size();
-        a.n_items = p.pass_items[q];
-        a.queue = queues + q;
+        a.scenes = scenes;
+        a.frames = frames;
+        a.n_scenes = c.n_scenes;
+        a.live = live;
+        a.n_live = cnt + 2 * q;
+        a.queue = cnt + 2 * q + 1;
         a.counters = counters;
-        const uint32_t g = grid < a.n_items ? grid : a.n_items;
-        KF_HIP(kf::launch_integrate(mode, false, a, g, stream), "integrate launch");
+        KF_HIP(kf::launch_integrate(mode, a, grid, stream), "integrate launch");
     }
     return KF_OK;
 }
@@ -425,7 +503,7 @@ struct GraphCache {
     hipStream_t capture[64] = {};
 };
 GraphCache g_graphs;
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 64;
 
 std::string batch_key(const kf_scene* scenes, int32_t n_scenes, int32_t K, int device)
 {
@@ -485,7 +563,8 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
     GraphEntry e;
     e.key = key;
     e.device = device;
-    KF_HIP(hipMalloc(&e.dev, t.host.size()), "hipMalloc");
+    KF_HIP(hipMalloc(&e.dev, t.bytes), "hipMalloc");
+    fill_tables(plan, e.dev, &t);
     hipError_t he = hipMemcpy(e.dev, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipMemcpy"); }
     uint32_t grid = 0;
@@ -527,7 +606,8 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     uint32_t grid = 0;
     if ((st = resident_grid(mode, &grid)) != KF_OK) return st;
     unsigned char* dev = nullptr;
-    KF_HIP(hipMallocAsync((void**)&dev, t.host.size(), stream), "hipMallocAsync");
+    KF_HIP(hipMallocAsync((void**)&dev, t.bytes, stream), "hipMallocAsync");
+    fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
     if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream);
     hipError_t he = hipFreeAsync(dev, stream);
@@ -600,27 +680,28 @@ kf_status kf_volume_reset(kf_volume* vol, void* stream)
     return KF_OK;
 }
 
-static kf_status integrate_one(int mode, kf_volume* vol, const float* depth, int32_t dw,
-                               int32_t dh, const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
-                               const double* K_d, const double* K_rgb, const double* T_rd,
-                               const double* T_wc, double trunc_m, double w_max,
-                               uint8_t* gstatus, uint8_t* cstatus, void* stream)
+static kf_scene single_scene(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
+                             const void* rgb, kf_pixfmt fmt, int32_t cw, int32_t ch,
+                             const double* K_d, const double* K_rgb, const double* T_rd,
+                             const double* T_wc, double trunc_m, double w_max)
 {
-    kf_status s = check_frame_args(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb, T_rd, T_wc,
-                                   trunc_m, w_max);
-    if (s != KF_OK) return s;
-    kf::IntegrateArgs a;
-    memset(&a, 0, sizeof a);
-    scene_dev(vol, fmt, &a.scene0);
-    a.scene0.n_frames = 1;
-    frame_consts(vol->desc, K_d, K_rgb, T_rd, T_wc, trunc_m, w_max, depth, dw, dh, rgb, cw, ch,
-                 &a.frame0);
-    a.n_scenes = 1;
-    a.n_items = a.scene0.geom_items + a.scene0.colour_items;
-    a.gstatus = gstatus;
-    a.cstatus = cstatus;
-    KF_HIP(kf::launch_integrate(mode, true, a, 0, (hipStream_t)stream), "integrate launch");
-    return KF_OK;
+    kf_scene sc;
+    sc.vol = vol;
+    sc.n_frames = 1;
+    sc.depth = depth;
+    sc.rgb = rgb;
+    sc.fmt = fmt;
+    sc.dw = dw;
+    sc.dh = dh;
+    sc.cw = cw;
+    sc.ch = ch;
+    sc.K_d = K_d;
+    sc.K_rgb = K_rgb;
+    sc.T_rgb_from_d = T_rd;
+    sc.T_world_from_cam = T_wc;
+    sc.trunc_m = trunc_m;
+    sc.w_max = w_max;
+    return sc;
 }
 
 kf_status kf_integrate(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
@@ -629,8 +710,12 @@ kf_status kf_integrate(kf_volume* vol, const float* depth, int32_t dw, int32_t d
                        const double T_rgb_from_d[16], const double T_world_from_cam[16],
                        double trunc_m, double w_max, void* stream)
 {
-    return integrate_one(kf::MODE_INTEGRATE, vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
-                         T_rgb_from_d, T_world_from_cam, trunc_m, w_max, nullptr, nullptr, stream);
+    kf_status s = check_frame_args(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
+                                   T_rgb_from_d, T_world_from_cam, trunc_m, w_max);
+    if (s != KF_OK) return s;
+    const kf_scene sc = single_scene(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
+                                     T_rgb_from_d, T_world_from_cam, trunc_m, w_max);
+    return run_batch(&sc, 1, 1, kf::MODE_INTEGRATE, nullptr, (hipStream_t)stream);
 }
 
 kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
@@ -640,10 +725,24 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
                           double trunc_m, double w_max, uint8_t* geom_status,
                           uint8_t* colour_status, void* stream)
 {
+    kf_status s = check_frame_args(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
+                                   T_rgb_from_d, T_world_from_cam, trunc_m, w_max);
+    if (s != KF_OK) return s;
     if (!geom_status || !colour_status) return fail(KF_E_ARG, "status output is NULL");
-    return integrate_one(kf::MODE_STATUS, vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
-                         T_rgb_from_d, T_world_from_cam, trunc_m, w_max, geom_status,
-                         colour_status, stream);
+    kf::StatusArgs a;
+    memset(&a, 0, sizeof a);
+    scene_dev(vol, fmt, &a.scene);
+    a.scene.n_frames = 1;
+    frame_consts(vol->desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc_m, w_max, depth,
+                 dw, dh, rgb, cw, ch, &a.frame);
+    hipStream_t st = (hipStream_t)stream;
+    a.n_items = a.scene.geom_items;
+    a.status = geom_status;
+    KF_HIP(kf::launch_status(false, a, st), "status launch");
+    a.n_items = a.scene.colour_items;
+    a.status = colour_status;
+    KF_HIP(kf::launch_status(true, a, st), "status launch");
+    return KF_OK;
 }
 
 kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t frames_per_pass,
@@ -697,8 +796,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     kf::BackwardArgs a;
     memset(&a, 0, sizeof a);
     for (int q = 0; q < 3; ++q) a.cdim[q] = desc->colour_dim[q];
-    a.ctiles[0] = (int32_t)ceil_div(a.cdim[0], kf::TX);
-    a.ctiles[1] = (int32_t)ceil_div(a.cdim[1], kf::TY);
+    a.ctiles[0] = (int32_t)ceil_div(a.cdim[0], kf::BWD_TX);
+    a.ctiles[1] = (int32_t)ceil_div(a.cdim[1], kf::BWD_TY);
     a.ctiles[2] = (int32_t)ceil_div(a.cdim[2], kf::ZS);
     a.n_items = (uint32_t)a.ctiles[0] * (uint32_t)a.ctiles[1] * (uint32_t)a.ctiles[2];
     a.n_frames = n_frames;

@@ -3,15 +3,22 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 namespace kf {
 
-// A work item is a brick of TX x TY columns and ZS voxels along z.  One workgroup of
-// TX*TY = 256 lanes (four wave64s, one x-row of 64 voxels each) handles it; every lane
-// keeps the state of its ZS voxels in registers for all frames of a pass.
-constexpr int TX = 64;
-constexpr int TY = 4;
+// A brick is the work of one wave64: 64 voxel columns by ZS voxels along z.  Each lane
+// owns one column and keeps the state of its ZS voxels for every frame of a pass.
+// Geometry bricks are 16 x 4 columns (64-byte rows of each state array); colour bricks
+// are 8 x 8 columns, compact enough that most of them are far from the observed surface
+// in a given frame and can be skipped whole.
 constexpr int ZS = 8;
-constexpr int BLOCK = TX * TY;
+constexpr int GBX = 16, GBY = 4;
+constexpr int CBX = 8, CBY = 8;
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;              // four waves that work independently
+constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
+constexpr int BWD_TX = 64, BWD_TY = 4;  // adjoint: a block covers 64 x 4 colour columns
 
 // Everything one frame contributes to the per-voxel arithmetic, rounded once from the
 // double-precision values computed on the host.
@@ -21,12 +28,14 @@ struct FrameConsts {
     float Ah[9], bh[3];   // colour voxel index   -> HD camera (Eq. 3 composed with Eq. 5)
     float fx, fy, cx, cy, inv_fx, inv_fy;  // K_c and the diagonal of K_c^-1
     float fxr, fyr, cxr, cyr;              // K_hd
-    float trunc, inv_trunc, w_max, sigma2, gate;
+    float trunc, inv_trunc, w_max, sigma2, gate, sigma;
     float wm1, hm1;       // depth image W-1, H-1 (exact in float)
     float cwm2, chm2;     // HD image CW-2, CH-2
     int32_t dw, dh, cw, ch;
     const float* depth;   // [dh][dw]
     const void* rgb;      // [ch][cw][3], uint8 or float
+    float2* pyr;          // min/max depth pyramid of this frame, levels back to back
+    int32_t pyr_w0, pyr_h0, pyr_levels;
 };
 
 enum PixFmt : int32_t { FMT_RGB8 = 0, FMT_RGBF32 = 1 };
@@ -35,28 +44,43 @@ enum PixFmt : int32_t { FMT_RGB8 = 0, FMT_RGBF32 = 1 };
 struct SceneDev {
     float *tsdf, *wg, *r, *g, *b, *wc;
     int32_t gdim[3], cdim[3];
-    int32_t gtiles[3], ctiles[3];   // bricks per axis
-    uint32_t item_begin;            // first global work item of this scene
-    uint32_t geom_items;            // geometry bricks; colour bricks follow them
+    int32_t gbricks[3], cbricks[3];   // bricks per axis
+    uint32_t item_begin;              // first global brick index of this scene in the pass
+    uint32_t geom_items;              // geometry bricks; colour bricks follow them
     uint32_t colour_items;
-    int32_t frame_begin;            // first entry of the frame table used by this pass
-    int32_t n_frames;               // frames of this scene in this pass (may be 0)
-    int32_t fmt;                    // PixFmt
+    int32_t frame_begin;              // first entry of the frame table used by this pass
+    int32_t n_frames;                 // frames of this scene in this pass (<= 32)
+    int32_t fmt;                      // PixFmt
 };
 
 enum Mode : int32_t { MODE_INTEGRATE = 0, MODE_STATUS = 1, MODE_COUNT = 2 };
 
 struct IntegrateArgs {
-    const SceneDev* scenes;         // table of n_scenes (batch launches)
-    const FrameConsts* frames;      // frame table (batch launches)
+    const SceneDev* scenes;           // table of n_scenes
+    const FrameConsts* frames;        // frame table
     int32_t n_scenes;
-    uint32_t n_items;
-    uint32_t* queue;                // persistent launch: shared item counter; NULL: grid launch
-    unsigned long long* counters;   // MODE_COUNT: uint64[6]
-    uint8_t* gstatus;               // MODE_STATUS outputs
-    uint8_t* cstatus;
-    SceneDev scene0;                // single-scene launches: the scene ...
-    FrameConsts frame0;             // ... and its single frame, passed by value
+    const uint2* live;                // (brick, frame mask) of the bricks to process
+    const uint32_t* n_live;           // number of entries in `live`
+    uint32_t* queue;                  // next entry to take
+    unsigned long long* counters;     // MODE_COUNT: uint64[6]
+};
+
+// Single-frame status dump (no culling, no update): one scene and frame by value.
+struct StatusArgs {
+    SceneDev scene;
+    FrameConsts frame;
+    uint32_t n_items;                 // bricks of one kind
+    uint8_t* status;
+};
+
+struct CullArgs {
+    const SceneDev* scenes;
+    const FrameConsts* frames;
+    int32_t n_scenes;
+    uint32_t n_items;                 // bricks of all scenes of the pass
+    int32_t disable;                  // 1: every brick is live in every frame
+    uint2* live;
+    uint32_t* n_live;
 };
 
 struct BackwardArgs {
@@ -64,11 +88,26 @@ struct BackwardArgs {
     int32_t ctiles[3];
     uint32_t n_items;
     int32_t n_frames;
-    const FrameConsts* frames;      // [n_frames]
-    const float* wc0;               // initial colour weights or NULL
-    const float* grad;              // [3][Nc]
-    float* d_rgb;                   // [n][ch][cw][3]
-    double* partials;               // [gridDim][6]
+    const FrameConsts* frames;        // [n_frames]
+    const float* wc0;                 // initial colour weights or NULL
+    const float* grad;                // [3][Nc]
+    float* d_rgb;                     // [n][ch][cw][3]
+    double* partials;                 // [gridDim][6]
 };
+
+// Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.
+__host__ __device__ inline void pyr_level_dims(int32_t w0, int32_t h0, int32_t l, int32_t* w,
+                                               int32_t* h, int32_t* offset)
+{
+    int32_t ww = w0, hh = h0, off = 0;
+    for (int32_t q = 0; q < l; ++q) {
+        off += ww * hh;
+        ww = (ww + 1) / 2;
+        hh = (hh + 1) / 2;
+    }
+    *w = ww;
+    *h = hh;
+    *offset = off;
+}
 
 }  // namespace kf

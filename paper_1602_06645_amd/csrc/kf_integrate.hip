@@ -1,12 +1,18 @@
 // Forward integration kernels for gfx950: TSDF geometry volume (Sec. III) and asymmetric
 // colour volume (Sec. IV.B, Eq. 5-10, with the depth-to-HD mapping of Eq. 1-4).
 //
-// One kernel serves every forward entry point.  A work item is a brick of 64 x 4 columns
-// by 8 voxels along z of one volume of one scan.  Each lane owns one column of the brick
-// and keeps the state of its 8 voxels in registers while it applies every frame of the
-// pass in order; a voxel's state is read only when a frame first needs it (lazily) and
-// written back only if some frame updated it.  A wave64 covers 64 consecutive x voxels,
-// so every state access is a coalesced 256-byte row per array.
+// A pass applies up to 32 consecutive frames of every scan in the launch:
+//   1. pyramid kernels: per frame, min/max of the valid depths over 8x8-pixel tiles and
+//      their 2x2 reductions (built once per batch call for all frames);
+//   2. cull kernel: one lane per brick decides, frame by frame, whether any voxel of the
+//      brick can pass the depth tests (conservatively, from the brick's corners and the
+//      pyramid) and appends (brick, frame mask) of the live bricks to a list;
+//   3. integrate kernel: persistent waves take live bricks from the list; each lane keeps
+//      its column's ZS voxels in an LDS scratchpad for all frames of the pass, reads a
+//      voxel's state only when a frame first needs it and writes it back only if a frame
+//      updated it.
+// Culling never changes a result: a brick is dropped for a frame only if every voxel in
+// it would have been rejected before touching its state.
 //
 // Arithmetic is IEEE single precision in a fixed order: explicit fmaf, correctly rounded
 // division and square root, rintf for the nearest depth pixel, floorf for the HD cell.
@@ -38,10 +44,25 @@ __device__ __forceinline__ float hd_px(const void* rgb, int idx)
         return ((const float*)rgb)[idx];
 }
 
-struct InlineFrames {
-    const FrameConsts& c;
-    __device__ __forceinline__ const FrameConsts& operator[](int) const { return c; }
-};
+// Bilinear HD sample of channel ch at the cell whose top-left pixel's first channel is
+// at `cell`: Eq. 9's HD(x_hd, y_hd) read between pixel centres.
+__device__ __forceinline__ float hd_sample(const void* rgb, int fmt, int cell, int row, int ch,
+                                           float ax, float ay)
+{
+    float p00, p10, p01, p11;
+    if (fmt == FMT_RGB8) {
+        p00 = hd_px<FMT_RGB8>(rgb, cell + ch);
+        p10 = hd_px<FMT_RGB8>(rgb, cell + 3 + ch);
+        p01 = hd_px<FMT_RGB8>(rgb, cell + row + ch);
+        p11 = hd_px<FMT_RGB8>(rgb, cell + row + 3 + ch);
+    } else {
+        p00 = hd_px<FMT_RGBF32>(rgb, cell + ch);
+        p10 = hd_px<FMT_RGBF32>(rgb, cell + 3 + ch);
+        p01 = hd_px<FMT_RGBF32>(rgb, cell + row + ch);
+        p11 = hd_px<FMT_RGBF32>(rgb, cell + row + 3 + ch);
+    }
+    return lerp(lerp(p00, p10, ax), lerp(p01, p11, ax), ay);
+}
 
 // Per-launch tables are read-only for the whole launch: reading them through the
 // constant address space lets the compiler use scalar loads and keep them in SGPRs.
@@ -54,54 +75,59 @@ __device__ __forceinline__ const_ptr<T> as_const(const T* p)
     return (const_ptr<T>)p;
 }
 
-struct TableFrames {
-    const_ptr<FrameConsts> p;
-    __device__ __forceinline__ const __attribute__((address_space(4))) FrameConsts&
-    operator[](int f) const { return p[f]; }
-};
-
 struct Counts {
     unsigned long long g_upd = 0, g_touch = 0, c_eval = 0, c_read = 0, c_upd = 0, c_touch = 0;
 };
 
-// Each lane parks the state of its ZS voxels in its own slots of an LDS scratchpad
-// (slot kk of lane t at [kk * BLOCK + t]); no other lane touches them, so no barrier is
-// needed, and the z loop can stay rolled.
-struct Scratch {
-    float4* v;   // ZS * BLOCK entries
+// Voxel column of a lane in brick li of a volume with brick shape BX x BY x ZS.
+struct Column {
+    int i, j, k0, kn;
+    size_t base, slice;
+    bool active;
 };
 
-// Geometry brick: projective TSDF with running average (KinectFusion, Sec. III).
-template <int MODE, class Scene, class Frames>
-__device__ __forceinline__ void geom_brick(const IntegrateArgs& a, const Scene& sc,
-                                           Frames frames, int nf, uint32_t li, Scratch lds,
+template <int BX, int BY, class Dims>
+__device__ __forceinline__ Column column(const Dims& dim, const Dims& bricks, uint32_t li)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint32_t bx = li % (uint32_t)bricks[0];
+    const uint32_t rest = li / (uint32_t)bricks[0];
+    const uint32_t by = rest % (uint32_t)bricks[1];
+    const uint32_t bz = rest / (uint32_t)bricks[1];
+    Column c;
+    c.i = (int)bx * BX + lane % BX;
+    c.j = (int)by * BY + lane / BX;
+    c.k0 = (int)bz * ZS;
+    c.kn = min(ZS, dim[2] - c.k0);
+    c.active = c.i < dim[0] && c.j < dim[1];
+    c.slice = (size_t)dim[0] * (size_t)dim[1];
+    c.base = ((size_t)c.k0 * (size_t)dim[1] + (size_t)c.j) * (size_t)dim[0] + (size_t)c.i;
+    return c;
+}
+
+// ------------------------------------------------------------------ geometry (Sec. III)
+
+// Projective TSDF with running average for the frames of `mask` (bit f = frame f of the
+// pass).  MODE_STATUS writes the outcome code of the (single) frame instead.
+template <int MODE, class Scene, class FramePtr>
+__device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uint32_t mask,
+                                           uint32_t li, float4* slot, uint8_t* status,
                                            Counts& cnt)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int X = sc.gdim[0], Y = sc.gdim[1], Z = sc.gdim[2];
-    const uint32_t tx = li % (uint32_t)sc.gtiles[0];
-    const uint32_t rest = li / (uint32_t)sc.gtiles[0];
-    const uint32_t ty = rest % (uint32_t)sc.gtiles[1];
-    const uint32_t tz = rest / (uint32_t)sc.gtiles[1];
-    const int i = (int)tx * TX + lane, j = (int)ty * TY + wave, k0 = (int)tz * ZS;
-    if (i >= X || j >= Y) return;
-    const int kn = min(ZS, Z - k0);
-    const size_t slice = (size_t)X * (size_t)Y;
-    const size_t base = ((size_t)k0 * (size_t)Y + (size_t)j) * (size_t)X + (size_t)i;
-    const float fi = (float)i, fj = (float)j;
-    float4* slot = lds.v + threadIdx.x;
-
+    const Column col = column<GBX, GBY>(sc.gdim, sc.gbricks, li);
+    if (!col.active) return;
+    const float fi = (float)col.i, fj = (float)col.j;
     uint32_t loaded = 0;
     unsigned long long n_upd = 0;
-    for (int f = 0; f < nf; ++f) {
-        const auto& c = frames[f];
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const auto& c = frames[__builtin_ctz(m)];
         // Eq. 5 for this column; the z term is added per voxel.
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
         const float cY = fmaf(c.Ag[4], fj, fmaf(c.Ag[3], fi, c.bg[1]));
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
 #pragma unroll 2
-        for (int kk = 0; kk < kn; ++kk) {
-            const float fk = (float)(k0 + kk);
+        for (int kk = 0; kk < col.kn; ++kk) {
+            const float fk = (float)(col.k0 + kk);
             const float Xc = fmaf(c.Ag[2], fk, cX);
             const float Yc = fmaf(c.Ag[5], fk, cY);
             const float Zc = fmaf(c.Ag[8], fk, cZ);
@@ -122,33 +148,33 @@ __device__ __forceinline__ void geom_brick(const IntegrateArgs& a, const Scene& 
                 }
             }
             if constexpr (MODE == MODE_STATUS) {
-                a.gstatus[base + (size_t)kk * slice] = (uint8_t)st;
+                status[col.base + (size_t)kk * col.slice] = (uint8_t)st;
             } else if (st == 6) {
-                float2 s;
+                float F, W;
                 if (!((loaded >> kk) & 1u)) {
-                    s.x = sc.tsdf[base + (size_t)kk * slice];
-                    s.y = sc.wg[base + (size_t)kk * slice];
+                    F = sc.tsdf[col.base + (size_t)kk * col.slice];
+                    W = sc.wg[col.base + (size_t)kk * col.slice];
                     loaded |= 1u << kk;
                 } else {
-                    const float4 t4 = slot[kk * BLOCK];
-                    s.x = t4.x;
-                    s.y = t4.y;
+                    const float4 t4 = slot[kk * WAVE];
+                    F = t4.x;
+                    W = t4.y;
                 }
                 const float t = fminf(1.0f, sdf * c.inv_trunc);
-                const float wn = s.y + 1.0f;
-                s.x = s.x + (t - s.x) / wn;
-                s.y = fminf(wn, c.w_max);
-                slot[kk * BLOCK] = make_float4(s.x, s.y, 0.0f, 0.0f);
+                const float wn = W + 1.0f;
+                F = F + (t - F) / wn;
+                W = fminf(wn, c.w_max);
+                slot[kk * WAVE] = make_float4(F, W, 0.0f, 0.0f);
                 ++n_upd;
             }
         }
     }
     if constexpr (MODE != MODE_STATUS) {
-        for (int kk = 0; kk < kn; ++kk) {
+        for (int kk = 0; kk < col.kn; ++kk) {
             if ((loaded >> kk) & 1u) {
-                const float4 t4 = slot[kk * BLOCK];
-                sc.tsdf[base + (size_t)kk * slice] = t4.x;
-                sc.wg[base + (size_t)kk * slice] = t4.y;
+                const float4 t4 = slot[kk * WAVE];
+                sc.tsdf[col.base + (size_t)kk * col.slice] = t4.x;
+                sc.wg[col.base + (size_t)kk * col.slice] = t4.y;
             }
         }
     }
@@ -158,57 +184,28 @@ __device__ __forceinline__ void geom_brick(const IntegrateArgs& a, const Scene& 
     }
 }
 
-// Bilinear HD sample of channel ch at cell `cell` (index of the top-left pixel's first
-// channel), Eq. 9's HD(x_hd, y_hd) read between pixel centres.
-__device__ __forceinline__ float hd_sample(const void* rgb, int fmt, int cell, int row, int ch,
-                                           float ax, float ay)
-{
-    float p00, p10, p01, p11;
-    if (fmt == FMT_RGB8) {
-        p00 = hd_px<FMT_RGB8>(rgb, cell + ch);
-        p10 = hd_px<FMT_RGB8>(rgb, cell + 3 + ch);
-        p01 = hd_px<FMT_RGB8>(rgb, cell + row + ch);
-        p11 = hd_px<FMT_RGB8>(rgb, cell + row + 3 + ch);
-    } else {
-        p00 = hd_px<FMT_RGBF32>(rgb, cell + ch);
-        p10 = hd_px<FMT_RGBF32>(rgb, cell + 3 + ch);
-        p01 = hd_px<FMT_RGBF32>(rgb, cell + row + ch);
-        p11 = hd_px<FMT_RGBF32>(rgb, cell + row + 3 + ch);
-    }
-    return lerp(lerp(p00, p10, ax), lerp(p01, p11, ax), ay);
-}
+// --------------------------------------------------------------- colour (Sec. IV.B)
 
-// Colour brick: Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10.
-template <int MODE, class Scene, class Frames>
-__device__ __forceinline__ void colour_brick(const IntegrateArgs& a, const Scene& sc,
-                                             Frames frames, int nf, uint32_t li, Scratch lds,
+// Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10, for the frames of mask.
+template <int MODE, class Scene, class FramePtr>
+__device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, uint32_t mask,
+                                             uint32_t li, float4* slot, uint8_t* status,
                                              Counts& cnt)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int X = sc.cdim[0], Y = sc.cdim[1], Z = sc.cdim[2];
-    const uint32_t tx = li % (uint32_t)sc.ctiles[0];
-    const uint32_t rest = li / (uint32_t)sc.ctiles[0];
-    const uint32_t ty = rest % (uint32_t)sc.ctiles[1];
-    const uint32_t tz = rest / (uint32_t)sc.ctiles[1];
-    const int i = (int)tx * TX + lane, j = (int)ty * TY + wave, k0 = (int)tz * ZS;
-    if (i >= X || j >= Y) return;
-    const int kn = min(ZS, Z - k0);
-    const size_t slice = (size_t)X * (size_t)Y;
-    const size_t base = ((size_t)k0 * (size_t)Y + (size_t)j) * (size_t)X + (size_t)i;
-    const float fi = (float)i, fj = (float)j;
-    float4* slot = lds.v + threadIdx.x;
-
+    const Column col = column<CBX, CBY>(sc.cdim, sc.cbricks, li);
+    if (!col.active) return;
+    const float fi = (float)col.i, fj = (float)col.j;
     uint32_t wl = 0;   // colour weight read (slot .w valid)
     uint32_t cl = 0;   // colour read and updated (slot .xyz valid, store at the end)
     unsigned long long n_eval = 0, n_upd = 0;
-    for (int f = 0; f < nf; ++f) {
-        const auto& c = frames[f];
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const auto& c = frames[__builtin_ctz(m)];
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
 #pragma unroll 2
-        for (int kk = 0; kk < kn; ++kk) {
-            const float fk = (float)(k0 + kk);
+        for (int kk = 0; kk < col.kn; ++kk) {
+            const float fk = (float)(col.k0 + kk);
             const float Xc = fmaf(c.Ac[2], fk, cX);
             const float Yc = fmaf(c.Ac[5], fk, cY);
             const float Zc = fmaf(c.Ac[8], fk, cZ);
@@ -260,8 +257,9 @@ __device__ __forceinline__ void colour_brick(const IntegrateArgs& a, const Scene
                 }
             }
             if (st >= 4) {
-                const size_t idx = base + (size_t)kk * slice;
-                float4 s = slot[kk * BLOCK];
+                const size_t idx = col.base + (size_t)kk * col.slice;
+                float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if constexpr (MODE != MODE_STATUS) s = slot[kk * WAVE];
                 if (!((wl >> kk) & 1u)) {
                     s.w = sc.wc[idx];
                     wl |= 1u << kk;
@@ -307,18 +305,18 @@ __device__ __forceinline__ void colour_brick(const IntegrateArgs& a, const Scene
                         s.w = fmaf(w, 1.0f - s.w, s.w);
                         ++n_upd;
                     }
+                    slot[kk * WAVE] = s;
                 }
-                slot[kk * BLOCK] = s;
             }
             if constexpr (MODE == MODE_STATUS)
-                a.cstatus[base + (size_t)kk * slice] = (uint8_t)st;
+                status[col.base + (size_t)kk * col.slice] = (uint8_t)st;
         }
     }
     if constexpr (MODE != MODE_STATUS) {
-        for (int kk = 0; kk < kn; ++kk) {
+        for (int kk = 0; kk < col.kn; ++kk) {
             if ((cl >> kk) & 1u) {
-                const size_t idx = base + (size_t)kk * slice;
-                const float4 s = slot[kk * BLOCK];
+                const size_t idx = col.base + (size_t)kk * col.slice;
+                const float4 s = slot[kk * WAVE];
                 sc.r[idx] = s.x;
                 sc.g[idx] = s.y;
                 sc.b[idx] = s.z;
@@ -334,44 +332,6 @@ __device__ __forceinline__ void colour_brick(const IntegrateArgs& a, const Scene
     }
 }
 
-// KIND: which bricks a kernel instantiation handles.
-enum Kind : int { KIND_BOTH = 0, KIND_GEOM = 1, KIND_COLOUR = 2 };
-
-template <int MODE, int KIND, class Scene, class Frames>
-__device__ __forceinline__ void run_brick(const IntegrateArgs& a, const Scene& sc,
-                                          Frames frames, int nf, uint32_t li, Scratch lds,
-                                          Counts& cnt)
-{
-    if constexpr (KIND == KIND_GEOM) {
-        geom_brick<MODE>(a, sc, frames, nf, li, lds, cnt);
-    } else if constexpr (KIND == KIND_COLOUR) {
-        colour_brick<MODE>(a, sc, frames, nf, li, lds, cnt);
-    } else {
-        if (li < sc.geom_items)
-            geom_brick<MODE>(a, sc, frames, nf, li, lds, cnt);
-        else
-            colour_brick<MODE>(a, sc, frames, nf, li - sc.geom_items, lds, cnt);
-    }
-}
-
-// INLINE: one scene and one frame passed by value; the geometry and the colour bricks of
-// the frame are then two launches (KIND_GEOM, KIND_COLOUR), item counted per kind.
-template <int MODE, bool INLINE, int KIND>
-__device__ __forceinline__ void run_item(const IntegrateArgs& a, uint32_t item, Scratch lds,
-                                         Counts& cnt)
-{
-    if constexpr (INLINE) {
-        run_brick<MODE, KIND>(a, a.scene0, InlineFrames{a.frame0}, 1, item, lds, cnt);
-    } else {
-        const const_ptr<SceneDev> scenes = as_const(a.scenes);
-        int s = 0;
-        while (s + 1 < a.n_scenes && scenes[s + 1].item_begin <= item) ++s;
-        const auto& sc = scenes[s];
-        run_brick<MODE, KIND_BOTH>(a, sc, TableFrames{as_const(a.frames) + sc.frame_begin},
-                                   sc.n_frames, item - sc.item_begin, lds, cnt);
-    }
-}
-
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 {
 #pragma unroll
@@ -379,44 +339,229 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
     return x;
 }
 
+// --------------------------------------------------------------------------- culling
+
+// Valid-depth (min, max) over pixels [u0,u1] x [v0,v1] (inclusive, inside the image),
+// read from the finest pyramid level on which the box spans at most 4 x 4 tiles.  The
+// tiles cover the box, so the range contains every depth inside it.
+__device__ float2 depth_range(const FrameConsts& c, int u0, int u1, int v0, int v1)
+{
+    int w = c.pyr_w0, h = c.pyr_h0, off = 0, s = PYR_SHIFT;
+    for (int l = 0; l < c.pyr_levels; ++l) {
+        const int tx0 = u0 >> s, tx1 = u1 >> s, ty0 = v0 >> s, ty1 = v1 >> s;
+        if ((tx1 - tx0 <= 3 && ty1 - ty0 <= 3) || l == c.pyr_levels - 1) {
+            float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const float2 r = c.pyr[off + ty * w + tx];
+                    dmin = fminf(dmin, r.x);
+                    dmax = fmaxf(dmax, r.y);
+                }
+            return make_float2(dmin, dmax);
+        }
+        off += w * h;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+        ++s;
+    }
+    return make_float2(__builtin_huge_valf(), -__builtin_huge_valf());
+}
+
+// Can any voxel of the index box [i0,i1] x [j0,j1] x [k0,k1] pass the depth tests of this
+// frame?  Its voxel centres form a parallelepiped (Eq. 5 is affine in the index), so
+// their depths lie between the corners' and, when all corners are in front of the
+// camera, their projections lie in the corners' bounding box (widened by a pixel for
+// rounding).  A colour voxel needs a depth within sigma of its own z (|p - P| >= |z - d|);
+// a geometry voxel needs a depth no more than trunc in front of it.  1 mm of slack covers
+// the single-precision rounding of z and d.
+__device__ bool brick_live(const FrameConsts& c, bool colour, int i0, int i1, int j0, int j1,
+                           int k0, int k1)
+{
+    const float* A = colour ? c.Ac : c.Ag;
+    const float* b = colour ? c.bc : c.bg;
+    float zmin = __builtin_huge_valf(), zmax = -__builtin_huge_valf();
+    float xmin = __builtin_huge_valf(), xmax = -__builtin_huge_valf();
+    float ymin = __builtin_huge_valf(), ymax = -__builtin_huge_valf();
+    bool near = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float fi = (float)((q & 1) ? i1 : i0);
+        const float fj = (float)((q & 2) ? j1 : j0);
+        const float fk = (float)((q & 4) ? k1 : k0);
+        const float X = fmaf(A[2], fk, fmaf(A[1], fj, fmaf(A[0], fi, b[0])));
+        const float Y = fmaf(A[5], fk, fmaf(A[4], fj, fmaf(A[3], fi, b[1])));
+        const float Z = fmaf(A[8], fk, fmaf(A[7], fj, fmaf(A[6], fi, b[2])));
+        zmin = fminf(zmin, Z);
+        zmax = fmaxf(zmax, Z);
+        if (Z > 1e-3f) {
+            const float x = c.fx * (X / Z) + c.cx, y = c.fy * (Y / Z) + c.cy;
+            xmin = fminf(xmin, x);
+            xmax = fmaxf(xmax, x);
+            ymin = fminf(ymin, y);
+            ymax = fmaxf(ymax, y);
+        } else {
+            near = true;
+        }
+    }
+    if (!(zmax > -1e-4f)) return false;                  // entirely behind the camera
+    int u0 = 0, u1 = c.dw - 1, v0 = 0, v1 = c.dh - 1;
+    if (!near) {
+        const float fu0 = floorf(xmin) - 1.0f, fu1 = ceilf(xmax) + 1.0f;
+        const float fv0 = floorf(ymin) - 1.0f, fv1 = ceilf(ymax) + 1.0f;
+        if (fu1 < 0.0f || fu0 > c.wm1 || fv1 < 0.0f || fv0 > c.hm1) return false;
+        u0 = (int)fmaxf(fu0, 0.0f);
+        u1 = (int)fminf(fu1, c.wm1);
+        v0 = (int)fmaxf(fv0, 0.0f);
+        v1 = (int)fminf(fv1, c.hm1);
+    }
+    const float2 r = depth_range(c, u0, u1, v0, v1);
+    if (!(r.x <= r.y)) return false;                      // no measurement in the footprint
+    const float slack = 1e-3f;
+    if (colour) return r.x <= zmax + c.sigma + slack && r.y >= zmin - c.sigma - slack;
+    return zmin <= r.y + c.trunc + slack;
+}
+
 }  // namespace
 
-template <int MODE, bool INLINE, int KIND>
+__global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
+{
+    const uint32_t item = blockIdx.x * BLOCK + threadIdx.x;
+    uint32_t mask = 0;
+    if (item < a.n_items) {
+        int s = 0;
+        while (s + 1 < a.n_scenes && a.scenes[s + 1].item_begin <= item) ++s;
+        const SceneDev& sc = a.scenes[s];
+        uint32_t li = item - sc.item_begin;
+        const bool colour = li >= sc.geom_items;
+        if (colour) li -= sc.geom_items;
+        const int32_t* dim = colour ? sc.cdim : sc.gdim;
+        const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
+        const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
+        const int bx = (int)(li % (uint32_t)nb[0]);
+        const int by = (int)((li / (uint32_t)nb[0]) % (uint32_t)nb[1]);
+        const int bz = (int)(li / ((uint32_t)nb[0] * (uint32_t)nb[1]));
+        const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
+        const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
+        const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
+        for (int f = 0; f < sc.n_frames; ++f) {
+            if (a.disable || brick_live(a.frames[sc.frame_begin + f], colour, i0, i1, j0, j1, k0, k1))
+                mask |= 1u << f;
+        }
+    }
+    // append the live bricks: one atomic per wave
+    const unsigned long long live = __ballot(mask != 0);
+    if (live == 0) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(a.n_live, (uint32_t)__popcll(live));
+    base = __shfl(base, 0, WAVE);
+    if (mask) {
+        const uint32_t rank = (uint32_t)__popcll(live & ((1ull << lane) - 1ull));
+        a.live[base + rank] = make_uint2(item, mask);
+    }
+}
+
+// ------------------------------------------------------------------- depth pyramid
+
+// Level 0: one lane per 8x8 tile of one frame (blockIdx.y = frame).
+__global__ __launch_bounds__(BLOCK) void pyramid_base_kernel(const FrameConsts* frames)
+{
+    const FrameConsts& c = frames[blockIdx.y];
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= c.pyr_w0 * c.pyr_h0) return;
+    const int tx = t % c.pyr_w0, ty = t / c.pyr_w0;
+    float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
+    const int u0 = tx << PYR_SHIFT, v0 = ty << PYR_SHIFT;
+    const int u1 = min(c.dw, u0 + (1 << PYR_SHIFT)), v1 = min(c.dh, v0 + (1 << PYR_SHIFT));
+    for (int v = v0; v < v1; ++v)
+        for (int u = u0; u < u1; ++u) {
+            const float d = c.depth[v * c.dw + u];
+            if (valid_depth(d)) {
+                dmin = fminf(dmin, d);
+                dmax = fmaxf(dmax, d);
+            }
+        }
+    c.pyr[t] = make_float2(dmin, dmax);
+}
+
+// Levels 1.. : one block per frame, each level the 2x2 reduction of the previous one.
+__global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* frames)
+{
+    const FrameConsts& c = frames[blockIdx.x];
+    int w = c.pyr_w0, h = c.pyr_h0, off = 0;
+    for (int l = 1; l < c.pyr_levels; ++l) {
+        const int nw = (w + 1) / 2, nh = (h + 1) / 2, noff = off + w * h;
+        for (int t = threadIdx.x; t < nw * nh; t += BLOCK) {
+            const int tx = t % nw, ty = t / nw;
+            float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
+            for (int y = 2 * ty; y < min(h, 2 * ty + 2); ++y)
+                for (int x = 2 * tx; x < min(w, 2 * tx + 2); ++x) {
+                    const float2 r = c.pyr[off + y * w + x];
+                    dmin = fminf(dmin, r.x);
+                    dmax = fmaxf(dmax, r.y);
+                }
+            c.pyr[noff + t] = make_float2(dmin, dmax);
+        }
+        __syncthreads();
+        off = noff;
+        w = nw;
+        h = nh;
+    }
+}
+
+// ------------------------------------------------------------------------ integration
+
+// Persistent waves: each takes (brick, frame mask) entries from the live list.
+template <int MODE>
 __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
-    __shared__ float4 s_state[ZS * BLOCK];
-    __shared__ uint32_t s_item;
+    __shared__ float4 s_state[BLOCK * ZS];
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float4* slot = s_state + wave * WAVE * ZS + lane;
     Counts cnt;
-    const Scratch lds{s_state};
+    const uint32_t n_live = *as_const(a.n_live);
+    const const_ptr<SceneDev> scenes = as_const(a.scenes);
     for (;;) {
-        uint32_t item;
-        if (a.queue) {
-            // persistent launch: take the next brick from the shared queue
-            if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1u);
-            __syncthreads();
-            // the item is the same for the whole block: keep it (and everything derived
-            // from it, such as the frame constants) in scalar registers
-            item = __builtin_amdgcn_readfirstlane(s_item);
-            __syncthreads();
-        } else {
-            // grid launch: consecutive blocks go to different XCDs round-robin, so hand
-            // each XCD a contiguous range of bricks (and of the image footprint) instead
-            item = (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
-        }
-        if (item >= a.n_items) break;
-        run_item<MODE, INLINE, KIND>(a, item, lds, cnt);
-        if (!a.queue) break;
+        uint32_t e = 0;
+        if (lane == 0) e = atomicAdd(a.queue, 1u);
+        e = __builtin_amdgcn_readfirstlane(e);
+        if (e >= n_live) break;
+        const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 2 * (size_t)e;
+        const uint32_t item = ent[0], fmask = ent[1];
+        int s = 0;
+        while (s + 1 < a.n_scenes && scenes[s + 1].item_begin <= item) ++s;
+        const auto& sc = scenes[s];
+        const const_ptr<FrameConsts> frames = as_const(a.frames) + sc.frame_begin;
+        const uint32_t li = item - sc.item_begin;
+        if (li < sc.geom_items)
+            geom_brick<MODE>(sc, frames, fmask, li, slot, nullptr, cnt);
+        else
+            colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, slot, nullptr, cnt);
     }
     if constexpr (MODE == MODE_COUNT) {
         const unsigned long long v[6] = {wave_sum(cnt.g_upd), wave_sum(cnt.g_touch),
                                          wave_sum(cnt.c_eval), wave_sum(cnt.c_read),
                                          wave_sum(cnt.c_upd), wave_sum(cnt.c_touch)};
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 6; ++q)
                 if (v[q]) atomicAdd(a.counters + q, v[q]);
         }
     }
+}
+
+// Outcome codes of one frame for every brick of one kind (no culling, no update).
+template <bool COLOUR>
+__global__ __launch_bounds__(BLOCK) void status_kernel(StatusArgs a)
+{
+    const uint32_t li = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+    if (li >= a.n_items) return;
+    Counts cnt;
+    const FrameConsts* frames = &a.frame;
+    if constexpr (COLOUR)
+        colour_brick<MODE_STATUS>(a.scene, frames, 1u, li, nullptr, a.status, cnt);
+    else
+        geom_brick<MODE_STATUS>(a.scene, frames, 1u, li, nullptr, a.status, cnt);
 }
 
 __global__ void fill_f32_kernel(float* p, size_t n, float v)
@@ -433,44 +578,47 @@ __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v)
 
 // ----------------------------------------------------------------------------- launchers
 
-static uint32_t pad8(uint32_t n) { return (n + 7u) / 8u * 8u; }
-
-
-template <int MODE, bool INLINE, int KIND>
-static void launch_one(const IntegrateArgs& a, uint32_t blocks, hipStream_t stream)
+hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_tiles0,
+                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((integrate_kernel<MODE, INLINE, KIND>), dim3(blocks), dim3(BLOCK), 0,
-                       stream, a);
+    if (n_frames <= 0) return hipSuccess;
+    const unsigned bx = (unsigned)((max_tiles0 + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(pyramid_base_kernel, dim3(bx, (unsigned)n_frames), dim3(BLOCK), 0, stream,
+                       frames_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pyramid_up_kernel, dim3((unsigned)n_frames), dim3(BLOCK), 0, stream,
+                       frames_dev);
+    return hipGetLastError();
 }
 
-hipError_t launch_integrate(int mode, bool inline_args, const IntegrateArgs& a, uint32_t grid,
-                            hipStream_t stream)
+hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
 {
-    if (inline_args) {
-        // one frame of one scene: geometry bricks, then colour bricks
-        IntegrateArgs g = a, c = a;
-        g.n_items = a.scene0.geom_items;
-        c.n_items = a.scene0.colour_items;
-        const uint32_t gb = pad8(g.n_items), cb = pad8(c.n_items);
-        if (mode == MODE_INTEGRATE) {
-            if (gb) launch_one<MODE_INTEGRATE, true, KIND_GEOM>(g, gb, stream);
-            if (cb) launch_one<MODE_INTEGRATE, true, KIND_COLOUR>(c, cb, stream);
-        } else if (mode == MODE_STATUS) {
-            if (gb) launch_one<MODE_STATUS, true, KIND_GEOM>(g, gb, stream);
-            if (cb) launch_one<MODE_STATUS, true, KIND_COLOUR>(c, cb, stream);
-        } else {
-            if (gb) launch_one<MODE_COUNT, true, KIND_GEOM>(g, gb, stream);
-            if (cb) launch_one<MODE_COUNT, true, KIND_COLOUR>(c, cb, stream);
-        }
-        return hipGetLastError();
-    }
-    // table-driven launch, persistent when a.queue is set (grid blocks), else one block
-    // per brick
-    const uint32_t blocks = a.queue ? grid : pad8(a.n_items);
-    if (blocks == 0) return hipSuccess;
-    if (mode == MODE_INTEGRATE) launch_one<MODE_INTEGRATE, false, KIND_BOTH>(a, blocks, stream);
-    else if (mode == MODE_COUNT) launch_one<MODE_COUNT, false, KIND_BOTH>(a, blocks, stream);
-    else return hipErrorInvalidValue;
+    if (a.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(cull_kernel, dim3((a.n_items + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(int mode, const IntegrateArgs& a, uint32_t grid, hipStream_t stream)
+{
+    if (grid == 0) return hipSuccess;
+    if (mode == MODE_INTEGRATE)
+        hipLaunchKernelGGL(integrate_kernel<MODE_INTEGRATE>, dim3(grid), dim3(BLOCK), 0, stream, a);
+    else if (mode == MODE_COUNT)
+        hipLaunchKernelGGL(integrate_kernel<MODE_COUNT>, dim3(grid), dim3(BLOCK), 0, stream, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream)
+{
+    if (a.n_items == 0) return hipSuccess;
+    const unsigned blocks = (a.n_items + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
+    if (colour)
+        hipLaunchKernelGGL(status_kernel<true>, dim3(blocks), dim3(BLOCK), 0, stream, a);
+    else
+        hipLaunchKernelGGL(status_kernel<false>, dim3(blocks), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -480,11 +628,9 @@ hipError_t persistent_grid(int mode, int device, uint32_t* blocks)
     hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
     if (mode == MODE_COUNT)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, integrate_kernel<MODE_COUNT, false, KIND_BOTH>, BLOCK, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_kernel<MODE_COUNT>, BLOCK, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, integrate_kernel<MODE_INTEGRATE, false, KIND_BOTH>, BLOCK, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_kernel<MODE_INTEGRATE>, BLOCK, 0);
     if (e != hipSuccess) return e;
     *blocks = (uint32_t)(n_cu * (per_cu > 0 ? per_cu : 1));
     return hipSuccess;

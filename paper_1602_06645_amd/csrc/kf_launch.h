@@ -6,10 +6,16 @@
 
 namespace kf {
 
-// mode: Mode; inline_args: single scene and single frame passed by value in `a`.
-// grid: number of blocks of a persistent launch (a.queue != NULL); ignored otherwise.
-hipError_t launch_integrate(int mode, bool inline_args, const IntegrateArgs& a, uint32_t grid,
-                            hipStream_t stream);
+// Depth min/max pyramids of frames_dev[0 .. n_frames); max_tiles0: the largest level-0
+// tile count among them.
+hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_tiles0,
+                           hipStream_t stream);
+// One lane per brick of the pass: append (brick, live-frame mask) entries.
+hipError_t launch_cull(const CullArgs& a, hipStream_t stream);
+// Persistent integration over the live list (mode: MODE_INTEGRATE or MODE_COUNT).
+hipError_t launch_integrate(int mode, const IntegrateArgs& a, uint32_t grid, hipStream_t stream);
+// Status codes of one frame for every brick of one kind.
+hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream);
 // Blocks that stay resident at once on `device` for a persistent launch of `mode`.
 hipError_t persistent_grid(int mode, int device, uint32_t* blocks);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t stream);

@@ -117,3 +117,17 @@ def test_kinect_properties_at_any_size(kinect8):
     for c in (r, g, b):
         assert float(c.min()) >= 0 and float(c.max()) <= 1 + 1e-6
     assert int((wc > 0).sum()) > 10 ** 5
+
+
+def test_culling_changes_nothing(kinect8, monkeypatch):
+    """Skipping bricks that cannot pass the depth tests leaves every bit of the volume
+    unchanged (the library reads KF_DISABLE_CULL on every call)."""
+    spec, fr = kinect8
+    say("kinect full size: culling on vs off")
+    a, b = kf.Volume(spec), kf.Volume(spec)
+    scan = kf.Scan.from_frames(fr)
+    kf.integrate_batch([(a, scan)], frames_per_pass=8)
+    monkeypatch.setenv("KF_DISABLE_CULL", "1")
+    kf.integrate_batch([(b, scan)], frames_per_pass=8)
+    monkeypatch.delenv("KF_DISABLE_CULL")
+    assert_bitwise(to_host(a), to_host(b), "cull vs no cull: ")
