@@ -154,7 +154,10 @@ def main() -> int:
                      "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
         "counters": {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
                      "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),
-                     "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5])},
+                     "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5]),
+                     "geom_brick_frames": int(cnt[6]), "colour_brick_frames": int(cnt[7]),
+                     "geom_live_fraction": int(cnt[6]) * 512 / (spec.n_geom * fr.n),
+                     "colour_live_fraction": int(cnt[7]) * 512 / (spec.n_colour * fr.n)},
         "effective_voxel_updates_per_s": (int(cnt[0]) + int(cnt[4])) * args.steps / wall,
     }
 

@@ -133,11 +133,13 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
 
 /*
  * Byte accounting for kf_integrate_batch with the same arguments: performs the same
- * integration and adds into counters (device, uint64[6], not cleared):
+ * integration and adds into counters (device, uint64[8], not cleared):
  *   [0] geometry voxel updates        [1] geometry voxels updated at least once per pass
  *   [2] colour voxel-frames reaching the weight gate
  *   [3] colour voxels reaching the gate at least once per pass
  *   [4] colour voxel updates          [5] colour voxels updated at least once per pass
+ *   [6] geometry brick-frames processed  [7] colour brick-frames processed
+ *       (a brick is 512 voxels; the rest were culled as unable to pass the depth tests)
  * Slower than kf_integrate_batch; for measurement only.
  */
 kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,

@@ -178,10 +178,10 @@ def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) ->
 
 
 def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:
-    """Same as integrate_batch, and return the six byte-accounting counters (include/kf.h)."""
+    """Same as integrate_batch, and return the eight accounting counters (include/kf.h)."""
     arr = _scenes(pairs)
     dev = pairs[0][0].tsdf.device if pairs else torch.device("cuda")
-    cnt = torch.zeros(6, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
     L.check(L.load().kf_integrate_batch_counted(arr, len(pairs), int(frames_per_pass),
                                                 C.c_void_p(cnt.data_ptr()), _stream()))
     return cnt.cpu().numpy()

@@ -62,7 +62,7 @@ struct IntegrateArgs {
     const uint2* live;                // (brick, frame mask) of the bricks to process
     const uint32_t* n_live;           // number of entries in `live`
     uint32_t* queue;                  // next entry to take
-    unsigned long long* counters;     // MODE_COUNT: uint64[6]
+    unsigned long long* counters;     // MODE_COUNT: uint64[8]
 };
 
 // Single-frame status dump (no culling, no update): one scene and frame by value.

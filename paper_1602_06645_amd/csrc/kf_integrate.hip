@@ -77,6 +77,7 @@ __device__ __forceinline__ const_ptr<T> as_const(const T* p)
 
 struct Counts {
     unsigned long long g_upd = 0, g_touch = 0, c_eval = 0, c_read = 0, c_upd = 0, c_touch = 0;
+    unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (counted by lane 0)
 };
 
 // Voxel column of a lane in brick li of a volume with brick shape BX x BY x ZS.
@@ -105,14 +106,70 @@ __device__ __forceinline__ Column column(const Dims& dim, const Dims& bricks, ui
     return c;
 }
 
+// ------------------------------------------------------------------ image fetches
+
+// The lane's LDS scratchpad (see integrate_kernel): one 16-byte entry per voxel.
+struct alignas(16) Vox {
+    float x, y, z, w;
+};
+using Slot = __attribute__((address_space(3))) Vox*;
+
+__device__ __forceinline__ float4 slot_get(Slot s, int k)
+{
+    return make_float4(s[k].x, s[k].y, s[k].z, s[k].w);
+}
+
+__device__ __forceinline__ void slot_put(Slot s, int k, float4 v)
+{
+    s[k].x = v.x;
+    s[k].y = v.y;
+    s[k].z = v.z;
+    s[k].w = v.w;
+}
+
+// Depth maps are read through a bounds-checked buffer resource: an offset past the image
+// reads 0 (a hole), so a voxel outside the frustum needs no separate branch.
+constexpr uint32_t kOutside = 0x7FFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
+// Nearest depth pixel of camera point (X, Y, Z) (Eq. 6 with the perspective division):
+// the pixel as floats, whether it lies inside the image, and its byte offset (kOutside
+// when it does not).
+struct Pixel {
+    float u, v;
+    bool inside;
+    uint32_t off;
+};
+
+template <class C>
+__device__ __forceinline__ Pixel project(const C& c, float X, float Y, float Z)
+{
+    Pixel p;
+    const float iz = 1.0f / Z;
+    p.u = rintf(fmaf(c.fx, X * iz, c.cx));
+    p.v = rintf(fmaf(c.fy, Y * iz, c.cy));
+    p.inside = (Z > 0.0f) & (p.u >= 0.0f) & (p.u <= c.wm1) & (p.v >= 0.0f) & (p.v <= c.hm1);
+    p.off = p.inside ? ((uint32_t)(int)p.v * (uint32_t)c.dw + (uint32_t)(int)p.u) * 4u : kOutside;
+    return p;
+}
+
 // ------------------------------------------------------------------ geometry (Sec. III)
 
 // Projective TSDF with running average for the frames of `mask` (bit f = frame f of the
 // pass).  MODE_STATUS writes the outcome code of the (single) frame instead.
 template <int MODE, class Scene, class FramePtr>
 __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uint32_t mask,
-                                           uint32_t li, float4* slot, uint8_t* status,
-                                           Counts& cnt)
+                                           uint32_t li, Slot slot, uint8_t* status, Counts& cnt)
 {
     const Column col = column<GBX, GBY>(sc.gdim, sc.gbricks, li);
     if (!col.active) return;
@@ -121,50 +178,42 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
     unsigned long long n_upd = 0;
     for (uint32_t m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctz(m)];
+        const __amdgpu_buffer_rsrc_t depth = image_rsrc(c.depth, (uint32_t)(c.dw * c.dh) * 4u);
         // Eq. 5 for this column; the z term is added per voxel.
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
         const float cY = fmaf(c.Ag[4], fj, fmaf(c.Ag[3], fi, c.bg[1]));
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
+        const float trunc = c.trunc, inv_trunc = c.inv_trunc, w_max = c.w_max;
 #pragma unroll 2
         for (int kk = 0; kk < col.kn; ++kk) {
             const float fk = (float)(col.k0 + kk);
             const float Xc = fmaf(c.Ag[2], fk, cX);
             const float Yc = fmaf(c.Ag[5], fk, cY);
             const float Zc = fmaf(c.Ag[8], fk, cZ);
-            int st = 0;
-            float sdf = 0.0f;
-            if (Zc > 0.0f) {
-                // Eq. 6 with the perspective division; nearest depth pixel.
-                const float iz = 1.0f / Zc;
-                const float u = rintf(fmaf(c.fx, Xc * iz, c.cx));
-                const float v = rintf(fmaf(c.fy, Yc * iz, c.cy));
-                if (u >= 0.0f && u <= c.wm1 && v >= 0.0f && v <= c.hm1) {
-                    const float d = c.depth[(int)v * c.dw + (int)u];
-                    st = 1;
-                    if (valid_depth(d)) {
-                        sdf = d - Zc;
-                        st = (sdf < -c.trunc) ? 2 : 6;
-                    }
-                }
-            }
+            const Pixel px = project(c, Xc, Yc, Zc);
+            const float d = load_f32(depth, px.off);
+            const bool valid = px.inside & valid_depth(d);
+            const float sdf = d - Zc;
+            const bool upd = valid & !(sdf < -trunc);
             if constexpr (MODE == MODE_STATUS) {
+                const int st = !px.inside ? 0 : !valid ? 1 : upd ? 6 : 2;
                 status[col.base + (size_t)kk * col.slice] = (uint8_t)st;
-            } else if (st == 6) {
+            } else if (upd) {
                 float F, W;
                 if (!((loaded >> kk) & 1u)) {
                     F = sc.tsdf[col.base + (size_t)kk * col.slice];
                     W = sc.wg[col.base + (size_t)kk * col.slice];
                     loaded |= 1u << kk;
                 } else {
-                    const float4 t4 = slot[kk * WAVE];
+                    const float4 t4 = slot_get(slot, kk * WAVE);
                     F = t4.x;
                     W = t4.y;
                 }
-                const float t = fminf(1.0f, sdf * c.inv_trunc);
+                const float t = fminf(1.0f, sdf * inv_trunc);
                 const float wn = W + 1.0f;
                 F = F + (t - F) / wn;
-                W = fminf(wn, c.w_max);
-                slot[kk * WAVE] = make_float4(F, W, 0.0f, 0.0f);
+                W = fminf(wn, w_max);
+                slot_put(slot, kk * WAVE, make_float4(F, W, 0.0f, 0.0f));
                 ++n_upd;
             }
         }
@@ -172,7 +221,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
     if constexpr (MODE != MODE_STATUS) {
         for (int kk = 0; kk < col.kn; ++kk) {
             if ((loaded >> kk) & 1u) {
-                const float4 t4 = slot[kk * WAVE];
+                const float4 t4 = slot_get(slot, kk * WAVE);
                 sc.tsdf[col.base + (size_t)kk * col.slice] = t4.x;
                 sc.wg[col.base + (size_t)kk * col.slice] = t4.y;
             }
@@ -187,9 +236,11 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
 // --------------------------------------------------------------- colour (Sec. IV.B)
 
 // Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10, for the frames of mask.
+// The frustum, depth and sigma tests run without branches; the rest only for the voxels
+// that pass them.
 template <int MODE, class Scene, class FramePtr>
 __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, uint32_t mask,
-                                             uint32_t li, float4* slot, uint8_t* status,
+                                             uint32_t li, Slot slot, uint8_t* status,
                                              Counts& cnt)
 {
     const Column col = column<CBX, CBY>(sc.cdim, sc.cbricks, li);
@@ -200,112 +251,96 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
     unsigned long long n_eval = 0, n_upd = 0;
     for (uint32_t m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctz(m)];
+        const __amdgpu_buffer_rsrc_t depth = image_rsrc(c.depth, (uint32_t)(c.dw * c.dh) * 4u);
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
+        const float sigma2 = c.sigma2;
 #pragma unroll 2
         for (int kk = 0; kk < col.kn; ++kk) {
             const float fk = (float)(col.k0 + kk);
             const float Xc = fmaf(c.Ac[2], fk, cX);
             const float Yc = fmaf(c.Ac[5], fk, cY);
             const float Zc = fmaf(c.Ac[8], fk, cZ);
-            int st = 0;
-            float w = 0.0f;
-            if (Zc > 0.0f) {
-                const float iz = 1.0f / Zc;
-                const float u = rintf(fmaf(c.fx, Xc * iz, c.cx));
-                const float v = rintf(fmaf(c.fy, Yc * iz, c.cy));
-                if (u >= 0.0f && u <= c.wm1 && v >= 0.0f && v <= c.hm1) {
-                    const int pix = (int)v * c.dw + (int)u;
-                    const float d = c.depth[pix];
-                    st = 1;
-                    if (valid_depth(d)) {
-                        // Eq. 7 at the integer pixel, then the distance test against sigma.
-                        const float Px = ((u - c.cx) * c.inv_fx) * d;
-                        const float Py = ((v - c.cy) * c.inv_fy) * d;
-                        const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
-                        const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        st = 2;
-                        if (!(dist2 > c.sigma2)) {
-                            st = 3;
-                            if (u + 1.0f <= c.wm1 && v + 1.0f <= c.hm1) {
-                                const float d1 = c.depth[pix + 1];
-                                const float d2 = c.depth[pix + c.dw];
-                                if (valid_depth(d1) && valid_depth(d2)) {
-                                    // Eq. 8 from the neighbours (u+1, v) and (u, v+1).
-                                    const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1;
-                                    const float P1y = ((v - c.cy) * c.inv_fy) * d1;
-                                    const float P2x = ((u - c.cx) * c.inv_fx) * d2;
-                                    const float P2y = ((v + 1.0f - c.cy) * c.inv_fy) * d2;
-                                    const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1 - d;
-                                    const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2 - d;
-                                    const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
-                                    const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
-                                    const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
-                                    const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
-                                    if (nn > 0.0f) {
-                                        // W: unit normal . unit viewing direction (camera -> P).
-                                        const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
-                                        const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
-                                        w = dp / sqrtf(nn * pp);
-                                        st = 4;
-                                    }
-                                }
-                            }
-                        }
+            const Pixel px = project(c, Xc, Yc, Zc);
+            const float d = load_f32(depth, px.off);
+            const bool valid = px.inside & valid_depth(d);
+            // Eq. 7 at the integer pixel, then the distance test against sigma.
+            const float Px = ((px.u - c.cx) * c.inv_fx) * d;
+            const float Py = ((px.v - c.cy) * c.inv_fy) * d;
+            const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
+            const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool band = valid & !(dist2 > sigma2);
+            int st = !px.inside ? 0 : !valid ? 1 : band ? 3 : 2;
+            if (band) {
+                // Eq. 8 from the neighbours (u+1, v) and (u, v+1).
+                const bool has_nb = (px.u + 1.0f <= c.wm1) & (px.v + 1.0f <= c.hm1);
+                const float d1 = load_f32(depth, has_nb ? px.off + 4u : kOutside);
+                const float d2 = load_f32(depth, has_nb ? px.off + (uint32_t)c.dw * 4u : kOutside);
+                const float P1x = ((px.u + 1.0f - c.cx) * c.inv_fx) * d1;
+                const float P1y = ((px.v - c.cy) * c.inv_fy) * d1;
+                const float P2x = ((px.u - c.cx) * c.inv_fx) * d2;
+                const float P2y = ((px.v + 1.0f - c.cy) * c.inv_fy) * d2;
+                const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1 - d;
+                const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2 - d;
+                const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
+                const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
+                const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
+                const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
+                if (has_nb & valid_depth(d1) & valid_depth(d2) & (nn > 0.0f)) {
+                    // W: unit normal . unit viewing direction (camera -> P).
+                    const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
+                    const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
+                    const float w = dp / sqrtf(nn * pp);
+                    st = 4;
+                    const size_t idx = col.base + (size_t)kk * col.slice;
+                    float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    if constexpr (MODE != MODE_STATUS) s = slot_get(slot, kk * WAVE);
+                    if (!((wl >> kk) & 1u)) {
+                        s.w = sc.wc[idx];
+                        wl |= 1u << kk;
                     }
-                }
-            }
-            if (st >= 4) {
-                const size_t idx = col.base + (size_t)kk * col.slice;
-                float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if constexpr (MODE != MODE_STATUS) s = slot[kk * WAVE];
-                if (!((wl >> kk) & 1u)) {
-                    s.w = sc.wc[idx];
-                    wl |= 1u << kk;
-                }
-                ++n_eval;
-                float ax = 0.0f, ay = 0.0f;
-                int cell = 0;
-                if (w > c.gate * s.w) {
-                    // Eq. 3-5 on the voxel centre: HD pixel and bilinear cell.
-                    st = 5;
-                    const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
-                    const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
-                    const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-                    if (qz > 0.0f) {
+                    ++n_eval;
+                    float ax = 0.0f, ay = 0.0f;
+                    int cell = 0;
+                    if (w > c.gate * s.w) {
+                        // Eq. 3-5 on the voxel centre: HD pixel and bilinear cell.
+                        st = 5;
+                        const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
+                        const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
+                        const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
                         const float iqz = 1.0f / qz;
                         const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
                         const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
                         const float x0 = floorf(xh), y0 = floorf(yh);
-                        if (x0 >= 0.0f && x0 <= c.cwm2 && y0 >= 0.0f && y0 <= c.chm2) {
+                        if ((qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.cwm2) & (y0 >= 0.0f) & (y0 <= c.chm2)) {
                             st = 6;
                             ax = xh - x0;
                             ay = yh - y0;
                             cell = ((int)y0 * c.cw + (int)x0) * 3;
                         }
                     }
-                }
-                if constexpr (MODE != MODE_STATUS) {
-                    if (st == 6) {
-                        if (!((cl >> kk) & 1u)) {
-                            s.x = sc.r[idx];
-                            s.y = sc.g[idx];
-                            s.z = sc.b[idx];
-                            cl |= 1u << kk;
+                    if constexpr (MODE != MODE_STATUS) {
+                        if (st == 6) {
+                            if (!((cl >> kk) & 1u)) {
+                                s.x = sc.r[idx];
+                                s.y = sc.g[idx];
+                                s.z = sc.b[idx];
+                                cl |= 1u << kk;
+                            }
+                            const int row = c.cw * 3;
+                            const float s0 = hd_sample(c.rgb, sc.fmt, cell, row, 0, ax, ay);
+                            const float s1 = hd_sample(c.rgb, sc.fmt, cell, row, 1, ax, ay);
+                            const float s2 = hd_sample(c.rgb, sc.fmt, cell, row, 2, ax, ay);
+                            const float alpha = w / (s.w + w);
+                            s.x = fmaf(alpha, s0 - s.x, s.x);
+                            s.y = fmaf(alpha, s1 - s.y, s.y);
+                            s.z = fmaf(alpha, s2 - s.z, s.z);
+                            s.w = fmaf(w, 1.0f - s.w, s.w);
+                            ++n_upd;
                         }
-                        const int row = c.cw * 3;
-                        const float s0 = hd_sample(c.rgb, sc.fmt, cell, row, 0, ax, ay);
-                        const float s1 = hd_sample(c.rgb, sc.fmt, cell, row, 1, ax, ay);
-                        const float s2 = hd_sample(c.rgb, sc.fmt, cell, row, 2, ax, ay);
-                        const float alpha = w / (s.w + w);
-                        s.x = fmaf(alpha, s0 - s.x, s.x);
-                        s.y = fmaf(alpha, s1 - s.y, s.y);
-                        s.z = fmaf(alpha, s2 - s.z, s.z);
-                        s.w = fmaf(w, 1.0f - s.w, s.w);
-                        ++n_upd;
+                        slot_put(slot, kk * WAVE, s);
                     }
-                    slot[kk * WAVE] = s;
                 }
             }
             if constexpr (MODE == MODE_STATUS)
@@ -316,7 +351,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         for (int kk = 0; kk < col.kn; ++kk) {
             if ((cl >> kk) & 1u) {
                 const size_t idx = col.base + (size_t)kk * col.slice;
-                const float4 s = slot[kk * WAVE];
+                const float4 s = slot_get(slot, kk * WAVE);
                 sc.r[idx] = s.x;
                 sc.g[idx] = s.y;
                 sc.b[idx] = s.z;
@@ -515,9 +550,10 @@ __global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* fr
 template <int MODE>
 __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
-    __shared__ float4 s_state[BLOCK * ZS];
+    // per-lane state scratchpad: slot kk of a lane at [kk * WAVE] from its base
+    __shared__ Vox s_state[BLOCK * ZS];
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    float4* slot = s_state + wave * WAVE * ZS + lane;
+    const Slot slot = (Slot)(s_state + wave * WAVE * ZS + lane);
     Counts cnt;
     const uint32_t n_live = *as_const(a.n_live);
     const const_ptr<SceneDev> scenes = as_const(a.scenes);
@@ -533,18 +569,22 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
         const auto& sc = scenes[s];
         const const_ptr<FrameConsts> frames = as_const(a.frames) + sc.frame_begin;
         const uint32_t li = item - sc.item_begin;
-        if (li < sc.geom_items)
+        if (li < sc.geom_items) {
             geom_brick<MODE>(sc, frames, fmask, li, slot, nullptr, cnt);
-        else
+            if (MODE == MODE_COUNT && lane == 0) cnt.g_bricks += (unsigned)__builtin_popcount(fmask);
+        } else {
             colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, slot, nullptr, cnt);
+            if (MODE == MODE_COUNT && lane == 0) cnt.c_bricks += (unsigned)__builtin_popcount(fmask);
+        }
     }
     if constexpr (MODE == MODE_COUNT) {
-        const unsigned long long v[6] = {wave_sum(cnt.g_upd), wave_sum(cnt.g_touch),
+        const unsigned long long v[8] = {wave_sum(cnt.g_upd), wave_sum(cnt.g_touch),
                                          wave_sum(cnt.c_eval), wave_sum(cnt.c_read),
-                                         wave_sum(cnt.c_upd), wave_sum(cnt.c_touch)};
+                                         wave_sum(cnt.c_upd), wave_sum(cnt.c_touch),
+                                         cnt.g_bricks, cnt.c_bricks};
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
+            for (int q = 0; q < 8; ++q)
                 if (v[q]) atomicAdd(a.counters + q, v[q]);
         }
     }
