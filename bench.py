@@ -7,7 +7,8 @@ Workload (synthetic, seeded): geometry 256^3 + colour 512^3 over a 0.75 m cube, 
 3 spheres and 2 boxes on a plane; trunc = 4 geometry voxels, w_max = 128.
 
 One step = one whole scan: reset the volume, then integrate all 300 frames in passes of
-K frames (each pass one persistent launch replayed from a HIP graph).  The metric counts
+K frames (one call: depth pyramids for all frames, then per pass a culling launch and a
+persistent integration launch).  The metric counts
 every voxel of both volumes once per frame (the swept voxel updates of KinectFusion-style
 integration).  Besides the headline line the JSON carries: the plain frame-by-frame path
 and the fused/plain speedup, forward + backward time of the differentiable form on the
@@ -46,6 +47,30 @@ def default_frames_per_pass() -> int:
         return 8
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kf_integrate.hip", "kf_device.h"):
+        with open(os.path.join(ROOT, "paper_1602_06645_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(K: int):
+    """HBM bytes per launch of the integrate kernel from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs recorded under profiles/ (scaled by the same counters on a plain copy
+    of known size); None when the kernel source or the pass length changed since."""
+    path = os.path.join(ROOT, "profiles", "integrate_kernel_kinect_traffic.txt")
+    try:
+        with open(path) as f:
+            rec = json.loads(f.read().split("JSON:", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("frames_per_pass") != K:
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def pass_scans(kf, fr, K):
     out = []
     for p in range(0, fr.n, K):
@@ -65,6 +90,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="time only the fused scan (for profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -82,6 +110,14 @@ def main() -> int:
         log("no GPU visible")
         return 1
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_dispatch": 4 << 28}), flush=True)
+        return 0
     K = args.frames_per_pass or default_frames_per_pass()
 
     t = time.perf_counter()
@@ -99,34 +135,36 @@ def main() -> int:
     alg_bytes = 16 * int(cnt[1]) + 4 * int(cnt[3]) + 28 * int(cnt[5]) + fr.n * frame_bytes
     log(f"counters {list(map(int, cnt))}; algorithmic bytes per scan {alg_bytes / 1e9:.3f} GB")
 
-    # ---- fused scan: warmup, then the timed steps
-    stream = torch.cuda.current_stream()
+    # ---- fused scan: warmup, then the timed steps.  A step integrates the whole scan in
+    # one call (passes of K frames); HIP events recorded by the library around each
+    # integration launch give the dominant kernel's duration.
+    scan = kf.Scan.from_frames(fr)
+    n_pass = len(passes)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(len(passes) * args.steps)]
+          for _ in range(n_pass * args.steps)]
 
     def scan_step(events=None):
         vol.reset()
-        for q, ps in enumerate(passes):
-            if events is not None:
-                events[q][0].record(stream)
-            kf.integrate_batch([(vol, ps)], frames_per_pass=K, use_graph=True)
-            if events is not None:
-                events[q][1].record(stream)
+        if events is None:
+            kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
+        else:
+            kf.integrate_batch_timed([(vol, scan)], K, events)
 
     for _ in range(args.warmup):
         scan_step()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} scans, K={K}, {len(passes)} passes per scan)")
+    log(f"warmup done ({args.warmup} scans, K={K}, {n_pass} passes per scan)")
     t0 = time.perf_counter()
     for s in range(args.steps):
-        scan_step(ev[s * len(passes):(s + 1) * len(passes)])
+        scan_step(ev[s * n_pass:(s + 1) * n_pass])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
     ms_step = 1e3 * wall / args.steps
     value = n_vox * fr.n * args.steps / wall
     launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, pass {launch_ms:.3f} ms")
+    log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, "
+        f"integrate kernel {launch_ms:.3f} ms per launch")
     per_launch_bytes = alg_bytes / len(passes)
     achieved = per_launch_bytes / (launch_ms * 1e-3) / 1e9
     out = {
@@ -149,8 +187,8 @@ def main() -> int:
                    "trunc_m": fr.trunc, "w_max": fr.w_max, "sigma_m": spec.sigma,
                    "gate": spec.gate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "integrate_kernel (persistent fused pass)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(K),
+                     "kernel": "integrate_kernel<0> (persistent fused pass)",
                      "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
         "counters": {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
                      "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),

@@ -120,16 +120,27 @@ typedef struct {
 
 /*
  * Integrate several independent scans (different volumes, sizes and frame counts).
- * Each voxel keeps its state in registers for frames_per_pass (K >= 1) consecutive
- * frames of its scan, so a voxel's state is read and written once per pass instead of
- * once per frame; all scans advance together in one persistent launch per pass that
- * takes (scan, slab) work items from a queue.  The result equals integrating each scan
- * frame by frame with kf_integrate.  use_graph != 0 records the passes into a HIP graph
- * the first time a given batch (same pointers, sizes and matrices) is seen and replays
- * it afterwards.  The volumes of the batch must be distinct.
+ * Each voxel keeps its state on chip for frames_per_pass (K, 1 <= K; values above 32 act
+ * as 32) consecutive frames of its scan, so a voxel's state is read and written at most
+ * once per pass instead of once per frame; all scans advance together, one pass at a
+ * time: a culling launch lists the (scan, brick) work items that can be updated in some
+ * frame of the pass, and one persistent launch takes them from a queue.  The result
+ * equals integrating each scan frame by frame with kf_integrate.  use_graph != 0 records
+ * the passes into a HIP graph the first time a given batch (same pointers, sizes and
+ * matrices) is seen and replays it afterwards.  The volumes of the batch must be distinct.
  */
 kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
                              int32_t frames_per_pass, int32_t use_graph, void* stream);
+
+/*
+ * kf_integrate_batch (without a graph) that also records start_events[q] and
+ * end_events[q] (hipEvent_t handles created by the caller) on `stream` immediately before
+ * and after the integration launch of pass q, for q < n_events; n_events must be at least
+ * the number of passes.  For measuring the integration kernel alone.
+ */
+kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
+                                   int32_t frames_per_pass, void* const* start_events,
+                                   void* const* end_events, int32_t n_events, void* stream);
 
 /*
  * Byte accounting for kf_integrate_batch with the same arguments: performs the same

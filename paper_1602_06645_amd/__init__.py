@@ -3,5 +3,5 @@ colour volume through a depth-to-HD calibration) from "Creating Simplified 3D Mo
 with High Quality Textures" (arXiv 1602.06645), with batched/fused and differentiable
 forms.  The work runs in libkfvol.so (HIP for gfx950, C ABI in include/kf.h)."""
 from .api import (Scan, Volume, integrate_backward, integrate_batch,  # noqa: F401
-                  integrate_batch_counted, volume_desc)
+                  integrate_batch_counted, integrate_batch_timed, volume_desc)
 from .autograd import KFColourFn, se3_exp, se3_left_jacobian  # noqa: F401

@@ -177,6 +177,19 @@ def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) ->
                                         _stream()))
 
 
+def integrate_batch_timed(pairs, frames_per_pass: int, events) -> None:
+    """integrate_batch that records each (start, end) pair of `events` (torch.cuda.Event,
+    enable_timing=True) around the integration launch of one pass, in order."""
+    for s, e in events:          # torch creates the HIP event on first record
+        s.record()
+        e.record()
+    starts = (C.c_void_p * len(events))(*[s.cuda_event for s, _ in events])
+    ends = (C.c_void_p * len(events))(*[e.cuda_event for _, e in events])
+    arr = _scenes(pairs)
+    L.check(L.load().kf_integrate_batch_timed(arr, len(pairs), int(frames_per_pass), starts,
+                                              ends, len(events), _stream()))
+
+
 def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:
     """Same as integrate_batch, and return the eight accounting counters (include/kf.h)."""
     arr = _scenes(pairs)

@@ -450,10 +450,18 @@ kf_status resident_grid(int mode, uint32_t* grid)
     return KF_OK;
 }
 
+// Caller events recorded around the integration launch of each pass (may be empty).
+struct PassEvents {
+    void* const* start = nullptr;
+    void* const* end = nullptr;
+    int32_t n = 0;
+};
+
 // Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`
 // blocks per persistent launch (resident_grid).
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
-                         unsigned long long* counters, uint32_t grid, hipStream_t stream)
+                         unsigned long long* counters, uint32_t grid, hipStream_t stream,
+                         const PassEvents& ev = PassEvents())
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
@@ -483,7 +491,10 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         a.n_live = cnt + 2 * q;
         a.queue = cnt + 2 * q + 1;
         a.counters = counters;
+        const bool timed = (int32_t)q < ev.n;
+        if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.start[q], stream), "hipEventRecord");
         KF_HIP(kf::launch_integrate(mode, a, grid, stream), "integrate launch");
+        if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.end[q], stream), "hipEventRecord");
     }
     return KF_OK;
 }
@@ -595,7 +606,8 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
 }
 
 kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mode,
-                    unsigned long long* counters, hipStream_t stream)
+                    unsigned long long* counters, hipStream_t stream,
+                    const PassEvents& ev = PassEvents())
 {
     BatchPlan plan;
     kf_status st = plan_batch(scenes, n_scenes, K, &plan);
@@ -609,7 +621,10 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     KF_HIP(hipMallocAsync((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
-    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream);
+    if (st == KF_OK && ev.n > 0 && (size_t)ev.n < plan.passes.size())
+        st = fail(KF_E_ARG, "n_events (%d) is below the number of passes (%zu)", (int)ev.n,
+                  plan.passes.size());
+    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream, ev);
     hipError_t he = hipFreeAsync(dev, stream);
     if (st != KF_OK) return st;
     if (he != hipSuccess) return hip_fail(he, "hipFreeAsync");
@@ -758,6 +773,21 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t f
     }
     return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
                      (hipStream_t)stream);
+}
+
+kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
+                                   int32_t frames_per_pass, void* const* start_events,
+                                   void* const* end_events, int32_t n_events, void* stream)
+{
+    if (n_events < 1 || !start_events || !end_events) return fail(KF_E_ARG, "events missing");
+    for (int32_t q = 0; q < n_events; ++q)
+        if (!start_events[q] || !end_events[q]) return fail(KF_E_ARG, "an event is NULL");
+    PassEvents ev;
+    ev.start = start_events;
+    ev.end = end_events;
+    ev.n = n_events;
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
+                     (hipStream_t)stream, ev);
 }
 
 kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
