@@ -10,14 +10,17 @@
 // chains the sample's spatial derivative through the pinhole projection and the se(3)
 // left perturbation dq/d(rho, phi) = [I | -[q]x].
 //
-// One lane per voxel column of a 64 x 4 x 8 brick (the forward's bricks).  Each voxel
-// first replays the forward decisions of all frames (the same single-precision sequence
-// as the forward kernel, so the same frames update it) and records alpha_n in LDS; a
-// reverse sweep then scatters the image gradient with float atomics and accumulates the
-// extrinsic gradient in double.  Per-block extrinsic partials are summed in a fixed order
-// by a second kernel, so d_xi is deterministic.
+// The colour bricks of the forward (8 x 8 x 8, one wave each) are culled frame by frame
+// exactly like the forward's (a culled frame cannot update any voxel of the brick, so
+// its alpha is 0).  Persistent waves take the live bricks; each voxel replays the forward
+// decisions of its live frames (the same single-precision sequence as the forward, so the
+// same frames update it), keeps alpha_n in an LDS history private to the lane, and a
+// reverse sweep scatters the image gradient with float atomics and accumulates the
+// extrinsic gradient in double.  Each brick writes its own extrinsic partial; a last
+// kernel sums them in a fixed order, so d_xi is deterministic.
 #include <hip/hip_runtime.h>
 
+#include "kf_cull.h"
 #include "kf_device.h"
 #include "kf_launch.h"
 
@@ -26,8 +29,6 @@ namespace kf {
 constexpr int BWD_MAX_FRAMES = 64;
 
 namespace {
-
-__device__ __forceinline__ bool bvalid(float d) { return d > 0.0f && d < __builtin_huge_valf(); }
 
 // Forward decision of one colour voxel for one frame; returns the weight W (> 0) if the
 // frame updates the voxel given the current weight, 0 otherwise.  Same operation
@@ -45,7 +46,7 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     if (!(u >= 0.0f && u <= c.wm1 && v >= 0.0f && v <= c.hm1)) return 0.0f;
     const int pix = (int)v * c.dw + (int)u;
     const float d = c.depth[pix];
-    if (!bvalid(d)) return 0.0f;
+    if (!valid_depth(d)) return 0.0f;
     const float Px = ((u - c.cx) * c.inv_fx) * d;
     const float Py = ((v - c.cy) * c.inv_fy) * d;
     const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
@@ -53,7 +54,7 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     if (!(u + 1.0f <= c.wm1 && v + 1.0f <= c.hm1)) return 0.0f;
     const float d1 = c.depth[pix + 1];
     const float d2 = c.depth[pix + c.dw];
-    if (!bvalid(d1) || !bvalid(d2)) return 0.0f;
+    if (!valid_depth(d1) || !valid_depth(d2)) return 0.0f;
     const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1;
     const float P1y = ((v - c.cy) * c.inv_fy) * d1;
     const float P2x = ((u - c.cx) * c.inv_fx) * d2;
@@ -89,109 +90,143 @@ __device__ __forceinline__ double wave_sum_d(double x)
 
 }  // namespace
 
-__global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
+// One lane per colour brick: the brick's live frames (64-bit mask) for the adjoint.
+__global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
 {
-    extern __shared__ float s_alpha[];   // [n_frames][BLOCK]
-    __shared__ double s_xi[BLOCK / 64][6];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t li = blockIdx.x;
-    const int X = a.cdim[0], Y = a.cdim[1], Z = a.cdim[2];
-    const uint32_t tx = li % (uint32_t)a.ctiles[0];
-    const uint32_t rest = li / (uint32_t)a.ctiles[0];
-    const uint32_t ty = rest % (uint32_t)a.ctiles[1];
-    const uint32_t tz = rest / (uint32_t)a.ctiles[1];
-    const int i = (int)tx * BWD_TX + lane, j = (int)ty * BWD_TY + wave, k0 = (int)tz * ZS;
-    const size_t nvox = (size_t)X * (size_t)Y * (size_t)Z;
-    double xi[6] = {0, 0, 0, 0, 0, 0};
-    float* hist = s_alpha + threadIdx.x;
-
-    if (i < X && j < Y) {
-        const float fi = (float)i, fj = (float)j;
-        const int kn = min(ZS, Z - k0);
-        for (int kk = 0; kk < kn; ++kk) {
-            const int k = k0 + kk;
-            const float fk = (float)k;
-            const size_t idx = ((size_t)k * (size_t)Y + (size_t)j) * (size_t)X + (size_t)i;
-            const float g0 = a.grad[idx], g1 = a.grad[nvox + idx], g2 = a.grad[2 * nvox + idx];
-            if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
-            // forward replay: alpha_n of every frame
-            float Wc = a.wc0 ? a.wc0[idx] : 0.0f;
-            int any = 0;
-            for (int f = 0; f < a.n_frames; ++f) {
-                const float w = colour_weight(a.frames[f], fi, fj, fk, Wc);
-                float alpha = 0.0f;
-                if (w > 0.0f) {
-                    alpha = w / (Wc + w);
-                    Wc = fmaf(w, 1.0f - Wc, Wc);
-                    any = 1;
-                }
-                hist[f * BLOCK] = alpha;
-            }
-            if (!any) continue;
-            // reverse sweep
-            float tail = 1.0f;
-            for (int f = a.n_frames - 1; f >= 0; --f) {
-                const float alpha = hist[f * BLOCK];
-                if (alpha == 0.0f) continue;
-                const float beta = alpha * tail;
-                tail *= 1.0f - alpha;
-                const FrameConsts& c = a.frames[f];
-                const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
-                const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
-                const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-                const float iqz = 1.0f / qz;
-                const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
-                const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
-                const float x0 = floorf(xh), y0 = floorf(yh);
-                const float ax = xh - x0, ay = yh - y0;
-                const int cell = ((int)y0 * c.cw + (int)x0) * 3;
-                const int row = c.cw * 3;
-                const float* img = (const float*)c.rgb;
-                float* dimg = a.d_rgb + (size_t)f * (size_t)c.cw * (size_t)c.ch * 3;
-                const float w00 = (1.0f - ax) * (1.0f - ay), w10 = ax * (1.0f - ay);
-                const float w01 = (1.0f - ax) * ay, w11 = ax * ay;
-                const float gv[3] = {g0, g1, g2};
-                float gx = 0.0f, gy = 0.0f;   // sum_ch g beta ds/dx, ds/dy
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float gb = gv[ch] * beta;
-                    if (gb == 0.0f) continue;
-                    unsafeAtomicAdd(dimg + cell + ch, gb * w00);
-                    unsafeAtomicAdd(dimg + cell + 3 + ch, gb * w10);
-                    unsafeAtomicAdd(dimg + cell + row + ch, gb * w01);
-                    unsafeAtomicAdd(dimg + cell + row + 3 + ch, gb * w11);
-                    const float p00 = img[cell + ch], p10 = img[cell + 3 + ch];
-                    const float p01 = img[cell + row + ch], p11 = img[cell + row + 3 + ch];
-                    gx = fmaf(gb, (1.0f - ay) * (p10 - p00) + ay * (p11 - p01), gx);
-                    gy = fmaf(gb, (1.0f - ax) * (p01 - p00) + ax * (p11 - p10), gy);
-                }
-                // pinhole Jacobian of Eq. 4 after the division by z
-                const double dqx = (double)gx * c.fxr * iqz;
-                const double dqy = (double)gy * c.fyr * iqz;
-                const double dqz = -((double)gx * c.fxr * qx + (double)gy * c.fyr * qy) * iqz * iqz;
-                xi[0] += dqx;
-                xi[1] += dqy;
-                xi[2] += dqz;
-                xi[3] += (double)qy * dqz - (double)qz * dqy;
-                xi[4] += (double)qz * dqx - (double)qx * dqz;
-                xi[5] += (double)qx * dqy - (double)qy * dqx;
-            }
-        }
+    const uint32_t li = blockIdx.x * BLOCK + threadIdx.x;
+    unsigned long long mask = 0;
+    if (li < a.n_items) {
+        const int bx = (int)(li % (uint32_t)a.cbricks[0]);
+        const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
+        const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
+        const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
+        const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
+        const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
+        for (int f = 0; f < a.n_frames; ++f)
+            if (a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1))
+                mask |= 1ull << f;
     }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double s = wave_sum_d(xi[q]);
-        if (lane == 0) s_xi[wave][q] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / 64; ++w) s += s_xi[w][threadIdx.x];
-        a.partials[(size_t)blockIdx.x * 6 + threadIdx.x] = s;
+    const unsigned long long live = __ballot(mask != 0);
+    if (live == 0) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(a.n_live, (uint32_t)__popcll(live));
+    base = __shfl(base, 0, WAVE);
+    if (mask) {
+        const uint32_t rank = (uint32_t)__popcll(live & ((1ull << lane) - 1ull));
+        a.live[base + rank] = make_uint4(li, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
     }
 }
 
-// Sum the per-block partials in a fixed order: lane t of component q adds blocks
+// HIST: LDS floats per lane for the alpha history (at least the frames of the call).
+template <int HIST>
+__global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
+{
+    __shared__ float s_alpha[BLOCK * HIST];   // lane t of wave w: [w][f][t]
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    float* hist = s_alpha + wave * WAVE * HIST + lane;
+    const size_t nvox = (size_t)a.cdim[0] * (size_t)a.cdim[1] * (size_t)a.cdim[2];
+    const uint32_t n_live = *a.n_live;
+    for (;;) {
+        uint32_t e = 0;
+        if (lane == 0) e = atomicAdd(a.queue, 1u);
+        e = __builtin_amdgcn_readfirstlane(e);
+        if (e >= n_live) break;
+        const uint4 ent = a.live[e];
+        const uint32_t li = __builtin_amdgcn_readfirstlane(ent.x);
+        const unsigned long long mask =
+            ((unsigned long long)__builtin_amdgcn_readfirstlane(ent.z) << 32) |
+            __builtin_amdgcn_readfirstlane(ent.y);
+        const int bx = (int)(li % (uint32_t)a.cbricks[0]);
+        const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
+        const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
+        const int i = bx * CBX + lane % CBX, j = by * CBY + lane / CBX, k0 = bz * ZS;
+        double xi[6] = {0, 0, 0, 0, 0, 0};
+        if (i < a.cdim[0] && j < a.cdim[1]) {
+            const float fi = (float)i, fj = (float)j;
+            const int kn = min(ZS, a.cdim[2] - k0);
+            for (int kk = 0; kk < kn; ++kk) {
+                const int k = k0 + kk;
+                const float fk = (float)k;
+                const size_t idx = ((size_t)k * (size_t)a.cdim[1] + (size_t)j) * (size_t)a.cdim[0] + (size_t)i;
+                const float g0 = a.grad[idx], g1 = a.grad[nvox + idx], g2 = a.grad[2 * nvox + idx];
+                if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
+                // forward replay over the live frames: alpha_n, by rank among them
+                float Wc = a.wc0 ? a.wc0[idx] : 0.0f;
+                int any = 0, r = 0;
+                for (unsigned long long m = mask; m; m &= m - 1, ++r) {
+                    const float w = colour_weight(a.frames[__builtin_ctzll(m)], fi, fj, fk, Wc);
+                    float alpha = 0.0f;
+                    if (w > 0.0f) {
+                        alpha = w / (Wc + w);
+                        Wc = fmaf(w, 1.0f - Wc, Wc);
+                        any = 1;
+                    }
+                    hist[r * WAVE] = alpha;
+                }
+                if (!any) continue;
+                // reverse sweep
+                float tail = 1.0f;
+                for (unsigned long long m = mask; m; m &= ~(1ull << (63 - __builtin_clzll(m)))) {
+                    const int f = 63 - __builtin_clzll(m);
+                    --r;
+                    const float alpha = hist[r * WAVE];
+                    if (alpha == 0.0f) continue;
+                    const float beta = alpha * tail;
+                    tail *= 1.0f - alpha;
+                    const FrameConsts& c = a.frames[f];
+                    const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
+                    const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
+                    const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
+                    const float iqz = 1.0f / qz;
+                    const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
+                    const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
+                    const float x0 = floorf(xh), y0 = floorf(yh);
+                    const float ax = xh - x0, ay = yh - y0;
+                    const int cell = ((int)y0 * c.cw + (int)x0) * 3;
+                    const int row = c.cw * 3;
+                    const float* img = (const float*)c.rgb;
+                    float* dimg = a.d_rgb + (size_t)f * (size_t)c.cw * (size_t)c.ch * 3;
+                    const float w00 = (1.0f - ax) * (1.0f - ay), w10 = ax * (1.0f - ay);
+                    const float w01 = (1.0f - ax) * ay, w11 = ax * ay;
+                    const float gv[3] = {g0, g1, g2};
+                    float gx = 0.0f, gy = 0.0f;   // sum_ch g beta ds/dx, ds/dy
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const float gb = gv[ch] * beta;
+                        if (gb == 0.0f) continue;
+                        unsafeAtomicAdd(dimg + cell + ch, gb * w00);
+                        unsafeAtomicAdd(dimg + cell + 3 + ch, gb * w10);
+                        unsafeAtomicAdd(dimg + cell + row + ch, gb * w01);
+                        unsafeAtomicAdd(dimg + cell + row + 3 + ch, gb * w11);
+                        const float p00 = img[cell + ch], p10 = img[cell + 3 + ch];
+                        const float p01 = img[cell + row + ch], p11 = img[cell + row + 3 + ch];
+                        gx = fmaf(gb, (1.0f - ay) * (p10 - p00) + ay * (p11 - p01), gx);
+                        gy = fmaf(gb, (1.0f - ax) * (p01 - p00) + ax * (p11 - p10), gy);
+                    }
+                    // pinhole Jacobian of Eq. 4 after the division by z
+                    const double dqx = (double)gx * c.fxr * iqz;
+                    const double dqy = (double)gy * c.fyr * iqz;
+                    const double dqz = -((double)gx * c.fxr * qx + (double)gy * c.fyr * qy) * iqz * iqz;
+                    xi[0] += dqx;
+                    xi[1] += dqy;
+                    xi[2] += dqz;
+                    xi[3] += (double)qy * dqz - (double)qz * dqy;
+                    xi[4] += (double)qz * dqx - (double)qx * dqz;
+                    xi[5] += (double)qx * dqy - (double)qy * dqx;
+                }
+            }
+        }
+        // the brick's extrinsic partial (a fixed butterfly order: deterministic)
+        const double s0 = wave_sum_d(xi[0]), s1 = wave_sum_d(xi[1]), s2 = wave_sum_d(xi[2]);
+        const double s3 = wave_sum_d(xi[3]), s4 = wave_sum_d(xi[4]), s5 = wave_sum_d(xi[5]);
+        if (lane == 0) {
+            double* out = a.partials + (size_t)li * 6;
+            out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3; out[4] = s4; out[5] = s5;
+        }
+    }
+}
+
+// Sum the per-brick partials in a fixed order: lane t of component q adds bricks
 // t, t+256, ...; then a fixed tree over the 256 lanes.
 __global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, uint32_t n, double* out)
 {
@@ -210,23 +245,29 @@ __global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, 
     }
 }
 
-uint32_t backward_blocks(const BackwardArgs& a) { return a.n_items; }
+template <int HIST>
+static hipError_t launch_backward_hist(const BackwardArgs& a, int device, hipStream_t stream)
+{
+    int n_cu = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_kernel<HIST>, BLOCK, 0);
+    if (e != hipSuccess) return e;
+    const unsigned grid = (unsigned)(n_cu * (per_cu > 0 ? per_cu : 1));
+    hipLaunchKernelGGL(backward_kernel<HIST>, dim3(grid), dim3(BLOCK), 0, stream, a);
+    return hipGetLastError();
+}
 
-hipError_t launch_backward(const BackwardArgs& a, double* d_xi, hipStream_t stream)
+hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipStream_t stream)
 {
     if (a.n_frames > BWD_MAX_FRAMES) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(a.n_frames > 0 ? a.n_frames : 1) * BLOCK * sizeof(float);
-    static bool lds_raised = false;
-    if (!lds_raised) {
-        const hipError_t e = hipFuncSetAttribute((const void*)backward_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)(BWD_MAX_FRAMES * BLOCK * sizeof(float)));
-        if (e != hipSuccess) return e;
-        lds_raised = true;
-    }
     if (a.n_items > 0) {
-        hipLaunchKernelGGL(backward_kernel, dim3(a.n_items), dim3(BLOCK), lds, stream, a);
+        hipLaunchKernelGGL(backward_cull_kernel, dim3((a.n_items + BLOCK - 1) / BLOCK), dim3(BLOCK),
+                           0, stream, a);
         hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = a.n_frames <= 32 ? launch_backward_hist<32>(a, device, stream)
+                             : launch_backward_hist<64>(a, device, stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(reduce_xi_kernel, dim3(1), dim3(256), 0, stream, a.partials, a.n_items, d_xi);

@@ -613,6 +613,9 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     kf_status st = plan_batch(scenes, n_scenes, K, &plan);
     if (st != KF_OK) return st;
     if (plan.passes.empty()) return KF_OK;
+    if (ev.n > 0 && (size_t)ev.n < plan.passes.size())
+        return fail(KF_E_ARG, "n_events (%d) is below the number of passes (%zu)", (int)ev.n,
+                    plan.passes.size());
     DeviceTables t;
     layout_tables(plan, &t);
     uint32_t grid = 0;
@@ -621,9 +624,6 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     KF_HIP(hipMallocAsync((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
-    if (st == KF_OK && ev.n > 0 && (size_t)ev.n < plan.passes.size())
-        st = fail(KF_E_ARG, "n_events (%d) is below the number of passes (%zu)", (int)ev.n,
-                  plan.passes.size());
     if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream, ev);
     hipError_t he = hipFreeAsync(dev, stream);
     if (st != KF_OK) return st;
@@ -826,34 +826,62 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     kf::BackwardArgs a;
     memset(&a, 0, sizeof a);
     for (int q = 0; q < 3; ++q) a.cdim[q] = desc->colour_dim[q];
-    a.ctiles[0] = (int32_t)ceil_div(a.cdim[0], kf::BWD_TX);
-    a.ctiles[1] = (int32_t)ceil_div(a.cdim[1], kf::BWD_TY);
-    a.ctiles[2] = (int32_t)ceil_div(a.cdim[2], kf::ZS);
-    a.n_items = (uint32_t)a.ctiles[0] * (uint32_t)a.ctiles[1] * (uint32_t)a.ctiles[2];
+    a.cbricks[0] = (int32_t)ceil_div(a.cdim[0], kf::CBX);
+    a.cbricks[1] = (int32_t)ceil_div(a.cdim[1], kf::CBY);
+    a.cbricks[2] = (int32_t)ceil_div(a.cdim[2], kf::ZS);
+    a.n_items = n_frames > 0 ? (uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1] * (uint32_t)a.cbricks[2] : 0u;
     a.n_frames = n_frames;
+    a.disable_cull = cull_disabled() ? 1 : 0;
     a.wc0 = w_col0;
     a.grad = grad_rgb_vol;
     a.d_rgb = d_rgb;
+    // workspace: [frames][n_live, queue][live list][partials][pyramids]
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     std::vector<kf::FrameConsts> fc((size_t)(n_frames > 0 ? n_frames : 1));
+    memset(fc.data(), 0, fc.size() * sizeof(kf::FrameConsts));
     const size_t dpix = (size_t)dw * dh, cvals = (size_t)cw * ch * 3;
     for (int f = 0; f < n_frames; ++f)
         frame_consts(*desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam + 16 * (size_t)f, 1.0, 1.0,
                      depth + dpix * f, dw, dh, rgb_f32 + cvals * f, cw, ch, &fc[f]);
-    const size_t fbytes = fc.size() * sizeof(kf::FrameConsts);
-    const size_t pbytes = (size_t)(a.n_items > 0 ? a.n_items : 1) * 6 * sizeof(double);
+    const size_t frames_off = 0;
+    const size_t counters_off = align(frames_off + fc.size() * sizeof(kf::FrameConsts));
+    const size_t live_off = align(counters_off + 2 * sizeof(uint32_t));
+    const size_t partials_off = align(live_off + (size_t)a.n_items * sizeof(uint4));
+    const size_t pyr_off = align(partials_off + (size_t)(a.n_items > 0 ? a.n_items : 1) * 6 * sizeof(double));
+    size_t off = pyr_off;
+    int32_t max_tiles0 = 0;
+    std::vector<size_t> pyr(fc.size(), 0);
+    for (int f = 0; f < n_frames; ++f) {
+        pyr[f] = off;
+        off += pyramid_entries(fc[f]) * sizeof(float2);
+        const int32_t tiles = fc[f].pyr_w0 * fc[f].pyr_h0;
+        max_tiles0 = tiles > max_tiles0 ? tiles : max_tiles0;
+    }
+    const size_t bytes = align(off);
     unsigned char* ws = nullptr;
-    KF_HIP(hipMallocAsync((void**)&ws, fbytes + pbytes, st), "hipMallocAsync");
-    a.frames = (const kf::FrameConsts*)ws;
-    a.partials = (double*)(ws + fbytes);
-    s = staged_copy(ws, fc.data(), fbytes, st);
+    KF_HIP(hipMallocAsync((void**)&ws, bytes, st), "hipMallocAsync");
+    for (int f = 0; f < n_frames; ++f) fc[f].pyr = (float2*)(ws + pyr[f]);
+    a.frames = (const kf::FrameConsts*)(ws + frames_off);
+    a.n_live = (uint32_t*)(ws + counters_off);
+    a.queue = a.n_live + 1;
+    a.live = (uint4*)(ws + live_off);
+    a.partials = (double*)(ws + partials_off);
+    s = staged_copy(ws + frames_off, fc.data(), fc.size() * sizeof(kf::FrameConsts), st);
+    hipError_t e = hipSuccess;
+    const char* what = nullptr;
     if (s == KF_OK && n_frames > 0) {
-        hipError_t e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st);
-        if (e != hipSuccess) s = hip_fail(e, "gradient reset");
+        if ((e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st)) != hipSuccess) what = "gradient reset";
+        else if ((e = kf::launch_fill_u32((uint32_t*)(ws + counters_off), 2, 0u, st)) != hipSuccess) what = "counter reset";
+        else if ((e = kf::launch_fill_u32((uint32_t*)a.partials, (size_t)a.n_items * 12, 0u, st)) != hipSuccess)
+            what = "partial reset";
+        else if ((e = kf::launch_pyramids(a.frames, n_frames, max_tiles0, st)) != hipSuccess) what = "pyramid launch";
     }
-    if (s == KF_OK) {
-        hipError_t e = kf::launch_backward(a, d_xi, st);
-        if (e != hipSuccess) s = hip_fail(e, "backward launch");
+    if (s == KF_OK && !what) {
+        int device = 0;
+        if ((e = hipGetDevice(&device)) != hipSuccess) what = "hipGetDevice";
+        else if ((e = kf::launch_backward(a, d_xi, device, st)) != hipSuccess) what = "backward launch";
     }
+    if (s == KF_OK && what) s = hip_fail(e, what);
     hipError_t fe = hipFreeAsync(ws, st);
     if (s != KF_OK) return s;
     if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");

@@ -18,7 +18,6 @@ constexpr int CBX = 8, CBY = 8;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
 constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
-constexpr int BWD_TX = 64, BWD_TY = 4;  // adjoint: a block covers 64 x 4 colour columns
 
 // Everything one frame contributes to the per-voxel arithmetic, rounded once from the
 // double-precision values computed on the host.
@@ -83,16 +82,22 @@ struct CullArgs {
     uint32_t* n_live;
 };
 
+// The adjoint over up to 64 frames: colour bricks culled like the forward's, then
+// persistent waves over the live list.
 struct BackwardArgs {
     int32_t cdim[3];
-    int32_t ctiles[3];
-    uint32_t n_items;
-    int32_t n_frames;
-    const FrameConsts* frames;        // [n_frames]
+    int32_t cbricks[3];
+    uint32_t n_items;                 // colour bricks
+    int32_t n_frames;                 // <= 64
+    int32_t disable_cull;             // 1: every brick is live in every frame
+    const FrameConsts* frames;        // [n_frames], with their depth pyramids
     const float* wc0;                 // initial colour weights or NULL
     const float* grad;                // [3][Nc]
     float* d_rgb;                     // [n][ch][cw][3]
-    double* partials;                 // [gridDim][6]
+    double* partials;                 // [n_items][6]; zero for bricks never live
+    uint4* live;                      // (brick, frame mask low, frame mask high, 0)
+    uint32_t* n_live;
+    uint32_t* queue;
 };
 
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.

@@ -19,17 +19,13 @@
 // The library is compiled with -ffp-contract=off, so nothing else is fused.
 #include <hip/hip_runtime.h>
 
+#include "kf_cull.h"
 #include "kf_device.h"
 #include "kf_launch.h"
 
 namespace kf {
 
 namespace {
-
-__device__ __forceinline__ bool valid_depth(float d)
-{
-    return d > 0.0f && d < __builtin_huge_valf();
-}
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
@@ -287,7 +283,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
                 const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
                 const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
-                if (has_nb & valid_depth(d1) & valid_depth(d2) & (nn > 0.0f)) {
+                if ((int)has_nb & (int)valid_depth(d1) & (int)valid_depth(d2) & (int)(nn > 0.0f)) {
                     // W: unit normal . unit viewing direction (camera -> P).
                     const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
                     const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
@@ -372,88 +368,6 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
-}
-
-// --------------------------------------------------------------------------- culling
-
-// Valid-depth (min, max) over pixels [u0,u1] x [v0,v1] (inclusive, inside the image),
-// read from the finest pyramid level on which the box spans at most 4 x 4 tiles.  The
-// tiles cover the box, so the range contains every depth inside it.
-__device__ float2 depth_range(const FrameConsts& c, int u0, int u1, int v0, int v1)
-{
-    int w = c.pyr_w0, h = c.pyr_h0, off = 0, s = PYR_SHIFT;
-    for (int l = 0; l < c.pyr_levels; ++l) {
-        const int tx0 = u0 >> s, tx1 = u1 >> s, ty0 = v0 >> s, ty1 = v1 >> s;
-        if ((tx1 - tx0 <= 3 && ty1 - ty0 <= 3) || l == c.pyr_levels - 1) {
-            float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    const float2 r = c.pyr[off + ty * w + tx];
-                    dmin = fminf(dmin, r.x);
-                    dmax = fmaxf(dmax, r.y);
-                }
-            return make_float2(dmin, dmax);
-        }
-        off += w * h;
-        w = (w + 1) / 2;
-        h = (h + 1) / 2;
-        ++s;
-    }
-    return make_float2(__builtin_huge_valf(), -__builtin_huge_valf());
-}
-
-// Can any voxel of the index box [i0,i1] x [j0,j1] x [k0,k1] pass the depth tests of this
-// frame?  Its voxel centres form a parallelepiped (Eq. 5 is affine in the index), so
-// their depths lie between the corners' and, when all corners are in front of the
-// camera, their projections lie in the corners' bounding box (widened by a pixel for
-// rounding).  A colour voxel needs a depth within sigma of its own z (|p - P| >= |z - d|);
-// a geometry voxel needs a depth no more than trunc in front of it.  1 mm of slack covers
-// the single-precision rounding of z and d.
-__device__ bool brick_live(const FrameConsts& c, bool colour, int i0, int i1, int j0, int j1,
-                           int k0, int k1)
-{
-    const float* A = colour ? c.Ac : c.Ag;
-    const float* b = colour ? c.bc : c.bg;
-    float zmin = __builtin_huge_valf(), zmax = -__builtin_huge_valf();
-    float xmin = __builtin_huge_valf(), xmax = -__builtin_huge_valf();
-    float ymin = __builtin_huge_valf(), ymax = -__builtin_huge_valf();
-    bool near = false;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float fi = (float)((q & 1) ? i1 : i0);
-        const float fj = (float)((q & 2) ? j1 : j0);
-        const float fk = (float)((q & 4) ? k1 : k0);
-        const float X = fmaf(A[2], fk, fmaf(A[1], fj, fmaf(A[0], fi, b[0])));
-        const float Y = fmaf(A[5], fk, fmaf(A[4], fj, fmaf(A[3], fi, b[1])));
-        const float Z = fmaf(A[8], fk, fmaf(A[7], fj, fmaf(A[6], fi, b[2])));
-        zmin = fminf(zmin, Z);
-        zmax = fmaxf(zmax, Z);
-        if (Z > 1e-3f) {
-            const float x = c.fx * (X / Z) + c.cx, y = c.fy * (Y / Z) + c.cy;
-            xmin = fminf(xmin, x);
-            xmax = fmaxf(xmax, x);
-            ymin = fminf(ymin, y);
-            ymax = fmaxf(ymax, y);
-        } else {
-            near = true;
-        }
-    }
-    if (!(zmax > -1e-4f)) return false;                  // entirely behind the camera
-    int u0 = 0, u1 = c.dw - 1, v0 = 0, v1 = c.dh - 1;
-    if (!near) {
-        const float fu0 = floorf(xmin) - 1.0f, fu1 = ceilf(xmax) + 1.0f;
-        const float fv0 = floorf(ymin) - 1.0f, fv1 = ceilf(ymax) + 1.0f;
-        if (fu1 < 0.0f || fu0 > c.wm1 || fv1 < 0.0f || fv0 > c.hm1) return false;
-        u0 = (int)fmaxf(fu0, 0.0f);
-        u1 = (int)fminf(fu1, c.wm1);
-        v0 = (int)fmaxf(fv0, 0.0f);
-        v1 = (int)fminf(fv1, c.hm1);
-    }
-    const float2 r = depth_range(c, u0, u1, v0, v1);
-    if (!(r.x <= r.y)) return false;                      // no measurement in the footprint
-    const float slack = 1e-3f;
-    if (colour) return r.x <= zmax + c.sigma + slack && r.y >= zmin - c.sigma - slack;
-    return zmin <= r.y + c.trunc + slack;
 }
 
 }  // namespace

@@ -145,6 +145,36 @@ def test_batch_rejects_bad_arguments():
         lib.kf_volume_destroy(h)
 
 
+def test_timed_batch_rejects_bad_arguments():
+    """Event arrays are checked, and too few events for the passes is an argument error
+    returned before any device work (the volume buffers here are fake addresses)."""
+    lib = L.load()
+    h = _volume()
+    try:
+        K = np.array([[525.0, 0, 319.5], [0, 525.0, 239.5], [0, 0, 1]])
+        Kr = np.array([[1050.0, 0, 959.5], [0, 1050.0, 539.5], [0, 0, 1]])
+        T = np.eye(4)
+        poses = np.stack([np.eye(4)] * 3)
+        sc = (L.Scene * 1)()
+        sc[0].vol = h.value
+        sc[0].n_frames = 3
+        sc[0].depth, sc[0].rgb, sc[0].fmt = 0x2000, 0x3000, L.KF_RGB8
+        sc[0].dw, sc[0].dh, sc[0].cw, sc[0].ch = 640, 480, 1920, 1080
+        sc[0].K_d, sc[0].K_rgb = K.ctypes.data, Kr.ctypes.data
+        sc[0].T_rgb_from_d, sc[0].T_world_from_cam = T.ctypes.data, poses.ctypes.data
+        sc[0].trunc_m, sc[0].w_max = 0.01, 128.0
+        ev = (C.c_void_p * 3)(0x10, 0x20, 0x30)
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, 0, None) == L.KF_E_ARG
+        holey = (C.c_void_p * 3)(0x10, None, 0x30)
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, holey, 3, None) == L.KF_E_ARG
+        # K = 1 makes three passes; two events are too few
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, 2, None) == L.KF_E_ARG
+        assert b"below the number of passes" in lib.kf_last_error()
+    finally:
+        lib.kf_volume_destroy(h)
+
+
 def test_backward_rejects_bad_arguments():
     lib = L.load()
     d = _desc()
