@@ -53,7 +53,9 @@ typedef enum {
 
 /* Volume description.  Both volumes cover the same axis-aligned box (Sec. IV.B: the
  * colour volume has a higher dimension but the same size); voxel (i,j,k) has its centre
- * at origin + (i+1/2, j+1/2, k+1/2) * extent / dim; storage is x fastest. */
+ * at origin + (i+1/2, j+1/2, k+1/2) * extent / dim; storage is x fastest.  Limits
+ * (KF_E_RANGE beyond them): at most 65536 voxels per axis, 2^31-1 per volume and fewer
+ * than 2^26 per z slice (dim x * dim y). */
 typedef struct {
     int32_t geom_dim[3];    /* geometry voxels per axis (x, y, z), each >= 1             */
     int32_t colour_dim[3];  /* colour voxels per axis, each >= 1                          */
@@ -88,8 +90,9 @@ void kf_volume_destroy(kf_volume* vol);
 
 /*
  * Integrate one frame (Sec. III and Sec. IV.B).
- *   depth: [dh][dw] float32 metres; 0, negative, NaN or infinite = no measurement.
- *   rgb:   [ch][cw][3] in `fmt`; cw, ch >= 2.
+ *   depth: [dh][dw] float32 metres; 0, negative, NaN or infinite = no measurement;
+ *          dw, dh <= 65535 and dw * dh < 2^29 - 4 (KF_E_RANGE otherwise).
+ *   rgb:   [ch][cw][3] in `fmt`; cw, ch >= 2; cw * ch * 3 < 2^31.
  *   K_d, K_rgb: 3x3 intrinsics (K_c, K_hd of Eq. 1-4), zero skew, last row (0,0,1),
  *          positive focal lengths.
  *   T_rgb_from_d: 4x4 rigid transform (R_calib, t_calib) of Eq. 3.
@@ -124,7 +127,8 @@ typedef struct {
  * as 32) consecutive frames of its scan, so a voxel's state is read and written at most
  * once per pass instead of once per frame; all scans advance together, one pass at a
  * time: a culling launch lists the (scan, brick) work items that can be updated in some
- * frame of the pass, and one persistent launch takes them from a queue.  The result
+ * frame of the pass, and two persistent launches (geometry bricks, then colour bricks)
+ * take them from queues.  The result
  * equals integrating each scan frame by frame with kf_integrate.  use_graph != 0 records
  * the passes into a HIP graph the first time a given batch (same pointers, sizes and
  * matrices) is seen and replays it afterwards.  The volumes of the batch must be distinct.
@@ -135,8 +139,9 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
 /*
  * kf_integrate_batch (without a graph) that also records start_events[q] and
  * end_events[q] (hipEvent_t handles created by the caller) on `stream` immediately before
- * and after the integration launch of pass q, for q < n_events; n_events must be at least
- * the number of passes.  For measuring the integration kernel alone.
+ * the geometry and after the colour integration launch of pass q, for q < n_events;
+ * n_events must be at least the number of passes.  For measuring the integration kernels
+ * alone.
  */
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
                                    int32_t frames_per_pass, void* const* start_events,

@@ -14,6 +14,9 @@ SOURCES = ["kf_integrate.hip", "kf_backward.hip", "kf_capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-ffp-contract=off", "-fno-fast-math", "-fhip-fp32-correctly-rounded-divide-sqrt",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # wave-wide atomics (queue tickets, list appends) are combined with a DPP prefix
+         # sum rather than a loop over the active lanes
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
          "-Wall", "-Wno-unused-command-line-argument"]
 
 

@@ -106,16 +106,10 @@ __global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
             if (a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1))
                 mask |= 1ull << f;
     }
-    const unsigned long long live = __ballot(mask != 0);
-    if (live == 0) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(a.n_live, (uint32_t)__popcll(live));
-    base = __shfl(base, 0, WAVE);
-    if (mask) {
-        const uint32_t rank = (uint32_t)__popcll(live & ((1ull << lane) - 1ull));
-        a.live[base + rank] = make_uint4(li, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
-    }
+    // every lane takes part in the atomic (adding 0 or 1): one atomic per wave and a
+    // prefix sum after the compiler's combining
+    const uint32_t pos = atomicAdd(a.n_live, mask != 0 ? 1u : 0u);
+    if (mask) a.live[pos] = make_uint4(li, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
 }
 
 // HIST: LDS floats per lane for the alpha history (at least the frames of the call).
@@ -128,15 +122,12 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
     const size_t nvox = (size_t)a.cdim[0] * (size_t)a.cdim[1] * (size_t)a.cdim[2];
     const uint32_t n_live = *a.n_live;
     for (;;) {
-        uint32_t e = 0;
-        if (lane == 0) e = atomicAdd(a.queue, 1u);
-        e = __builtin_amdgcn_readfirstlane(e);
+        const uint32_t e = wave_ticket(a.queue);
         if (e >= n_live) break;
         const uint4 ent = a.live[e];
-        const uint32_t li = __builtin_amdgcn_readfirstlane(ent.x);
-        const unsigned long long mask =
-            ((unsigned long long)__builtin_amdgcn_readfirstlane(ent.z) << 32) |
-            __builtin_amdgcn_readfirstlane(ent.y);
+        const uint32_t li = first_lane_u32(ent.x);
+        const unsigned long long mask = ((unsigned long long)first_lane_u32(ent.z) << 32) |
+                                        (unsigned long long)first_lane_u32(ent.y);
         const int bx = (int)(li % (uint32_t)a.cbricks[0]);
         const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
         const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
@@ -219,10 +210,11 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
         // the brick's extrinsic partial (a fixed butterfly order: deterministic)
         const double s0 = wave_sum_d(xi[0]), s1 = wave_sum_d(xi[1]), s2 = wave_sum_d(xi[2]);
         const double s3 = wave_sum_d(xi[3]), s4 = wave_sum_d(xi[4]), s5 = wave_sum_d(xi[5]);
-        if (lane == 0) {
-            double* out = a.partials + (size_t)li * 6;
-            out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3; out[4] = s4; out[5] = s5;
-        }
+        // every lane stores component lane % 6 (the values are the same in every lane), so
+        // nothing in the loop depends on the lane index
+        const int q = lane % 6;
+        const double sq = q == 0 ? s0 : q == 1 ? s1 : q == 2 ? s2 : q == 3 ? s3 : q == 4 ? s4 : s5;
+        a.partials[(size_t)li * 6 + q] = sq;
     }
 }
 

@@ -97,6 +97,9 @@ kf_status check_desc(const kf_volume_desc* d)
     const double nc = (double)d->colour_dim[0] * d->colour_dim[1] * d->colour_dim[2];
     if (ng > 2147483647.0 || nc > 2147483647.0)
         return fail(KF_E_RANGE, "a volume holds more than 2^31-1 voxels");
+    if ((double)d->geom_dim[0] * d->geom_dim[1] >= 67108864.0 ||
+        (double)d->colour_dim[0] * d->colour_dim[1] >= 67108864.0)
+        return fail(KF_E_RANGE, "a z slice holds 2^26 voxels or more");
     if (!isfinite(d->colour_band) || !(d->colour_band > 0.0))
         return fail(KF_E_ARG, "colour_band must be finite and > 0");
     if (!isfinite(d->colour_gate) || d->colour_gate < 0.0)
@@ -109,7 +112,8 @@ kf_status check_images(const float* depth, int32_t dw, int32_t dh, const void* r
 {
     if (dw < 1 || dh < 1) return fail(KF_E_SHAPE, "depth image must be at least 1x1");
     if (cw < 2 || ch < 2) return fail(KF_E_SHAPE, "HD image must be at least 2x2");
-    if ((double)dw * dh > 2147483647.0 || (double)cw * ch * 3.0 > 2147483647.0)
+    if (dw > 65535 || dh > 65535 || (double)dw * dh * 4.0 >= 2147483632.0 ||
+        (double)cw * ch * 3.0 > 2147483647.0)
         return fail(KF_E_RANGE, "image too large");
     if (fmt != KF_RGB8 && fmt != KF_RGBF32) return fail(KF_E_ARG, "unknown pixel format");
     if (!depth || !rgb) return fail(KF_E_ARG, "image pointer is NULL");
@@ -394,7 +398,8 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
 }
 
 // Device image of a plan:
-//   [frame table][scene table of each pass][n_live, queue per pass][live list][pyramids]
+//   [frame table][scene table of each pass][4 counters per pass: live entries and queue
+//   heads of each kind][live list][pyramids]
 struct DeviceTables {
     std::vector<unsigned char> host;
     size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
@@ -413,7 +418,7 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
         off = align(off + pass.size() * sizeof(kf::SceneDev));
     }
     t->counters_off = off;
-    off = align(off + 2 * (p.passes.size() + 1) * sizeof(uint32_t));
+    off = align(off + 4 * (p.passes.size() + 1) * sizeof(uint32_t));
     uint32_t max_items = 0;
     for (uint32_t n : p.pass_items) max_items = n > max_items ? n : max_items;
     t->live_off = off;
@@ -442,11 +447,13 @@ void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
             memcpy(t->host.data() + t->pass_off[q], p.passes[q].data(), p.passes[q].size() * sizeof(kf::SceneDev));
 }
 
-kf_status resident_grid(int mode, uint32_t* grid)
+// Resident blocks of the geometry ([0]) and colour ([1]) persistent launches.
+kf_status resident_grid(int mode, uint32_t grid[2])
 {
     int device = 0;
     KF_HIP(hipGetDevice(&device), "hipGetDevice");
-    KF_HIP(kf::persistent_grid(mode, device, grid), "occupancy query");
+    KF_HIP(kf::persistent_grid(mode, kf::KIND_GEOM, device, &grid[0]), "occupancy query");
+    KF_HIP(kf::persistent_grid(mode, kf::KIND_COLOUR, device, &grid[1]), "occupancy query");
     return KF_OK;
 }
 
@@ -457,16 +464,16 @@ struct PassEvents {
     int32_t n = 0;
 };
 
-// Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`
-// blocks per persistent launch (resident_grid).
+// Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`:
+// blocks of the geometry and colour persistent launches (resident_grid).
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
-                         unsigned long long* counters, uint32_t grid, hipStream_t stream,
+                         unsigned long long* counters, const uint32_t grid[2], hipStream_t stream,
                          const PassEvents& ev = PassEvents())
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
-    KF_HIP(kf::launch_fill_u32(cnt, 2 * (p.passes.size() + 1), 0u, stream), "counter reset");
+    KF_HIP(kf::launch_fill_u32(cnt, 4 * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint2* live = (uint2*)(dev + t.live_off);
     const int disable = cull_disabled() ? 1 : 0;
     for (size_t q = 0; q < p.passes.size(); ++q) {
@@ -480,7 +487,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         c.n_items = p.pass_items[q];
         c.disable = disable;
         c.live = live;
-        c.n_live = cnt + 2 * q;
+        c.n_live = cnt + 4 * q;
         KF_HIP(kf::launch_cull(c, stream), "cull launch");
         kf::IntegrateArgs a;
         memset(&a, 0, sizeof a);
@@ -488,12 +495,14 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         a.frames = frames;
         a.n_scenes = c.n_scenes;
         a.live = live;
-        a.n_live = cnt + 2 * q;
-        a.queue = cnt + 2 * q + 1;
+        a.cap = c.n_items;
+        a.n_live = cnt + 4 * q;
+        a.queue = cnt + 4 * q + 2;
         a.counters = counters;
         const bool timed = (int32_t)q < ev.n;
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.start[q], stream), "hipEventRecord");
-        KF_HIP(kf::launch_integrate(mode, a, grid, stream), "integrate launch");
+        KF_HIP(kf::launch_integrate(mode, kf::KIND_GEOM, a, grid[0], stream), "integrate launch");
+        KF_HIP(kf::launch_integrate(mode, kf::KIND_COLOUR, a, grid[1], stream), "integrate launch");
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.end[q], stream), "hipEventRecord");
     }
     return KF_OK;
@@ -578,8 +587,8 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
     fill_tables(plan, e.dev, &t);
     hipError_t he = hipMemcpy(e.dev, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipMemcpy"); }
-    uint32_t grid = 0;
-    if ((st = resident_grid(kf::MODE_INTEGRATE, &grid)) != KF_OK) { drop_entry(e); return st; }
+    uint32_t grid[2] = {0, 0};
+    if ((st = resident_grid(kf::MODE_INTEGRATE, grid)) != KF_OK) { drop_entry(e); return st; }
     hipStream_t& cs = g_graphs.capture[device];
     if (!cs) {
         he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -618,8 +627,8 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
                     plan.passes.size());
     DeviceTables t;
     layout_tables(plan, &t);
-    uint32_t grid = 0;
-    if ((st = resident_grid(mode, &grid)) != KF_OK) return st;
+    uint32_t grid[2] = {0, 0};
+    if ((st = resident_grid(mode, grid)) != KF_OK) return st;
     unsigned char* dev = nullptr;
     KF_HIP(hipMallocAsync((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);

@@ -53,14 +53,19 @@ struct SceneDev {
 };
 
 enum Mode : int32_t { MODE_INTEGRATE = 0, MODE_STATUS = 1, MODE_COUNT = 2 };
+// Geometry and colour bricks are integrated by separate launches (their register needs
+// differ, and so does the occupancy each can reach).
+enum Kind : int32_t { KIND_GEOM = 0, KIND_COLOUR = 1 };
 
 struct IntegrateArgs {
     const SceneDev* scenes;           // table of n_scenes
     const FrameConsts* frames;        // frame table
     int32_t n_scenes;
-    const uint2* live;                // (brick, frame mask) of the bricks to process
-    const uint32_t* n_live;           // number of entries in `live`
-    uint32_t* queue;                  // next entry to take
+    const uint2* live;                // (brick, frame mask): geometry entries from the
+                                      // front, colour entries from the back
+    uint32_t cap;                     // entries `live` can hold (bricks of the pass)
+    const uint32_t* n_live;           // [KIND]: entries of each kind
+    uint32_t* queue;                  // [KIND]: next entry to take
     unsigned long long* counters;     // MODE_COUNT: uint64[8]
 };
 
@@ -78,8 +83,8 @@ struct CullArgs {
     int32_t n_scenes;
     uint32_t n_items;                 // bricks of all scenes of the pass
     int32_t disable;                  // 1: every brick is live in every frame
-    uint2* live;
-    uint32_t* n_live;
+    uint2* live;                      // n_items entries (see IntegrateArgs)
+    uint32_t* n_live;                 // [KIND]
 };
 
 // The adjoint over up to 64 frames: colour bricks culled like the forward's, then
@@ -99,6 +104,26 @@ struct BackwardArgs {
     uint32_t* n_live;
     uint32_t* queue;
 };
+
+// The first active lane's value of a 32-bit unsigned quantity.  The builtin takes and
+// returns a signed int: widening its result directly would sign-extend bit 31.
+__device__ __forceinline__ uint32_t first_lane_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Next entry of a work queue for the whole wave (one ticket per wave).  Every active lane
+// takes part in the atomic (the first active lane adds 1, the others 0) and the first
+// lane's result is broadcast, so the ticket is never defined under lane-dependent
+// control flow.  (With a ticket taken inside `if (lane == 0)` the compiler may thread the
+// loop into per-lane paths on which the other lanes never see a new ticket.)
+__device__ __forceinline__ uint32_t wave_ticket(uint32_t* queue)
+{
+    const uint64_t ex = __builtin_amdgcn_read_exec();
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ex >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ex, 0u));
+    return first_lane_u32(atomicAdd(queue, rank == 0 ? 1u : 0u));
+}
 
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.
 __host__ __device__ inline void pyr_level_dims(int32_t w0, int32_t h0, int32_t l, int32_t* w,

@@ -7,10 +7,10 @@
 //   2. cull kernel: one lane per brick decides, frame by frame, whether any voxel of the
 //      brick can pass the depth tests (conservatively, from the brick's corners and the
 //      pyramid) and appends (brick, frame mask) of the live bricks to a list;
-//   3. integrate kernel: persistent waves take live bricks from the list; each lane keeps
-//      its column's ZS voxels in an LDS scratchpad for all frames of the pass, reads a
-//      voxel's state only when a frame first needs it and writes it back only if a frame
-//      updated it.
+//   3. integrate kernels (one launch for geometry bricks, one for colour bricks):
+//      persistent waves take live bricks from the list; each lane keeps its column's ZS
+//      voxels in registers for all frames of the pass, reads a voxel's state only when a
+//      frame first needs it and writes it back only if it was read.
 // Culling never changes a result: a brick is dropped for a frame only if every voxel in
 // it would have been rejected before touching its state.
 //
@@ -73,13 +73,16 @@ __device__ __forceinline__ const_ptr<T> as_const(const T* p)
 
 struct Counts {
     unsigned long long g_upd = 0, g_touch = 0, c_eval = 0, c_read = 0, c_upd = 0, c_touch = 0;
-    unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (counted by lane 0)
+    unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (same in every lane)
 };
 
-// Voxel column of a lane in brick li of a volume with brick shape BX x BY x ZS.
+// Voxel column of a lane in brick li of a volume with brick shape BX x BY x ZS.  The
+// brick's z slab (ZS slices from k0) is wave-uniform: state arrays are read through a
+// buffer resource based at the slab, with per-lane byte offsets off + kk * zstride.
 struct Column {
     int i, j, k0, kn;
-    size_t base, slice;
+    size_t base, slice, slab;   // element index of (i, j, k0); elements per slice; of (0, 0, k0)
+    uint32_t off, zstride, slab_bytes;
     bool active;
 };
 
@@ -98,30 +101,15 @@ __device__ __forceinline__ Column column(const Dims& dim, const Dims& bricks, ui
     c.kn = min(ZS, dim[2] - c.k0);
     c.active = c.i < dim[0] && c.j < dim[1];
     c.slice = (size_t)dim[0] * (size_t)dim[1];
-    c.base = ((size_t)c.k0 * (size_t)dim[1] + (size_t)c.j) * (size_t)dim[0] + (size_t)c.i;
+    c.slab = (size_t)c.k0 * c.slice;
+    c.base = c.slab + (size_t)c.j * (size_t)dim[0] + (size_t)c.i;
+    c.off = ((uint32_t)c.j * (uint32_t)dim[0] + (uint32_t)c.i) * 4u;
+    c.zstride = (uint32_t)c.slice * 4u;
+    c.slab_bytes = (uint32_t)c.kn * c.zstride;
     return c;
 }
 
 // ------------------------------------------------------------------ image fetches
-
-// The lane's LDS scratchpad (see integrate_kernel): one 16-byte entry per voxel.
-struct alignas(16) Vox {
-    float x, y, z, w;
-};
-using Slot = __attribute__((address_space(3))) Vox*;
-
-__device__ __forceinline__ float4 slot_get(Slot s, int k)
-{
-    return make_float4(s[k].x, s[k].y, s[k].z, s[k].w);
-}
-
-__device__ __forceinline__ void slot_put(Slot s, int k, float4 v)
-{
-    s[k].x = v.x;
-    s[k].y = v.y;
-    s[k].z = v.z;
-    s[k].w = v.w;
-}
 
 // Depth maps are read through a bounds-checked buffer resource: an offset past the image
 // reads 0 (a hole), so a voxel outside the frustum needs no separate branch.
@@ -159,17 +147,29 @@ __device__ __forceinline__ Pixel project(const C& c, float X, float Y, float Z)
     return p;
 }
 
+// Buffer resource over the lane column's z slab of one state array (see Column).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(float* p, const Column& col)
+{
+    return image_rsrc(p + col.slab, col.slab_bytes);
+}
+
 // ------------------------------------------------------------------ geometry (Sec. III)
 
 // Projective TSDF with running average for the frames of `mask` (bit f = frame f of the
-// pass).  MODE_STATUS writes the outcome code of the (single) frame instead.
+// pass).  The column's state lives in registers for the whole pass: read from HBM when a
+// frame first updates a voxel, written back at the end if it was read.  Per frame, the
+// eight depth samples of the column are fetched before any of them is used.  MODE_STATUS
+// writes the outcome code of the (single) frame instead.
 template <int MODE, class Scene, class FramePtr>
 __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uint32_t mask,
-                                           uint32_t li, Slot slot, uint8_t* status, Counts& cnt)
+                                           uint32_t li, uint8_t* status, Counts& cnt)
 {
     const Column col = column<GBX, GBY>(sc.gdim, sc.gbricks, li);
     if (!col.active) return;
     const float fi = (float)col.i, fj = (float)col.j;
+    float F[ZS], W[ZS];
+#pragma unroll
+    for (int kk = 0; kk < ZS; ++kk) F[kk] = W[kk] = 0.0f;
     uint32_t loaded = 0;
     unsigned long long n_upd = 0;
     for (uint32_t m = mask; m; m &= m - 1) {
@@ -179,47 +179,56 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
         const float cY = fmaf(c.Ag[4], fj, fmaf(c.Ag[3], fi, c.bg[1]));
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
-        const float trunc = c.trunc, inv_trunc = c.inv_trunc, w_max = c.w_max;
-#pragma unroll 2
-        for (int kk = 0; kk < col.kn; ++kk) {
+        float sdf[ZS];
+        uint32_t upd = 0;
+#pragma unroll
+        for (int kk = 0; kk < ZS; ++kk) {
             const float fk = (float)(col.k0 + kk);
-            const float Xc = fmaf(c.Ag[2], fk, cX);
-            const float Yc = fmaf(c.Ag[5], fk, cY);
             const float Zc = fmaf(c.Ag[8], fk, cZ);
-            const Pixel px = project(c, Xc, Yc, Zc);
-            const float d = load_f32(depth, px.off);
-            const bool valid = px.inside & valid_depth(d);
-            const float sdf = d - Zc;
-            const bool upd = valid & !(sdf < -trunc);
+            const Pixel px = project(c, fmaf(c.Ag[2], fk, cX), fmaf(c.Ag[5], fk, cY), Zc);
+            const bool in = px.inside & (kk < col.kn);
+            const float d = load_f32(depth, in ? px.off : kOutside);
+            const bool valid = in & valid_depth(d);
+            sdf[kk] = d - Zc;
+            const bool u = valid & !(sdf[kk] < -c.trunc);
+            upd |= (uint32_t)u << kk;
             if constexpr (MODE == MODE_STATUS) {
-                const int st = !px.inside ? 0 : !valid ? 1 : upd ? 6 : 2;
-                status[col.base + (size_t)kk * col.slice] = (uint8_t)st;
-            } else if (upd) {
-                float F, W;
-                if (!((loaded >> kk) & 1u)) {
-                    F = sc.tsdf[col.base + (size_t)kk * col.slice];
-                    W = sc.wg[col.base + (size_t)kk * col.slice];
-                    loaded |= 1u << kk;
-                } else {
-                    const float4 t4 = slot_get(slot, kk * WAVE);
-                    F = t4.x;
-                    W = t4.y;
-                }
-                const float t = fminf(1.0f, sdf * inv_trunc);
-                const float wn = W + 1.0f;
-                F = F + (t - F) / wn;
-                W = fminf(wn, w_max);
-                slot_put(slot, kk * WAVE, make_float4(F, W, 0.0f, 0.0f));
-                ++n_upd;
+                if (kk < col.kn)
+                    status[col.base + (size_t)kk * col.slice] = (uint8_t)(!px.inside ? 0 : !valid ? 1 : u ? 6 : 2);
             }
+        }
+        if constexpr (MODE != MODE_STATUS) {
+            const uint32_t need = upd & ~loaded;
+            if (need) {
+                const __amdgpu_buffer_rsrc_t tr = slab_rsrc(sc.tsdf, col), wr = slab_rsrc(sc.wg, col);
+#pragma unroll
+                for (int kk = 0; kk < ZS; ++kk) {
+                    const bool nk = (need >> kk) & 1u;
+                    const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
+                    const float f = load_f32(tr, o), w = load_f32(wr, o);
+                    F[kk] = nk ? f : F[kk];
+                    W[kk] = nk ? w : W[kk];
+                }
+                loaded |= need;
+            }
+#pragma unroll
+            for (int kk = 0; kk < ZS; ++kk) {
+                if ((upd >> kk) & 1u) {
+                    const float t = fminf(1.0f, sdf[kk] * c.inv_trunc);
+                    const float wn = W[kk] + 1.0f;
+                    F[kk] = F[kk] + (t - F[kk]) / wn;
+                    W[kk] = fminf(wn, c.w_max);
+                }
+            }
+            n_upd += (unsigned)__builtin_popcount(upd);
         }
     }
     if constexpr (MODE != MODE_STATUS) {
-        for (int kk = 0; kk < col.kn; ++kk) {
+#pragma unroll
+        for (int kk = 0; kk < ZS; ++kk) {
             if ((loaded >> kk) & 1u) {
-                const float4 t4 = slot_get(slot, kk * WAVE);
-                sc.tsdf[col.base + (size_t)kk * col.slice] = t4.x;
-                sc.wg[col.base + (size_t)kk * col.slice] = t4.y;
+                sc.tsdf[col.base + (size_t)kk * col.slice] = F[kk];
+                sc.wg[col.base + (size_t)kk * col.slice] = W[kk];
             }
         }
     }
@@ -232,18 +241,23 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
 // --------------------------------------------------------------- colour (Sec. IV.B)
 
 // Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10, for the frames of mask.
-// The frustum, depth and sigma tests run without branches; the rest only for the voxels
-// that pass them.
+// Per frame, in stages over the column's eight voxels so that the loads of a stage are in
+// flight together: (1) frustum, depth and sigma tests; (2) the Eq. 8 neighbour depths of
+// the voxels in the band; (3) normals and weights, and the first read of the colour
+// weight of the voxels that reach the gate; (4) gate, HD pixel, Eq. 9 and Eq. 10.  The
+// column's colour state lives in registers for the whole pass.
 template <int MODE, class Scene, class FramePtr>
 __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, uint32_t mask,
-                                             uint32_t li, Slot slot, uint8_t* status,
-                                             Counts& cnt)
+                                             uint32_t li, uint8_t* status, Counts& cnt)
 {
     const Column col = column<CBX, CBY>(sc.cdim, sc.cbricks, li);
     if (!col.active) return;
     const float fi = (float)col.i, fj = (float)col.j;
-    uint32_t wl = 0;   // colour weight read (slot .w valid)
-    uint32_t cl = 0;   // colour read and updated (slot .xyz valid, store at the end)
+    float R[ZS], G[ZS], B[ZS], Wt[ZS];
+#pragma unroll
+    for (int kk = 0; kk < ZS; ++kk) R[kk] = G[kk] = B[kk] = Wt[kk] = 0.0f;
+    uint32_t wl = 0;   // colour weight read
+    uint32_t cl = 0;   // colour read and updated (stored at the end)
     unsigned long long n_eval = 0, n_upd = 0;
     for (uint32_t m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctz(m)];
@@ -251,57 +265,96 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
-        const float sigma2 = c.sigma2;
-#pragma unroll 2
-        for (int kk = 0; kk < col.kn; ++kk) {
+        int st[ZS];
+        // (1) Eq. 5-7 and the distance test against sigma.
+        uint32_t uv[ZS];   // depth pixel (u | v << 16) of voxels inside the frustum
+        float dd[ZS];
+        uint32_t band = 0;
+#pragma unroll
+        for (int kk = 0; kk < ZS; ++kk) {
             const float fk = (float)(col.k0 + kk);
             const float Xc = fmaf(c.Ac[2], fk, cX);
             const float Yc = fmaf(c.Ac[5], fk, cY);
             const float Zc = fmaf(c.Ac[8], fk, cZ);
             const Pixel px = project(c, Xc, Yc, Zc);
-            const float d = load_f32(depth, px.off);
-            const bool valid = px.inside & valid_depth(d);
-            // Eq. 7 at the integer pixel, then the distance test against sigma.
+            const bool in = px.inside & (kk < col.kn);
+            const float d = load_f32(depth, in ? px.off : kOutside);
+            const bool valid = in & valid_depth(d);
             const float Px = ((px.u - c.cx) * c.inv_fx) * d;
             const float Py = ((px.v - c.cy) * c.inv_fy) * d;
             const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
             const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool band = valid & !(dist2 > sigma2);
-            int st = !px.inside ? 0 : !valid ? 1 : band ? 3 : 2;
-            if (band) {
-                // Eq. 8 from the neighbours (u+1, v) and (u, v+1).
-                const bool has_nb = (px.u + 1.0f <= c.wm1) & (px.v + 1.0f <= c.hm1);
-                const float d1 = load_f32(depth, has_nb ? px.off + 4u : kOutside);
-                const float d2 = load_f32(depth, has_nb ? px.off + (uint32_t)c.dw * 4u : kOutside);
-                const float P1x = ((px.u + 1.0f - c.cx) * c.inv_fx) * d1;
-                const float P1y = ((px.v - c.cy) * c.inv_fy) * d1;
-                const float P2x = ((px.u - c.cx) * c.inv_fx) * d2;
-                const float P2y = ((px.v + 1.0f - c.cy) * c.inv_fy) * d2;
-                const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1 - d;
-                const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2 - d;
-                const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
-                const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
-                const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
-                const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
-                if ((int)has_nb & (int)valid_depth(d1) & (int)valid_depth(d2) & (int)(nn > 0.0f)) {
-                    // W: unit normal . unit viewing direction (camera -> P).
-                    const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
-                    const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
-                    const float w = dp / sqrtf(nn * pp);
-                    st = 4;
-                    const size_t idx = col.base + (size_t)kk * col.slice;
-                    float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    if constexpr (MODE != MODE_STATUS) s = slot_get(slot, kk * WAVE);
-                    if (!((wl >> kk) & 1u)) {
-                        s.w = sc.wc[idx];
-                        wl |= 1u << kk;
+            const bool bd = valid & !(dist2 > c.sigma2);
+            band |= (uint32_t)bd << kk;
+            uv[kk] = in ? (((uint32_t)(int)px.v << 16) | (uint32_t)(int)px.u) : 0u;
+            dd[kk] = d;
+            if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
+        }
+        if (band) {
+            // (2) neighbours (u+1, v) and (u, v+1); a missing neighbour reads as a hole.
+            float d1[ZS], d2[ZS];
+#pragma unroll
+            for (int kk = 0; kk < ZS; ++kk) {
+                const uint32_t pu = uv[kk] & 0xFFFFu, pv = uv[kk] >> 16;
+                const bool has_nb = ((band >> kk) & 1u) & (pu + 1u < (uint32_t)c.dw) & (pv + 1u < (uint32_t)c.dh);
+                const uint32_t o = (pv * (uint32_t)c.dw + pu) * 4u;
+                d1[kk] = load_f32(depth, has_nb ? o + 4u : kOutside);
+                d2[kk] = load_f32(depth, has_nb ? o + (uint32_t)c.dw * 4u : kOutside);
+            }
+            // (3) Eq. 8 normal; W = unit normal . unit viewing direction (camera -> P).
+            float wv[ZS];
+            uint32_t reach = 0;
+#pragma unroll
+            for (int kk = 0; kk < ZS; ++kk) {
+                wv[kk] = 0.0f;
+                if ((band >> kk) & 1u) {
+                    const float u = (float)(uv[kk] & 0xFFFFu), v = (float)(uv[kk] >> 16);
+                    const float d = dd[kk];
+                    const float Px = ((u - c.cx) * c.inv_fx) * d;
+                    const float Py = ((v - c.cy) * c.inv_fy) * d;
+                    const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1[kk];
+                    const float P1y = ((v - c.cy) * c.inv_fy) * d1[kk];
+                    const float P2x = ((u - c.cx) * c.inv_fx) * d2[kk];
+                    const float P2y = ((v + 1.0f - c.cy) * c.inv_fy) * d2[kk];
+                    const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1[kk] - d;
+                    const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2[kk] - d;
+                    const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
+                    const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
+                    const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
+                    const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
+                    if ((int)valid_depth(d1[kk]) & (int)valid_depth(d2[kk]) & (int)(nn > 0.0f)) {
+                        const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
+                        const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
+                        wv[kk] = dp / sqrtf(nn * pp);
+                        reach |= 1u << kk;
                     }
-                    ++n_eval;
-                    float ax = 0.0f, ay = 0.0f;
-                    int cell = 0;
-                    if (w > c.gate * s.w) {
-                        // Eq. 3-5 on the voxel centre: HD pixel and bilinear cell.
-                        st = 5;
+                }
+            }
+            const uint32_t needw = reach & ~wl;
+            if (needw) {
+                const __amdgpu_buffer_rsrc_t wr = slab_rsrc(sc.wc, col);
+#pragma unroll
+                for (int kk = 0; kk < ZS; ++kk) {
+                    const bool nk = (needw >> kk) & 1u;
+                    const float w = load_f32(wr, nk ? col.off + (uint32_t)kk * col.zstride : kOutside);
+                    Wt[kk] = nk ? w : Wt[kk];
+                }
+                wl |= needw;
+            }
+            n_eval += (unsigned)__builtin_popcount(reach);
+            // (4) gate, HD pixel of the voxel centre (Eq. 3-5), bilinear cell inside the image.
+            uint32_t upd = 0;
+            int cell[ZS];
+            float ax[ZS], ay[ZS];
+#pragma unroll
+            for (int kk = 0; kk < ZS; ++kk) {
+                cell[kk] = 0;
+                ax[kk] = ay[kk] = 0.0f;
+                if ((reach >> kk) & 1u) {
+                    if constexpr (MODE == MODE_STATUS) st[kk] = 4;
+                    if (wv[kk] > c.gate * Wt[kk]) {
+                        if constexpr (MODE == MODE_STATUS) st[kk] = 5;
+                        const float fk = (float)(col.k0 + kk);
                         const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
                         const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
                         const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
@@ -310,48 +363,63 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                         const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
                         const float x0 = floorf(xh), y0 = floorf(yh);
                         if ((qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.cwm2) & (y0 >= 0.0f) & (y0 <= c.chm2)) {
-                            st = 6;
-                            ax = xh - x0;
-                            ay = yh - y0;
-                            cell = ((int)y0 * c.cw + (int)x0) * 3;
+                            if constexpr (MODE == MODE_STATUS) st[kk] = 6;
+                            ax[kk] = xh - x0;
+                            ay[kk] = yh - y0;
+                            cell[kk] = ((int)y0 * c.cw + (int)x0) * 3;
+                            upd |= 1u << kk;
                         }
-                    }
-                    if constexpr (MODE != MODE_STATUS) {
-                        if (st == 6) {
-                            if (!((cl >> kk) & 1u)) {
-                                s.x = sc.r[idx];
-                                s.y = sc.g[idx];
-                                s.z = sc.b[idx];
-                                cl |= 1u << kk;
-                            }
-                            const int row = c.cw * 3;
-                            const float s0 = hd_sample(c.rgb, sc.fmt, cell, row, 0, ax, ay);
-                            const float s1 = hd_sample(c.rgb, sc.fmt, cell, row, 1, ax, ay);
-                            const float s2 = hd_sample(c.rgb, sc.fmt, cell, row, 2, ax, ay);
-                            const float alpha = w / (s.w + w);
-                            s.x = fmaf(alpha, s0 - s.x, s.x);
-                            s.y = fmaf(alpha, s1 - s.y, s.y);
-                            s.z = fmaf(alpha, s2 - s.z, s.z);
-                            s.w = fmaf(w, 1.0f - s.w, s.w);
-                            ++n_upd;
-                        }
-                        slot_put(slot, kk * WAVE, s);
                     }
                 }
             }
-            if constexpr (MODE == MODE_STATUS)
-                status[col.base + (size_t)kk * col.slice] = (uint8_t)st;
+            if constexpr (MODE != MODE_STATUS) {
+                const uint32_t needc = upd & ~cl;
+                if (needc) {
+                    const __amdgpu_buffer_rsrc_t rr = slab_rsrc(sc.r, col), gr = slab_rsrc(sc.g, col),
+                                                 br = slab_rsrc(sc.b, col);
+#pragma unroll
+                    for (int kk = 0; kk < ZS; ++kk) {
+                        const bool nk = (needc >> kk) & 1u;
+                        const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
+                        const float r = load_f32(rr, o), g = load_f32(gr, o), b = load_f32(br, o);
+                        R[kk] = nk ? r : R[kk];
+                        G[kk] = nk ? g : G[kk];
+                        B[kk] = nk ? b : B[kk];
+                    }
+                    cl |= needc;
+                }
+                const int row = c.cw * 3;
+#pragma unroll
+                for (int kk = 0; kk < ZS; ++kk) {
+                    if ((upd >> kk) & 1u) {
+                        const float s0 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 0, ax[kk], ay[kk]);
+                        const float s1 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 1, ax[kk], ay[kk]);
+                        const float s2 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 2, ax[kk], ay[kk]);
+                        const float alpha = wv[kk] / (Wt[kk] + wv[kk]);
+                        R[kk] = fmaf(alpha, s0 - R[kk], R[kk]);
+                        G[kk] = fmaf(alpha, s1 - G[kk], G[kk]);
+                        B[kk] = fmaf(alpha, s2 - B[kk], B[kk]);
+                        Wt[kk] = fmaf(wv[kk], 1.0f - Wt[kk], Wt[kk]);
+                    }
+                }
+                n_upd += (unsigned)__builtin_popcount(upd);
+            }
+        }
+        if constexpr (MODE == MODE_STATUS) {
+#pragma unroll
+            for (int kk = 0; kk < ZS; ++kk)
+                if (kk < col.kn) status[col.base + (size_t)kk * col.slice] = (uint8_t)st[kk];
         }
     }
     if constexpr (MODE != MODE_STATUS) {
-        for (int kk = 0; kk < col.kn; ++kk) {
+#pragma unroll
+        for (int kk = 0; kk < ZS; ++kk) {
             if ((cl >> kk) & 1u) {
                 const size_t idx = col.base + (size_t)kk * col.slice;
-                const float4 s = slot_get(slot, kk * WAVE);
-                sc.r[idx] = s.x;
-                sc.g[idx] = s.y;
-                sc.b[idx] = s.z;
-                sc.wc[idx] = s.w;
+                sc.r[idx] = R[kk];
+                sc.g[idx] = G[kk];
+                sc.b[idx] = B[kk];
+                sc.wc[idx] = Wt[kk];
             }
         }
     }
@@ -376,12 +444,13 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 {
     const uint32_t item = blockIdx.x * BLOCK + threadIdx.x;
     uint32_t mask = 0;
+    bool colour = false;
     if (item < a.n_items) {
         int s = 0;
         while (s + 1 < a.n_scenes && a.scenes[s + 1].item_begin <= item) ++s;
         const SceneDev& sc = a.scenes[s];
         uint32_t li = item - sc.item_begin;
-        const bool colour = li >= sc.geom_items;
+        colour = li >= sc.geom_items;
         if (colour) li -= sc.geom_items;
         const int32_t* dim = colour ? sc.cdim : sc.gdim;
         const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
@@ -397,17 +466,14 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
                 mask |= 1u << f;
         }
     }
-    // append the live bricks: one atomic per wave
-    const unsigned long long live = __ballot(mask != 0);
-    if (live == 0) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(a.n_live, (uint32_t)__popcll(live));
-    base = __shfl(base, 0, WAVE);
-    if (mask) {
-        const uint32_t rank = (uint32_t)__popcll(live & ((1ull << lane) - 1ull));
-        a.live[base + rank] = make_uint2(item, mask);
-    }
+    // append the live bricks, geometry from the front and colour from the back of the
+    // list; every lane takes part in both atomics (adding 0 or 1), which the compiler
+    // turns into one atomic per wave and a prefix sum
+    const bool is_g = mask != 0 && !colour, is_c = mask != 0 && colour;
+    const uint32_t pg = atomicAdd(a.n_live + KIND_GEOM, is_g ? 1u : 0u);
+    const uint32_t pc = atomicAdd(a.n_live + KIND_COLOUR, is_c ? 1u : 0u);
+    if (is_g) a.live[pg] = make_uint2(item, mask);
+    if (is_c) a.live[a.n_items - 1u - pc] = make_uint2(item, mask);
 }
 
 // ------------------------------------------------------------------- depth pyramid
@@ -460,35 +526,31 @@ __global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* fr
 
 // ------------------------------------------------------------------------ integration
 
-// Persistent waves: each takes (brick, frame mask) entries from the live list.
-template <int MODE>
+// Persistent waves: each takes (brick, frame mask) entries of one kind from the live list.
+template <int MODE, int KIND>
 __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
-    // per-lane state scratchpad: slot kk of a lane at [kk * WAVE] from its base
-    __shared__ Vox s_state[BLOCK * ZS];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    const Slot slot = (Slot)(s_state + wave * WAVE * ZS + lane);
+    const int lane = threadIdx.x & (WAVE - 1);
     Counts cnt;
-    const uint32_t n_live = *as_const(a.n_live);
+    const uint32_t n_live = *as_const(a.n_live + KIND);
     const const_ptr<SceneDev> scenes = as_const(a.scenes);
     for (;;) {
-        uint32_t e = 0;
-        if (lane == 0) e = atomicAdd(a.queue, 1u);
-        e = __builtin_amdgcn_readfirstlane(e);
+        const uint32_t e = wave_ticket(a.queue + KIND);
         if (e >= n_live) break;
-        const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 2 * (size_t)e;
+        const uint32_t pos = KIND == KIND_COLOUR ? a.cap - 1u - e : e;
+        const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 2 * (size_t)pos;
         const uint32_t item = ent[0], fmask = ent[1];
         int s = 0;
         while (s + 1 < a.n_scenes && scenes[s + 1].item_begin <= item) ++s;
         const auto& sc = scenes[s];
         const const_ptr<FrameConsts> frames = as_const(a.frames) + sc.frame_begin;
         const uint32_t li = item - sc.item_begin;
-        if (li < sc.geom_items) {
-            geom_brick<MODE>(sc, frames, fmask, li, slot, nullptr, cnt);
-            if (MODE == MODE_COUNT && lane == 0) cnt.g_bricks += (unsigned)__builtin_popcount(fmask);
+        if constexpr (KIND == KIND_GEOM) {
+            geom_brick<MODE>(sc, frames, fmask, li, nullptr, cnt);
+            if constexpr (MODE == MODE_COUNT) cnt.g_bricks += (unsigned)__builtin_popcount(fmask);
         } else {
-            colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, slot, nullptr, cnt);
-            if (MODE == MODE_COUNT && lane == 0) cnt.c_bricks += (unsigned)__builtin_popcount(fmask);
+            colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, nullptr, cnt);
+            if constexpr (MODE == MODE_COUNT) cnt.c_bricks += (unsigned)__builtin_popcount(fmask);
         }
     }
     if constexpr (MODE == MODE_COUNT) {
@@ -513,9 +575,9 @@ __global__ __launch_bounds__(BLOCK) void status_kernel(StatusArgs a)
     Counts cnt;
     const FrameConsts* frames = &a.frame;
     if constexpr (COLOUR)
-        colour_brick<MODE_STATUS>(a.scene, frames, 1u, li, nullptr, a.status, cnt);
+        colour_brick<MODE_STATUS>(a.scene, frames, 1u, li, a.status, cnt);
     else
-        geom_brick<MODE_STATUS>(a.scene, frames, 1u, li, nullptr, a.status, cnt);
+        geom_brick<MODE_STATUS>(a.scene, frames, 1u, li, a.status, cnt);
 }
 
 __global__ void fill_f32_kernel(float* p, size_t n, float v)
@@ -553,13 +615,18 @@ hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(int mode, const IntegrateArgs& a, uint32_t grid, hipStream_t stream)
+hipError_t launch_integrate(int mode, int kind, const IntegrateArgs& a, uint32_t grid,
+                            hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
-    if (mode == MODE_INTEGRATE)
-        hipLaunchKernelGGL(integrate_kernel<MODE_INTEGRATE>, dim3(grid), dim3(BLOCK), 0, stream, a);
-    else if (mode == MODE_COUNT)
-        hipLaunchKernelGGL(integrate_kernel<MODE_COUNT>, dim3(grid), dim3(BLOCK), 0, stream, a);
+    if (mode == MODE_INTEGRATE && kind == KIND_GEOM)
+        hipLaunchKernelGGL((integrate_kernel<MODE_INTEGRATE, KIND_GEOM>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    else if (mode == MODE_INTEGRATE && kind == KIND_COLOUR)
+        hipLaunchKernelGGL((integrate_kernel<MODE_INTEGRATE, KIND_COLOUR>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    else if (mode == MODE_COUNT && kind == KIND_GEOM)
+        hipLaunchKernelGGL((integrate_kernel<MODE_COUNT, KIND_GEOM>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    else if (mode == MODE_COUNT && kind == KIND_COLOUR)
+        hipLaunchKernelGGL((integrate_kernel<MODE_COUNT, KIND_COLOUR>), dim3(grid), dim3(BLOCK), 0, stream, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -576,15 +643,18 @@ hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t persistent_grid(int mode, int device, uint32_t* blocks)
+hipError_t persistent_grid(int mode, int kind, int device, uint32_t* blocks)
 {
     int n_cu = 0, per_cu = 0;
     hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    if (mode == MODE_COUNT)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_kernel<MODE_COUNT>, BLOCK, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_kernel<MODE_INTEGRATE>, BLOCK, 0);
+    const void* fn = nullptr;
+    if (mode == MODE_INTEGRATE && kind == KIND_GEOM) fn = (const void*)integrate_kernel<MODE_INTEGRATE, KIND_GEOM>;
+    else if (mode == MODE_INTEGRATE && kind == KIND_COLOUR) fn = (const void*)integrate_kernel<MODE_INTEGRATE, KIND_COLOUR>;
+    else if (mode == MODE_COUNT && kind == KIND_GEOM) fn = (const void*)integrate_kernel<MODE_COUNT, KIND_GEOM>;
+    else if (mode == MODE_COUNT && kind == KIND_COLOUR) fn = (const void*)integrate_kernel<MODE_COUNT, KIND_COLOUR>;
+    else return hipErrorInvalidValue;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, 0);
     if (e != hipSuccess) return e;
     *blocks = (uint32_t)(n_cu * (per_cu > 0 ? per_cu : 1));
     return hipSuccess;

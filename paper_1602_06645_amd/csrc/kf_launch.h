@@ -12,12 +12,14 @@ hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int3
                            hipStream_t stream);
 // One lane per brick of the pass: append (brick, live-frame mask) entries.
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream);
-// Persistent integration over the live list (mode: MODE_INTEGRATE or MODE_COUNT).
-hipError_t launch_integrate(int mode, const IntegrateArgs& a, uint32_t grid, hipStream_t stream);
+// Persistent integration over the live entries of one kind (mode: MODE_INTEGRATE or
+// MODE_COUNT; kind: KIND_GEOM or KIND_COLOUR).
+hipError_t launch_integrate(int mode, int kind, const IntegrateArgs& a, uint32_t grid,
+                            hipStream_t stream);
 // Status codes of one frame for every brick of one kind.
 hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream);
-// Blocks that stay resident at once on `device` for a persistent launch of `mode`.
-hipError_t persistent_grid(int mode, int device, uint32_t* blocks);
+// Blocks that stay resident at once on `device` for a persistent launch of (mode, kind).
+hipError_t persistent_grid(int mode, int kind, int device, uint32_t* blocks);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream);
 

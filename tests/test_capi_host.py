@@ -61,6 +61,12 @@ def test_buffer_bytes_and_desc_validation():
     bad = _desc()
     bad.colour_dim[:] = [2048, 2048, 1024]
     assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_RANGE
+    bad = _desc()
+    bad.colour_dim[:] = [8192, 8192, 8]      # one z slice of 2^26 voxels
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_E_RANGE
+    assert b"slice" in lib.kf_last_error()
+    bad.colour_dim[:] = [8192, 8191, 8]
+    assert lib.kf_volume_buffer_bytes(C.byref(bad), out) == L.KF_OK
     assert lib.kf_volume_buffer_bytes(None, out) == L.KF_E_ARG
 
 
@@ -109,6 +115,8 @@ def _call_integrate(h, **over):
     (dict(T_rd=np.array([[1.0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0.1, 1]])), L.KF_E_ARG),
     (dict(T_wc=np.full((4, 4), np.nan)), L.KF_E_ARG),
     (dict(cw=50000, ch=50000), L.KF_E_RANGE),
+    (dict(dw=65536, dh=2), L.KF_E_RANGE),
+    (dict(dw=30000, dh=20000), L.KF_E_RANGE),
 ])
 def test_integrate_rejects_bad_arguments(over, code):
     h = _volume()

@@ -121,12 +121,14 @@ def test_autograd_function_against_central_differences(oracle):
     torch.testing.assert_close(rgb.grad, d_rgb, rtol=1e-5, atol=1e-6)
 
 
-def test_backward_full_size_sampled_slabs(oracle):
-    """Kinect-like volume (256^3 / 512^3) with 1920x1080 float images, 6 frames; g is
-    non-zero on two seeded colour z-slabs so that the oracle's adjoint of exactly the same
-    functional can be computed on those slabs."""
-    say("backward: full-size volume, sampled slabs")
-    spec, fr = configs.kinect(device=DEV, n_frames=6)
+@pytest.mark.parametrize("n_frames", [6, 32])
+def test_backward_full_size_sampled_slabs(oracle, n_frames):
+    """Kinect-like volume (256^3 / 512^3) with 1920x1080 float images; g is non-zero on
+    two seeded colour z-slabs so that the oracle's adjoint of exactly the same functional
+    can be computed on those slabs.  32 frames put a live frame in bit 31 of the bricks'
+    frame masks (regression: that bit must not sign-extend into frames 32-63)."""
+    say(f"backward: full-size volume, {n_frames} frames, sampled slabs")
+    spec, fr = configs.kinect(device=DEV, n_frames=n_frames)
     fr = fr.as_float_rgb()
     rng = np.random.default_rng(91)
     nxy = spec.cdim[0] * spec.cdim[1]
