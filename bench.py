@@ -7,8 +7,8 @@ Workload (synthetic, seeded): geometry 256^3 + colour 512^3 over a 0.75 m cube, 
 3 spheres and 2 boxes on a plane; trunc = 4 geometry voxels, w_max = 128.
 
 One step = one whole scan: reset the volume, then integrate all 300 frames in passes of
-K frames (one call: depth pyramids for all frames, then per pass a culling launch and a
-persistent integration launch).  The metric counts
+K frames (one call: depth pyramids for all frames, then per pass a culling launch and two
+persistent integration launches, geometry bricks then colour bricks).  The metric counts
 every voxel of both volumes once per frame (the swept voxel updates of KinectFusion-style
 integration).  Besides the headline line the JSON carries: the plain frame-by-frame path
 and the fused/plain speedup, forward + backward time of the differentiable form on the
@@ -50,14 +50,14 @@ def default_frames_per_pass() -> int:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in ("kf_integrate.hip", "kf_device.h"):
+    for name in ("kf_integrate.hip", "kf_device.h", "kf_cull.h"):
         with open(os.path.join(ROOT, "paper_1602_06645_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(K: int):
-    """HBM bytes per launch of the integrate kernel from the rocprofv3 FETCH_SIZE and
+    """HBM bytes per pass of the integrate kernels from the rocprofv3 FETCH_SIZE and
     WRITE_SIZE runs recorded under profiles/ (scaled by the same counters on a plain copy
     of known size); None when the kernel source or the pass length changed since."""
     path = os.path.join(ROOT, "profiles", "integrate_kernel_kinect_traffic.txt")
@@ -164,7 +164,7 @@ def main() -> int:
     value = n_vox * fr.n * args.steps / wall
     launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, "
-        f"integrate kernel {launch_ms:.3f} ms per launch")
+        f"integrate kernels {launch_ms:.3f} ms per pass")
     per_launch_bytes = alg_bytes / len(passes)
     achieved = per_launch_bytes / (launch_ms * 1e-3) / 1e9
     out = {
@@ -188,7 +188,8 @@ def main() -> int:
                    "gate": spec.gate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(K),
-                     "kernel": "integrate_kernel<0> (persistent fused pass)",
+                     "kernel": "integrate_kernel<0,0> + integrate_kernel<0,1> (geometry and "
+                               "colour persistent launches of one fused pass)",
                      "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
         "counters": {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
                      "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),

@@ -1,0 +1,101 @@
+"""Driver run in a child process (with the sanitizer runtime preloaded): integrates and
+differentiates seeded scans through the emulated C ABI with host buffers and prints one
+JSON line comparing every output with the oracle."""
+import ctypes as C
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.abspath(os.path.join(HERE, "..", ".."))
+sys.path.insert(0, ROOT)
+from paper_1602_06645_amd import _lib as L          # noqa: E402
+from paper_1602_06645_amd.api import volume_desc    # noqa: E402
+from kf_synth import configs                        # noqa: E402
+from oracle import oracle as O                      # noqa: E402
+
+lib = C.CDLL(sys.argv[1])
+for name, (res, args) in L.SIGNATURES.items():
+    fn = getattr(lib, name)
+    fn.restype = res
+    fn.argtypes = args
+
+
+def check(st):
+    if st != 0:
+        raise RuntimeError(f"status {st}: {lib.kf_last_error().decode()}")
+
+
+class Vol:
+    def __init__(self, spec):
+        ng, nc = int(np.prod(spec.gdim)), int(np.prod(spec.cdim))
+        self.arrs = [np.zeros(ng, np.float32) for _ in range(2)] + \
+                    [np.zeros(nc, np.float32) for _ in range(4)]
+        bufs = L.VolumeBuffers(*[a.ctypes.data for a in self.arrs])
+        self.desc = volume_desc(spec)
+        self.h = C.c_void_p()
+        check(lib.kf_volume_create(C.byref(self.desc), C.byref(bufs), C.byref(self.h)))
+
+
+def scene(vol, fr, keep):
+    s = L.Scene()
+    d = np.ascontiguousarray(fr.depth, np.float32)
+    rgb = np.ascontiguousarray(fr.rgb)
+    mats = [np.ascontiguousarray(m, np.float64)
+            for m in (fr.K_d, fr.K_rgb, fr.T_rgb_from_d, fr.T_world_from_cam)]
+    keep += [d, rgb] + mats
+    s.vol, s.n_frames = vol.h.value, d.shape[0]
+    s.depth, s.rgb = d.ctypes.data, rgb.ctypes.data
+    s.fmt = L.KF_RGB8 if rgb.dtype == np.uint8 else L.KF_RGBF32
+    s.dh, s.dw, s.ch, s.cw = d.shape[1], d.shape[2], rgb.shape[1], rgb.shape[2]
+    s.K_d, s.K_rgb, s.T_rgb_from_d, s.T_world_from_cam = [m.ctypes.data for m in mats]
+    s.trunc_m, s.w_max = float(fr.trunc), float(fr.w_max)
+    return s
+
+
+def forward_case(pairs, K):
+    keep = []
+    arr = (L.Scene * len(pairs))(*[scene(v, f, keep) for v, f in pairs])
+    check(lib.kf_integrate_batch(arr, len(pairs), K, 0, None))
+    worst = 0
+    for (v, fr), spec in zip(pairs, SPECS):
+        st = O.State(spec, np.float32)
+        O.integrate(spec, fr, st)
+        for a, b in zip(v.arrs, st.arrays()):
+            worst += int(np.count_nonzero(a.view(np.uint32) != b.astype(np.float32).view(np.uint32)))
+    return worst
+
+
+def backward_case(spec, fr):
+    fr = fr.as_float_rgb()
+    d = np.ascontiguousarray(fr.depth, np.float32)
+    rgb = np.ascontiguousarray(fr.rgb, np.float32)
+    mats = [np.ascontiguousarray(m, np.float64)
+            for m in (fr.K_d, fr.K_rgb, fr.T_rgb_from_d, fr.T_world_from_cam)]
+    g = configs.gradient_weights(spec.n_colour).numpy()
+    d_rgb = np.empty_like(rgb)
+    d_xi = np.empty(6, np.float64)
+    desc = volume_desc(spec)
+    check(lib.kf_integrate_backward(
+        C.byref(desc), None, d.shape[0], d.ctypes.data, rgb.ctypes.data, d.shape[2],
+        d.shape[1], rgb.shape[2], rgb.shape[1], *[m.ctypes.data for m in mats], g.ctypes.data,
+        d_rgb.ctypes.data, d_xi.ctypes.data, None))
+    want_rgb, want_xi = O.backward(spec, fr, g.astype(np.float64), decide_f32=True)
+    def rel(got, want):
+        floor = 1e-3 * np.abs(want).max()
+        return float((np.abs(got - want) / (1e-3 * np.abs(want) + floor)).max())
+    return {"rgb": rel(d_rgb, want_rgb), "xi": rel(d_xi, want_xi)}
+
+
+out = {}
+spec6, fr6 = configs.tiny(n_frames=6)
+fr6 = fr6.numpy()
+spec32, fr32 = configs.tiny(n_frames=32)
+fr32 = fr32.numpy()
+SPECS = [spec6, spec32]
+out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb())], 32)
+out["backward_6"] = backward_case(spec6, fr6)
+out["backward_32"] = backward_case(spec32, fr32)
+print("JSON:" + json.dumps(out), flush=True)
