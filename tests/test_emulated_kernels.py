@@ -13,22 +13,30 @@ import sys
 import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, os.path.join(HERE, "emu"))
-import build as emu_build  # noqa: E402
+EMU = os.path.join(HERE, "emu")
 
 
 @pytest.fixture(scope="module")
-def emulated(tmp_path_factory):
-    if not os.path.exists(emu_build.CLANG):
+def emu_build():
+    if not os.path.exists(os.path.join(EMU, "build.py")):
+        pytest.skip("tests/emu is not present")
+    sys.path.insert(0, EMU)
+    import build
+    if not os.path.exists(build.CLANG):
         pytest.skip("host clang of the ROCm toolchain not found")
+    return build
+
+
+@pytest.fixture(scope="module")
+def emulated(emu_build, tmp_path_factory):
     return emu_build.build(str(tmp_path_factory.mktemp("emu")))
 
 
-def test_emulated_kernels_match_oracle(emulated):
+def test_emulated_kernels_match_oracle(emu_build, emulated):
     env = dict(os.environ, LD_PRELOAD=emu_build.asan_runtime(),
                ASAN_OPTIONS="detect_leaks=0:max_malloc_fill_size=1000000000:malloc_fill_byte=190",
                UBSAN_OPTIONS="halt_on_error=1", EMU_THREADS="4")
-    r = subprocess.run([sys.executable, os.path.join(HERE, "emu", "run_emulated.py"), emulated],
+    r = subprocess.run([sys.executable, os.path.join(EMU, "run_emulated.py"), emulated],
                        env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stderr[-4000:]
     res = json.loads(r.stdout.split("JSON:", 1)[1])
