@@ -51,24 +51,9 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     const float Py = ((v - c.cy) * c.inv_fy) * d;
     const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
     if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > c.sigma2) return 0.0f;
-    if (!(u + 1.0f <= c.wm1 && v + 1.0f <= c.hm1)) return 0.0f;
-    const float d1 = c.depth[pix + 1];
-    const float d2 = c.depth[pix + c.dw];
-    if (!valid_depth(d1) || !valid_depth(d2)) return 0.0f;
-    const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1;
-    const float P1y = ((v - c.cy) * c.inv_fy) * d1;
-    const float P2x = ((u - c.cx) * c.inv_fx) * d2;
-    const float P2y = ((v + 1.0f - c.cy) * c.inv_fy) * d2;
-    const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1 - d;
-    const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2 - d;
-    const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
-    const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
-    const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
-    const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
-    if (!(nn > 0.0f)) return 0.0f;
-    const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
-    const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
-    const float w = dp / sqrtf(nn * pp);
+    // W of the depth pixel (Eq. 8 normal and the viewing ray), from the frame's weight map
+    const float w = c.wmap[pix];
+    if (__builtin_bit_cast(uint32_t, w) == kNoNormal) return 0.0f;
     if (!(w > c.gate * Wc)) return 0.0f;
     const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
@@ -90,26 +75,39 @@ __device__ __forceinline__ double wave_sum_d(double x)
 
 }  // namespace
 
-// One lane per colour brick: the brick's live frames (64-bit mask) for the adjoint.
+// Each block culls a chunk of BWD_CULL_CHUNK consecutive colour bricks, four at a time:
+// one wave per brick and one lane per frame, a ballot giving the brick's live frames.  The
+// chunk's live entries are gathered in LDS and appended with one atomic per block.
+constexpr int BWD_CULL_CHUNK = 64;
+
 __global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
 {
-    const uint32_t li = blockIdx.x * BLOCK + threadIdx.x;
-    unsigned long long mask = 0;
-    if (li < a.n_items) {
-        const int bx = (int)(li % (uint32_t)a.cbricks[0]);
-        const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
-        const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
-        const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
-        const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
-        const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
-        for (int f = 0; f < a.n_frames; ++f)
-            if (a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1))
-                mask |= 1ull << f;
+    __shared__ uint4 s_ent[BWD_CULL_CHUNK];
+    __shared__ uint32_t s_n, s_base;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const int f = (int)(threadIdx.x % WAVE);
+    const uint32_t first = blockIdx.x * (uint32_t)BWD_CULL_CHUNK;
+    for (int r = 0; r < BWD_CULL_CHUNK / (BLOCK / WAVE); ++r) {
+        const uint32_t li = first + (uint32_t)(r * (BLOCK / WAVE)) + threadIdx.x / WAVE;
+        bool live = false;
+        if (li < a.n_items && f < a.n_frames) {
+            const int bx = (int)(li % (uint32_t)a.cbricks[0]);
+            const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
+            const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
+            const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
+            const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
+            const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
+            live = a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1);
+        }
+        const unsigned long long mask = __ballot(live);
+        if (f == 0 && mask != 0)
+            s_ent[atomicAdd(&s_n, 1u)] = make_uint4(li, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
     }
-    // every lane takes part in the atomic (adding 0 or 1): one atomic per wave and a
-    // prefix sum after the compiler's combining
-    const uint32_t pos = atomicAdd(a.n_live, mask != 0 ? 1u : 0u);
-    if (mask) a.live[pos] = make_uint4(li, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(a.n_live, s_n) : 0u;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < s_n; e += BLOCK) a.live[s_base + e] = s_ent[e];
 }
 
 // HIST: LDS floats per lane for the alpha history (at least the frames of the call).
@@ -218,23 +216,28 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
     }
 }
 
-// Sum the per-brick partials in a fixed order: lane t of component q adds bricks
-// t, t+256, ...; then a fixed tree over the 256 lanes.
-__global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, uint32_t n, double* out)
+// Sum the per-brick partials in a fixed order, in two launches: block b of the first adds
+// the partials of bricks [b * span, (b + 1) * span) (lane t takes bricks t, t + 256, ...
+// of the range, then a fixed tree over the 256 lanes); the second adds the block sums the
+// same way.  The result does not depend on scheduling.
+
+__global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, uint32_t n,
+                                                        uint32_t span, double* out)
 {
-    __shared__ double s[256];
-    for (int q = 0; q < 6; ++q) {
-        double acc = 0.0;
-        for (uint32_t b = threadIdx.x; b < n; b += 256) acc += partials[(size_t)b * 6 + q];
-        s[threadIdx.x] = acc;
-        __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[q] = s[0];
+    __shared__ double s[6][256];
+    const uint32_t b0 = blockIdx.x * span;
+    const uint32_t b1 = min(n, b0 + span);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += 256)
+        for (int q = 0; q < 6; ++q) acc[q] += partials[(size_t)b * 6 + q];
+    for (int q = 0; q < 6; ++q) s[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int q = 0; q < 6; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + off];
         __syncthreads();
     }
+    if (threadIdx.x < 6) out[(size_t)blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
 template <int HIST>
@@ -254,15 +257,24 @@ hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipS
 {
     if (a.n_frames > BWD_MAX_FRAMES) return hipErrorInvalidValue;
     if (a.n_items > 0) {
-        hipLaunchKernelGGL(backward_cull_kernel, dim3((a.n_items + BLOCK - 1) / BLOCK), dim3(BLOCK),
-                           0, stream, a);
+        hipLaunchKernelGGL(backward_cull_kernel,
+                           dim3((a.n_items + BWD_CULL_CHUNK - 1) / BWD_CULL_CHUNK), dim3(BLOCK), 0,
+                           stream, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = a.n_frames <= 32 ? launch_backward_hist<32>(a, device, stream)
                              : launch_backward_hist<64>(a, device, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(reduce_xi_kernel, dim3(1), dim3(256), 0, stream, a.partials, a.n_items, d_xi);
+    // stage 1 writes XI_BLOCKS block sums after the partials (a.partials holds room for them)
+    double* block_sums = a.partials + (size_t)a.n_items * 6;
+    const uint32_t span = (a.n_items + XI_BLOCKS - 1) / XI_BLOCKS;
+    hipLaunchKernelGGL(reduce_xi_kernel, dim3(XI_BLOCKS), dim3(256), 0, stream, a.partials,
+                       a.n_items, span > 0 ? span : 1u, block_sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_xi_kernel, dim3(1), dim3(256), 0, stream, (const double*)block_sums,
+                       (uint32_t)XI_BLOCKS, (uint32_t)XI_BLOCKS, d_xi);
     return hipGetLastError();
 }
 

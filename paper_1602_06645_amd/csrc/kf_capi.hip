@@ -399,12 +399,12 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
 
 // Device image of a plan:
 //   [frame table][scene table of each pass][4 counters per pass: live entries and queue
-//   heads of each kind][live list][pyramids]
+//   heads of each kind][live list][pyramids][weight maps]
 struct DeviceTables {
     std::vector<unsigned char> host;
     size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
-    std::vector<size_t> pass_off, frame_pyr_off;
-    int32_t max_tiles0 = 0;
+    std::vector<size_t> pass_off, frame_pyr_off, frame_wmap_off;
+    int32_t max_tiles0 = 0, max_pixels = 0;
 };
 
 void layout_tables(const BatchPlan& p, DeviceTables* t)
@@ -430,16 +430,25 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
         const int32_t tiles = fc.pyr_w0 * fc.pyr_h0;
         t->max_tiles0 = tiles > t->max_tiles0 ? tiles : t->max_tiles0;
     }
+    off = align(off);
+    for (const auto& fc : p.frames) {
+        t->frame_wmap_off.push_back(off);
+        off = align(off + (size_t)fc.dw * fc.dh * sizeof(float));
+        const int32_t pixels = fc.dw * fc.dh;
+        t->max_pixels = pixels > t->max_pixels ? pixels : t->max_pixels;
+    }
     t->bytes = align(off);
 }
 
 // Fill the host image for device base address `dev` (the frames point at their pyramids).
 void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
 {
-    t->host.assign(t->pyr_off, 0);   // the pyramids are written on the device
+    t->host.assign(t->pyr_off, 0);   // the pyramids and weight maps are written on the device
     std::vector<kf::FrameConsts> frames = p.frames;
-    for (size_t f = 0; f < frames.size(); ++f)
+    for (size_t f = 0; f < frames.size(); ++f) {
         frames[f].pyr = (float2*)(dev + t->frame_pyr_off[f]);
+        frames[f].wmap = (float*)(dev + t->frame_wmap_off[f]);
+    }
     if (!frames.empty())
         memcpy(t->host.data() + t->frames_off, frames.data(), frames.size() * sizeof(kf::FrameConsts));
     for (size_t q = 0; q < p.passes.size(); ++q)
@@ -472,6 +481,8 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
+    KF_HIP(kf::launch_weight_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
+           "weight map launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
     KF_HIP(kf::launch_fill_u32(cnt, 4 * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint2* live = (uint2*)(dev + t.live_off);
@@ -760,12 +771,32 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
     frame_consts(vol->desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc_m, w_max, depth,
                  dw, dh, rgb, cw, ch, &a.frame);
     hipStream_t st = (hipStream_t)stream;
-    a.n_items = a.scene.geom_items;
-    a.status = geom_status;
-    KF_HIP(kf::launch_status(false, a, st), "status launch");
-    a.n_items = a.scene.colour_items;
-    a.status = colour_status;
-    KF_HIP(kf::launch_status(true, a, st), "status launch");
+    // workspace: [frame constants][weight map]
+    const size_t map_off = (sizeof(kf::FrameConsts) + 255) / 256 * 256;
+    unsigned char* ws = nullptr;
+    KF_HIP(hipMallocAsync((void**)&ws, map_off + (size_t)dw * dh * sizeof(float), st), "hipMallocAsync");
+    a.frame.wmap = (float*)(ws + map_off);
+    s = staged_copy(ws, &a.frame, sizeof a.frame, st);
+    hipError_t e = hipSuccess;
+    const char* what = nullptr;
+    if (s == KF_OK) {
+        if ((e = kf::launch_weight_maps((const kf::FrameConsts*)ws, 1, dw * dh, st)) != hipSuccess)
+            what = "weight map launch";
+        if (!what) {
+            a.n_items = a.scene.geom_items;
+            a.status = geom_status;
+            if ((e = kf::launch_status(false, a, st)) != hipSuccess) what = "status launch";
+        }
+        if (!what) {
+            a.n_items = a.scene.colour_items;
+            a.status = colour_status;
+            if ((e = kf::launch_status(true, a, st)) != hipSuccess) what = "status launch";
+        }
+        if (what) s = hip_fail(e, what);
+    }
+    const hipError_t fe = hipFreeAsync(ws, st);
+    if (s != KF_OK) return s;
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
     return KF_OK;
 }
 
@@ -844,7 +875,7 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     a.wc0 = w_col0;
     a.grad = grad_rgb_vol;
     a.d_rgb = d_rgb;
-    // workspace: [frames][n_live, queue][live list][partials][pyramids]
+    // workspace: [frames][n_live, queue][live list][partials][pyramids][weight maps]
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     std::vector<kf::FrameConsts> fc((size_t)(n_frames > 0 ? n_frames : 1));
     memset(fc.data(), 0, fc.size() * sizeof(kf::FrameConsts));
@@ -856,7 +887,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     const size_t counters_off = align(frames_off + fc.size() * sizeof(kf::FrameConsts));
     const size_t live_off = align(counters_off + 2 * sizeof(uint32_t));
     const size_t partials_off = align(live_off + (size_t)a.n_items * sizeof(uint4));
-    const size_t pyr_off = align(partials_off + (size_t)(a.n_items > 0 ? a.n_items : 1) * 6 * sizeof(double));
+    // per-brick partials, then the block sums of the first reduction stage
+    const size_t pyr_off = align(partials_off + ((size_t)a.n_items + kf::XI_BLOCKS) * 6 * sizeof(double));
     size_t off = pyr_off;
     int32_t max_tiles0 = 0;
     std::vector<size_t> pyr(fc.size(), 0);
@@ -866,10 +898,19 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
         const int32_t tiles = fc[f].pyr_w0 * fc[f].pyr_h0;
         max_tiles0 = tiles > max_tiles0 ? tiles : max_tiles0;
     }
+    off = align(off);
+    std::vector<size_t> wmap(fc.size(), 0);
+    for (int f = 0; f < n_frames; ++f) {
+        wmap[f] = off;
+        off = align(off + dpix * sizeof(float));
+    }
     const size_t bytes = align(off);
     unsigned char* ws = nullptr;
     KF_HIP(hipMallocAsync((void**)&ws, bytes, st), "hipMallocAsync");
-    for (int f = 0; f < n_frames; ++f) fc[f].pyr = (float2*)(ws + pyr[f]);
+    for (int f = 0; f < n_frames; ++f) {
+        fc[f].pyr = (float2*)(ws + pyr[f]);
+        fc[f].wmap = (float*)(ws + wmap[f]);
+    }
     a.frames = (const kf::FrameConsts*)(ws + frames_off);
     a.n_live = (uint32_t*)(ws + counters_off);
     a.queue = a.n_live + 1;
@@ -884,6 +925,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
         else if ((e = kf::launch_fill_u32((uint32_t*)a.partials, (size_t)a.n_items * 12, 0u, st)) != hipSuccess)
             what = "partial reset";
         else if ((e = kf::launch_pyramids(a.frames, n_frames, max_tiles0, st)) != hipSuccess) what = "pyramid launch";
+        else if ((e = kf::launch_weight_maps(a.frames, n_frames, dw * dh, st)) != hipSuccess)
+            what = "weight map launch";
     }
     if (s == KF_OK && !what) {
         int device = 0;

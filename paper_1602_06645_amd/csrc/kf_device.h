@@ -18,6 +18,7 @@ constexpr int CBX = 8, CBY = 8;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
 constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
+constexpr int XI_BLOCKS = 256;          // first-stage blocks of the adjoint's dxi reduction
 
 // Everything one frame contributes to the per-voxel arithmetic, rounded once from the
 // double-precision values computed on the host.
@@ -34,8 +35,16 @@ struct FrameConsts {
     const float* depth;   // [dh][dw]
     const void* rgb;      // [ch][cw][3], uint8 or float
     float2* pyr;          // min/max depth pyramid of this frame, levels back to back
+    float* wmap;          // [dh][dw] colour weight W of each depth pixel (Eq. 8 normal and
+                          // the viewing ray), or kNoNormal
     int32_t pyr_w0, pyr_h0, pyr_levels;
 };
+
+// Weight-map entry of a pixel without a normal (no depth at the pixel or a neighbour, a
+// neighbour outside the image, or a zero cross product): a signalling-NaN pattern, which
+// no arithmetic result can take, so that every computed weight (NaN included) stays
+// distinguishable from it.
+constexpr uint32_t kNoNormal = 0x7F800001u;
 
 enum PixFmt : int32_t { FMT_RGB8 = 0, FMT_RGBF32 = 1 };
 
@@ -99,7 +108,8 @@ struct BackwardArgs {
     const float* wc0;                 // initial colour weights or NULL
     const float* grad;                // [3][Nc]
     float* d_rgb;                     // [n][ch][cw][3]
-    double* partials;                 // [n_items][6]; zero for bricks never live
+    double* partials;                 // [n_items][6] (zero for bricks never live), then
+                                      // [XI_BLOCKS][6] block sums of the reduction
     uint4* live;                      // (brick, frame mask low, frame mask high, 0)
     uint32_t* n_live;
     uint32_t* queue;

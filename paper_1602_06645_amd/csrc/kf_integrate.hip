@@ -216,7 +216,12 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
                 if ((upd >> kk) & 1u) {
                     const float t = fminf(1.0f, sdf[kk] * c.inv_trunc);
                     const float wn = W[kk] + 1.0f;
-                    F[kk] = F[kk] + (t - F[kk]) / wn;
+                    // F + (t - F) / wn is F itself when t and F are the same float (then
+                    // t - F = +0), except for F = -0: skip the division in that case (free
+                    // space seen again, t = F = 1).
+                    const uint32_t tb = __builtin_bit_cast(uint32_t, t);
+                    const uint32_t fb = __builtin_bit_cast(uint32_t, F[kk]);
+                    if ((tb != fb) | (fb == 0x80000000u)) F[kk] = F[kk] + (t - F[kk]) / wn;
                     W[kk] = fminf(wn, c.w_max);
                 }
             }
@@ -267,8 +272,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
         int st[ZS];
         // (1) Eq. 5-7 and the distance test against sigma.
-        uint32_t uv[ZS];   // depth pixel (u | v << 16) of voxels inside the frustum
-        float dd[ZS];
+        uint32_t poff[ZS];   // byte offset of the depth pixel of voxels in the band
         uint32_t band = 0;
 #pragma unroll
         for (int kk = 0; kk < ZS; ++kk) {
@@ -286,49 +290,21 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             const bool bd = valid & !(dist2 > c.sigma2);
             band |= (uint32_t)bd << kk;
-            uv[kk] = in ? (((uint32_t)(int)px.v << 16) | (uint32_t)(int)px.u) : 0u;
-            dd[kk] = d;
+            poff[kk] = bd ? px.off : kOutside;
             if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
         }
         if (band) {
-            // (2) neighbours (u+1, v) and (u, v+1); a missing neighbour reads as a hole.
-            float d1[ZS], d2[ZS];
-#pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
-                const uint32_t pu = uv[kk] & 0xFFFFu, pv = uv[kk] >> 16;
-                const bool has_nb = ((band >> kk) & 1u) & (pu + 1u < (uint32_t)c.dw) & (pv + 1u < (uint32_t)c.dh);
-                const uint32_t o = (pv * (uint32_t)c.dw + pu) * 4u;
-                d1[kk] = load_f32(depth, has_nb ? o + 4u : kOutside);
-                d2[kk] = load_f32(depth, has_nb ? o + (uint32_t)c.dw * 4u : kOutside);
-            }
-            // (3) Eq. 8 normal; W = unit normal . unit viewing direction (camera -> P).
+            // (2)-(3) W of the voxel's depth pixel (Eq. 8 normal from the neighbours
+            // (u+1, v) and (u, v+1); unit normal . unit viewing direction), computed once
+            // per pixel by weight_map_kernel in the same operations.
+            const __amdgpu_buffer_rsrc_t wmap = image_rsrc(c.wmap, (uint32_t)(c.dw * c.dh) * 4u);
             float wv[ZS];
             uint32_t reach = 0;
 #pragma unroll
             for (int kk = 0; kk < ZS; ++kk) {
-                wv[kk] = 0.0f;
-                if ((band >> kk) & 1u) {
-                    const float u = (float)(uv[kk] & 0xFFFFu), v = (float)(uv[kk] >> 16);
-                    const float d = dd[kk];
-                    const float Px = ((u - c.cx) * c.inv_fx) * d;
-                    const float Py = ((v - c.cy) * c.inv_fy) * d;
-                    const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1[kk];
-                    const float P1y = ((v - c.cy) * c.inv_fy) * d1[kk];
-                    const float P2x = ((u - c.cx) * c.inv_fx) * d2[kk];
-                    const float P2y = ((v + 1.0f - c.cy) * c.inv_fy) * d2[kk];
-                    const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1[kk] - d;
-                    const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2[kk] - d;
-                    const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
-                    const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
-                    const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
-                    const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
-                    if ((int)valid_depth(d1[kk]) & (int)valid_depth(d2[kk]) & (int)(nn > 0.0f)) {
-                        const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
-                        const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
-                        wv[kk] = dp / sqrtf(nn * pp);
-                        reach |= 1u << kk;
-                    }
-                }
+                wv[kk] = load_f32(wmap, poff[kk]);
+                const bool ok = ((band >> kk) & 1u) & (__builtin_bit_cast(uint32_t, wv[kk]) != kNoNormal);
+                reach |= (uint32_t)ok << kk;
             }
             const uint32_t needw = reach & ~wl;
             if (needw) {
@@ -440,40 +416,62 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 }  // namespace
 
+// Each block culls a chunk of CULL_CHUNK consecutive bricks, eight at a time: lanes 0-31
+// of a wave test frames 0-31 of one brick, lanes 32-63 those of the next, and a ballot
+// assembles each brick's frame mask.  The chunk's live entries are gathered in LDS and
+// appended to the list with one atomic per kind and block (geometry from the front,
+// colour from the back), which keeps the list counters uncontended.
+constexpr int CULL_CHUNK = 64;
+
 __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 {
-    const uint32_t item = blockIdx.x * BLOCK + threadIdx.x;
-    uint32_t mask = 0;
-    bool colour = false;
-    if (item < a.n_items) {
-        int s = 0;
-        while (s + 1 < a.n_scenes && a.scenes[s + 1].item_begin <= item) ++s;
-        const SceneDev& sc = a.scenes[s];
-        uint32_t li = item - sc.item_begin;
-        colour = li >= sc.geom_items;
-        if (colour) li -= sc.geom_items;
-        const int32_t* dim = colour ? sc.cdim : sc.gdim;
-        const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
-        const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
-        const int bx = (int)(li % (uint32_t)nb[0]);
-        const int by = (int)((li / (uint32_t)nb[0]) % (uint32_t)nb[1]);
-        const int bz = (int)(li / ((uint32_t)nb[0] * (uint32_t)nb[1]));
-        const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
-        const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
-        const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
-        for (int f = 0; f < sc.n_frames; ++f) {
-            if (a.disable || brick_live(a.frames[sc.frame_begin + f], colour, i0, i1, j0, j1, k0, k1))
-                mask |= 1u << f;
+    __shared__ uint2 s_ent[2][CULL_CHUNK];
+    __shared__ uint32_t s_n[2], s_base[2];
+    if (threadIdx.x < 2) s_n[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int f = lane & 31;
+    const uint32_t first = blockIdx.x * (uint32_t)CULL_CHUNK;
+    for (int r = 0; r < CULL_CHUNK / (BLOCK / 32); ++r) {
+        const uint32_t item = first + (uint32_t)(r * (BLOCK / 32)) + threadIdx.x / 32;
+        bool live = false, colour = false;
+        if (item < a.n_items) {
+            int s = 0;
+            while (s + 1 < a.n_scenes && a.scenes[s + 1].item_begin <= item) ++s;
+            const SceneDev& sc = a.scenes[s];
+            uint32_t li = item - sc.item_begin;
+            colour = li >= sc.geom_items;
+            if (colour) li -= sc.geom_items;
+            if (f < sc.n_frames) {
+                const int32_t* dim = colour ? sc.cdim : sc.gdim;
+                const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
+                const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
+                const int bx = (int)(li % (uint32_t)nb[0]);
+                const int by = (int)((li / (uint32_t)nb[0]) % (uint32_t)nb[1]);
+                const int bz = (int)(li / ((uint32_t)nb[0] * (uint32_t)nb[1]));
+                const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
+                const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
+                const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
+                live = a.disable || brick_live(a.frames[sc.frame_begin + f], colour, i0, i1, j0, j1, k0, k1);
+            }
+        }
+        const uint32_t mask = (uint32_t)(__ballot(live) >> (lane & 32));
+        if (f == 0 && mask != 0) {
+            const int kind = colour ? KIND_COLOUR : KIND_GEOM;
+            s_ent[kind][atomicAdd(&s_n[kind], 1u)] = make_uint2(item, mask);
         }
     }
-    // append the live bricks, geometry from the front and colour from the back of the
-    // list; every lane takes part in both atomics (adding 0 or 1), which the compiler
-    // turns into one atomic per wave and a prefix sum
-    const bool is_g = mask != 0 && !colour, is_c = mask != 0 && colour;
-    const uint32_t pg = atomicAdd(a.n_live + KIND_GEOM, is_g ? 1u : 0u);
-    const uint32_t pc = atomicAdd(a.n_live + KIND_COLOUR, is_c ? 1u : 0u);
-    if (is_g) a.live[pg] = make_uint2(item, mask);
-    if (is_c) a.live[a.n_items - 1u - pc] = make_uint2(item, mask);
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const uint32_t n = s_n[threadIdx.x];
+        s_base[threadIdx.x] = n ? atomicAdd(a.n_live + threadIdx.x, n) : 0u;
+    }
+    __syncthreads();
+    for (int kind = 0; kind < 2; ++kind)
+        for (uint32_t e = threadIdx.x; e < s_n[kind]; e += BLOCK) {
+            const uint32_t pos = s_base[kind] + e;
+            a.live[kind == KIND_GEOM ? pos : a.n_items - 1u - pos] = s_ent[kind][e];
+        }
 }
 
 // ------------------------------------------------------------------- depth pyramid
@@ -522,6 +520,45 @@ __global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* fr
         w = nw;
         h = nh;
     }
+}
+
+// ------------------------------------------------------------------- weight maps
+
+// Colour weight W (Sec. IV.B: Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dot
+// the unit viewing direction from the camera to the back-projected pixel, Eq. 7) of every
+// pixel of one frame (blockIdx.y = frame).  W depends only on the depth pixel, so every
+// colour voxel that looks up a pixel shares it; the operations are those of the
+// per-voxel definition.
+__global__ __launch_bounds__(BLOCK) void weight_map_kernel(const FrameConsts* frames)
+{
+    const FrameConsts& c = frames[blockIdx.y];
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= c.dw * c.dh) return;
+    const int x = p % c.dw, y = p / c.dw;
+    float W = __builtin_bit_cast(float, kNoNormal);
+    const float d = c.depth[p];
+    if (valid_depth(d) && x + 1 < c.dw && y + 1 < c.dh) {
+        const float d1 = c.depth[p + 1], d2 = c.depth[p + c.dw];
+        const float u = (float)x, v = (float)y;
+        const float Px = ((u - c.cx) * c.inv_fx) * d;
+        const float Py = ((v - c.cy) * c.inv_fy) * d;
+        const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1;
+        const float P1y = ((v - c.cy) * c.inv_fy) * d1;
+        const float P2x = ((u - c.cx) * c.inv_fx) * d2;
+        const float P2y = ((v + 1.0f - c.cy) * c.inv_fy) * d2;
+        const float e1x = P1x - Px, e1y = P1y - Py, e1z = d1 - d;
+        const float e2x = P2x - Px, e2y = P2y - Py, e2z = d2 - d;
+        const float Nx = fmaf(e1y, e2z, -(e1z * e2y));
+        const float Ny = fmaf(e1z, e2x, -(e1x * e2z));
+        const float Nz = fmaf(e1x, e2y, -(e1y * e2x));
+        const float nn = fmaf(Nx, Nx, fmaf(Ny, Ny, Nz * Nz));
+        if ((int)valid_depth(d1) & (int)valid_depth(d2) & (int)(nn > 0.0f)) {
+            const float pp = fmaf(Px, Px, fmaf(Py, Py, d * d));
+            const float dp = fmaf(Nx, Px, fmaf(Ny, Py, Nz * d));
+            W = dp / sqrtf(nn * pp);
+        }
+    }
+    c.wmap[p] = W;
 }
 
 // ------------------------------------------------------------------------ integration
@@ -608,10 +645,21 @@ hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int3
     return hipGetLastError();
 }
 
+hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
+                              hipStream_t stream)
+{
+    if (n_frames <= 0 || max_pixels <= 0) return hipSuccess;
+    const unsigned bx = (unsigned)((max_pixels + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(weight_map_kernel, dim3(bx, (unsigned)n_frames), dim3(BLOCK), 0, stream,
+                       frames_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
 {
     if (a.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(cull_kernel, dim3((a.n_items + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, a);
+    hipLaunchKernelGGL(cull_kernel, dim3((a.n_items + CULL_CHUNK - 1) / CULL_CHUNK), dim3(BLOCK), 0,
+                       stream, a);
     return hipGetLastError();
 }
 

@@ -10,7 +10,11 @@ namespace kf {
 // tile count among them.
 hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_tiles0,
                            hipStream_t stream);
-// One lane per brick of the pass: append (brick, live-frame mask) entries.
+// Colour weight maps (FrameConsts::wmap) of frames_dev[0 .. n_frames); max_pixels: the
+// largest depth image among them.
+hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
+                              hipStream_t stream);
+// One lane per (brick, frame) of the pass: append (brick, live-frame mask) entries.
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream);
 // Persistent integration over the live entries of one kind (mode: MODE_INTEGRATE or
 // MODE_COUNT; kind: KIND_GEOM or KIND_COLOUR).

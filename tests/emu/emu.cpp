@@ -2,13 +2,45 @@
 // against emu_shim.h, with a fiber scheduler standing in for waves and blocks.
 #include "emu_shim.h"
 
-#include <ucontext.h>
-
 #include <mutex>
 #include <thread>
 
+// Minimal x86-64 System V context switch: saves the callee-saved registers, MXCSR and the
+// x87 control word on the current stack, stores the stack pointer in *save_sp and resumes
+// the context whose stack pointer is new_sp.
+extern "C" void emu_ctx_switch(void** save_sp, void* new_sp);
+asm(R"(
+.text
+.globl emu_ctx_switch
+.type emu_ctx_switch,@function
+emu_ctx_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    subq $8, %rsp
+    stmxcsr (%rsp)
+    fnstcw 4(%rsp)
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    ldmxcsr (%rsp)
+    fldcw 4(%rsp)
+    addq $8, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+.size emu_ctx_switch, .-emu_ctx_switch
+)");
+
 #if defined(__has_feature)
 #if __has_feature(address_sanitizer)
+#include <sanitizer/asan_interface.h>
 #include <sanitizer/common_interface_defs.h>
 #define EMU_ASAN 1
 #endif
@@ -22,16 +54,16 @@ thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 
 namespace emu {
 
-constexpr size_t kStack = 256 * 1024;
+constexpr size_t kStack = 64 * 1024;
 
 struct Fiber {
-    ucontext_t ctx;
+    void* sp = nullptr;
     char* stack = nullptr;
     bool done = false;
 };
 
 struct Block {
-    ucontext_t sched;
+    void* sched_sp = nullptr;
     std::vector<Fiber> f;
     std::vector<uint64_t> slot[2];
     std::vector<int> par;
@@ -73,7 +105,7 @@ static void to_scheduler(bool finishing)
     void* fake = nullptr;
     __sanitizer_start_switch_fiber(finishing ? nullptr : &fake, B->sched_bottom, B->sched_size);
 #endif
-    swapcontext(&me.ctx, &B->sched);
+    emu_ctx_switch(&me.sp, B->sched_sp);
 #ifdef EMU_ASAN
     __sanitizer_finish_switch_fiber(fake, &B->sched_bottom, &B->sched_size);
 #endif
@@ -91,7 +123,7 @@ void syncthreads()
     while (B->bar_gen == gen) to_scheduler(false);
 }
 
-static void fiber_entry()
+[[noreturn]] static void fiber_entry()
 {
     Block* B = g_blk;
 #ifdef EMU_ASAN
@@ -101,6 +133,21 @@ static void fiber_entry()
     B->f[B->cur].done = true;
     --B->alive;
     to_scheduler(true);
+    abort();   // a finished fiber is never resumed
+}
+
+// Initial stack of a fiber, laid out as emu_ctx_switch expects to find it: control words,
+// six callee-saved registers, then the entry address as the return address (and a zero
+// slot so that the entry sees the stack alignment of a called function).
+static void* fiber_stack_init(char* stack, size_t size)
+{
+    uintptr_t top = ((uintptr_t)(stack + size)) & ~(uintptr_t)15;
+    uint64_t* sp = (uint64_t*)top;
+    *--sp = 0;                              // alignment slot / fake return address
+    *--sp = (uint64_t)(uintptr_t)&fiber_entry;
+    for (int r = 0; r < 6; ++r) *--sp = 0;  // rbp rbx r12 r13 r14 r15
+    *--sp = 0x037F00001F80ull;              // MXCSR 0x1F80 | x87 control word 0x037F << 32
+    return sp;
 }
 
 static void run_block_fibers(Block& B, unsigned n, const std::function<void()>& body)
@@ -118,11 +165,11 @@ static void run_block_fibers(Block& B, unsigned n, const std::function<void()>& 
     for (unsigned t = 0; t < n; ++t) {
         Fiber& fb = B.f[t];
         fb.done = false;
-        getcontext(&fb.ctx);
-        fb.ctx.uc_stack.ss_sp = fb.stack;
-        fb.ctx.uc_stack.ss_size = kStack;
-        fb.ctx.uc_link = nullptr;
-        makecontext(&fb.ctx, fiber_entry, 0);
+#ifdef EMU_ASAN
+        // a finished fiber never unwinds its frames: clear their redzones before reuse
+        __asan_unpoison_memory_region(fb.stack, kStack);
+#endif
+        fb.sp = fiber_stack_init(fb.stack, kStack);
     }
     g_blk = &B;
     while (B.alive > 0) {
@@ -134,7 +181,7 @@ static void run_block_fibers(Block& B, unsigned n, const std::function<void()>& 
             void* fake = nullptr;
             __sanitizer_start_switch_fiber(&fake, B.f[t].stack, kStack);
 #endif
-            swapcontext(&B.sched, &B.f[t].ctx);
+            emu_ctx_switch(&B.sched_sp, B.f[t].sp);
 #ifdef EMU_ASAN
             __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
 #endif
@@ -151,6 +198,8 @@ static bool needs_fibers(const void* k)
 {
     static const void* list[] = {
         (const void*)kf::pyramid_up_kernel,
+        (const void*)kf::cull_kernel,
+        (const void*)kf::backward_cull_kernel,
         (const void*)kf::reduce_xi_kernel,
         (const void*)kf::integrate_kernel<kf::MODE_INTEGRATE, kf::KIND_GEOM>,
         (const void*)kf::integrate_kernel<kf::MODE_INTEGRATE, kf::KIND_COLOUR>,

@@ -113,6 +113,19 @@ inline uint32_t emu_mbcnt_hi(uint32_t m, uint32_t acc)
 #define __builtin_amdgcn_mbcnt_lo(m, a) emu_mbcnt_lo(m, a)
 #define __builtin_amdgcn_mbcnt_hi(m, a) emu_mbcnt_hi(m, a)
 
+inline unsigned long long __ballot(int pred)
+{
+    emu::check_direct("ballot");
+    const int p = emu::next_parity();
+    emu::slots(p)[threadIdx.x] = pred ? 1u : 0u;
+    emu::yield_collective();
+    const unsigned base = threadIdx.x & ~63u;
+    unsigned long long m = 0;
+    for (unsigned l = 0; l < 64; ++l)
+        if (base + l < blockDim.x && !emu::lane_done(base + l) && emu::slots(p)[base + l]) m |= 1ull << l;
+    return m;
+}
+
 inline void __syncthreads() { emu::syncthreads(); }
 
 // ---------------------------------------------------------------- atomics

@@ -89,13 +89,52 @@ def backward_case(spec, fr):
     return {"rgb": rel(d_rgb, want_rgb), "xi": rel(d_xi, want_xi)}
 
 
+def status_case(spec, fr):
+    """kf_debug_status of every frame, each against the state after the frames before it,
+    equals the oracle's outcome codes."""
+    v = Vol(spec)
+    st = O.State(spec, np.float32)
+    keep = []
+    bad = 0
+    for f in range(fr.n):
+        one = fr.select(f)
+        d = np.ascontiguousarray(one.depth[0], np.float32)
+        rgb = np.ascontiguousarray(one.rgb[0])
+        mats = [np.ascontiguousarray(m, np.float64)
+                for m in (fr.K_d, fr.K_rgb, fr.T_rgb_from_d, one.T_world_from_cam[0])]
+        gs = np.empty(v.arrs[0].size, np.uint8)
+        cs = np.empty(v.arrs[2].size, np.uint8)
+        check(lib.kf_debug_status(v.h, d.ctypes.data, d.shape[1], d.shape[0], rgb.ctypes.data,
+                                  L.KF_RGB8 if rgb.dtype == np.uint8 else L.KF_RGBF32,
+                                  rgb.shape[1], rgb.shape[0], *[m.ctypes.data for m in mats],
+                                  float(fr.trunc), float(fr.w_max), gs.ctypes.data,
+                                  cs.ctypes.data, None))
+        ogs, ocs = O.status(spec, fr, st, f)
+        bad += int(np.count_nonzero(gs != np.asarray(ogs).ravel()))
+        bad += int(np.count_nonzero(cs != np.asarray(ocs).ravel()))
+        arr = (L.Scene * 1)(scene(v, one, keep))
+        check(lib.kf_integrate_batch(arr, 1, 1, 0, None))
+        O.integrate(spec, one, st)
+    return bad
+
+
+import time
+T0 = time.time()
+def tick(msg):
+    print(f"{time.time() - T0:7.1f} s {msg}", file=sys.stderr, flush=True)
 out = {}
 spec6, fr6 = configs.tiny(n_frames=6)
 fr6 = fr6.numpy()
 spec32, fr32 = configs.tiny(n_frames=32)
 fr32 = fr32.numpy()
 SPECS = [spec6, spec32]
+tick("inputs")
 out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb())], 32)
+tick("forward")
+out["status_mismatches"] = status_case(spec6, fr6)
+tick("status")
 out["backward_6"] = backward_case(spec6, fr6)
+tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)
+tick("backward 32")
 print("JSON:" + json.dumps(out), flush=True)

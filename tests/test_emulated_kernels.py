@@ -3,8 +3,9 @@ shim with one fiber per GPU thread, wave collectives and barriers switching betw
 them, bounds-checked buffer loads) and run under AddressSanitizer and UBSan.  Checks
 without a GPU that the kernels' logic equals the oracle (bit for bit in the forward, to
 the adjoint tolerance in the backward) and touches no memory outside its buffers: two
-scans in one batch (RGB8 and float images, 6 and 32 frames, 32 frames per pass) and the
-adjoint over 6 and 32 frames (a live frame in bit 31 of a brick's frame mask)."""
+scans in one batch (RGB8 and float images, 6 and 32 frames, 32 frames per pass), the
+per-voxel outcome codes of every frame of a scan, and the adjoint over 6 and 32 frames (a
+live frame in bit 31 of a brick's frame mask)."""
 import json
 import os
 import subprocess
@@ -34,12 +35,14 @@ def emulated(emu_build, tmp_path_factory):
 
 def test_emulated_kernels_match_oracle(emu_build, emulated):
     env = dict(os.environ, LD_PRELOAD=emu_build.asan_runtime(),
-               ASAN_OPTIONS="detect_leaks=0:max_malloc_fill_size=1000000000:malloc_fill_byte=190",
+               ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0:"
+                            "max_malloc_fill_size=1000000000:malloc_fill_byte=190",
                UBSAN_OPTIONS="halt_on_error=1", EMU_THREADS="4")
     r = subprocess.run([sys.executable, os.path.join(EMU, "run_emulated.py"), emulated],
                        env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stderr[-4000:]
     res = json.loads(r.stdout.split("JSON:", 1)[1])
     assert res["forward_mismatches"] == 0
+    assert res["status_mismatches"] == 0
     for case in ("backward_6", "backward_32"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
