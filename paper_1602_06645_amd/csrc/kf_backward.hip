@@ -75,30 +75,58 @@ __device__ __forceinline__ double wave_sum_d(double x)
 
 }  // namespace
 
-// Each block culls a chunk of BWD_CULL_CHUNK consecutive colour bricks, four at a time:
-// one wave per brick and one lane per frame, a ballot giving the brick's live frames.  The
-// chunk's live entries are gathered in LDS and appended with one atomic per block.
-constexpr int BWD_CULL_CHUNK = 64;
+// One block per culling chunk of CHUNK^3 colour bricks: the first wave tests the chunk's
+// voxel box against the frames (one lane per frame); the chunk's bricks are then tested,
+// four at a time (one wave per brick), only for the frames the chunk passed (exact, the
+// chunk test being conservative for every voxel in it), a ballot giving each brick's live
+// frames.  The live entries are gathered in LDS and appended with one atomic per block.
+constexpr int BWD_CHUNK_BRICKS = CHUNK * CHUNK * CHUNK;
 
 __global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
 {
-    __shared__ uint4 s_ent[BWD_CULL_CHUNK];
+    __shared__ uint4 s_ent[BWD_CHUNK_BRICKS];
     __shared__ uint32_t s_n, s_base;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
+    __shared__ unsigned long long s_cmask;
+    const int cc[3] = {(a.cbricks[0] + CHUNK - 1) / CHUNK, (a.cbricks[1] + CHUNK - 1) / CHUNK,
+                       (a.cbricks[2] + CHUNK - 1) / CHUNK};
+    const uint32_t lc = blockIdx.x;
+    const int bx0 = (int)(lc % (uint32_t)cc[0]) * CHUNK;
+    const int by0 = (int)((lc / (uint32_t)cc[0]) % (uint32_t)cc[1]) * CHUNK;
+    const int bz0 = (int)(lc / ((uint32_t)cc[0] * (uint32_t)cc[1])) * CHUNK;
+    const int nbx = min(CHUNK, a.cbricks[0] - bx0), nby = min(CHUNK, a.cbricks[1] - by0);
+    const int nbz = min(CHUNK, a.cbricks[2] - bz0);
     const int f = (int)(threadIdx.x % WAVE);
-    const uint32_t first = blockIdx.x * (uint32_t)BWD_CULL_CHUNK;
-    for (int r = 0; r < BWD_CULL_CHUNK / (BLOCK / WAVE); ++r) {
-        const uint32_t li = first + (uint32_t)(r * (BLOCK / WAVE)) + threadIdx.x / WAVE;
+    if (threadIdx.x < WAVE) {
         bool live = false;
-        if (li < a.n_items && f < a.n_frames) {
-            const int bx = (int)(li % (uint32_t)a.cbricks[0]);
-            const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
-            const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
-            const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
-            const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
-            const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
+        if (f < a.n_frames) {
+            const int i0 = bx0 * CBX, i1 = min(a.cdim[0], (bx0 + nbx) * CBX) - 1;
+            const int j0 = by0 * CBY, j1 = min(a.cdim[1], (by0 + nby) * CBY) - 1;
+            const int k0 = bz0 * ZS, k1 = min(a.cdim[2], (bz0 + nbz) * ZS) - 1;
             live = a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1);
+        }
+        const unsigned long long m = __ballot(live);
+        if (threadIdx.x == 0) {
+            s_cmask = m;
+            s_n = 0;
+        }
+    }
+    __syncthreads();
+    const unsigned long long cmask = s_cmask;
+    if (cmask == 0) return;   // the whole block
+    const int nbr = nbx * nby * nbz;
+    for (int r = 0; r < BWD_CHUNK_BRICKS / (BLOCK / WAVE); ++r) {
+        const int q = r * (BLOCK / WAVE) + (int)(threadIdx.x / WAVE);
+        bool live = false;
+        uint32_t li = 0;
+        if (q < nbr) {
+            const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = bz0 + q / (nbx * nby);
+            li = (uint32_t)bx + (uint32_t)a.cbricks[0] * ((uint32_t)by + (uint32_t)a.cbricks[1] * (uint32_t)bz);
+            if ((cmask >> f) & 1ull) {
+                const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
+                const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
+                const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
+                live = a.disable_cull || brick_live(a.frames[f], true, i0, i1, j0, j1, k0, k1);
+            }
         }
         const unsigned long long mask = __ballot(live);
         if (f == 0 && mask != 0)
@@ -257,9 +285,10 @@ hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipS
 {
     if (a.n_frames > BWD_MAX_FRAMES) return hipErrorInvalidValue;
     if (a.n_items > 0) {
-        hipLaunchKernelGGL(backward_cull_kernel,
-                           dim3((a.n_items + BWD_CULL_CHUNK - 1) / BWD_CULL_CHUNK), dim3(BLOCK), 0,
-                           stream, a);
+        const uint32_t chunks = (uint32_t)((a.cbricks[0] + CHUNK - 1) / CHUNK) *
+                                (uint32_t)((a.cbricks[1] + CHUNK - 1) / CHUNK) *
+                                (uint32_t)((a.cbricks[2] + CHUNK - 1) / CHUNK);
+        hipLaunchKernelGGL(backward_cull_kernel, dim3(chunks), dim3(BLOCK), 0, stream, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = a.n_frames <= 32 ? launch_backward_hist<32>(a, device, stream)

@@ -257,6 +257,12 @@ void scene_dev(const kf_volume* v, int32_t fmt, kf::SceneDev* s)
     s->cbricks[2] = (int32_t)ceil_div(s->cdim[2], kf::ZS);
     s->geom_items = (uint32_t)s->gbricks[0] * (uint32_t)s->gbricks[1] * (uint32_t)s->gbricks[2];
     s->colour_items = (uint32_t)s->cbricks[0] * (uint32_t)s->cbricks[1] * (uint32_t)s->cbricks[2];
+    for (int a = 0; a < 3; ++a) {
+        s->gchunks[a] = (int32_t)ceil_div(s->gbricks[a], kf::CHUNK);
+        s->cchunks[a] = (int32_t)ceil_div(s->cbricks[a], kf::CHUNK);
+    }
+    s->geom_chunks = (uint32_t)s->gchunks[0] * (uint32_t)s->gchunks[1] * (uint32_t)s->gchunks[2];
+    s->colour_chunks = (uint32_t)s->cchunks[0] * (uint32_t)s->cchunks[1] * (uint32_t)s->cchunks[2];
     s->fmt = fmt;
 }
 
@@ -333,6 +339,7 @@ struct BatchPlan {
     std::vector<kf::FrameConsts> frames;            // every frame of every scene
     std::vector<std::vector<kf::SceneDev>> passes;  // scenes with frames in each pass
     std::vector<uint32_t> pass_items;
+    std::vector<uint32_t> pass_chunks;
 };
 
 // Frames a pass can hold: one bit per frame in a brick's live mask.
@@ -378,7 +385,7 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
     if ((double)plan->frames.size() > 1e7) return fail(KF_E_RANGE, "too many frames in one batch");
     for (int32_t f0 = 0; f0 < max_frames; f0 += K) {
         std::vector<kf::SceneDev> pass;
-        uint64_t items = 0;
+        uint64_t items = 0, chunks = 0;
         for (int s = 0; s < n_scenes; ++s) {
             const int32_t nf = scenes[s].n_frames - f0;
             if (nf <= 0) continue;
@@ -387,12 +394,15 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
             d.frame_begin = first[s] + f0;
             d.n_frames = nf < K ? nf : K;
             d.item_begin = (uint32_t)items;
+            d.chunk_begin = (uint32_t)chunks;
             items += (uint64_t)d.geom_items + d.colour_items;
+            chunks += (uint64_t)d.geom_chunks + d.colour_chunks;
             if (items > 2147483647ull) return fail(KF_E_RANGE, "too many work items in one pass");
             pass.push_back(d);
         }
         plan->passes.push_back(pass);
         plan->pass_items.push_back((uint32_t)items);
+        plan->pass_chunks.push_back((uint32_t)chunks);
     }
     return KF_OK;
 }
@@ -496,6 +506,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         c.frames = frames;
         c.n_scenes = (int32_t)p.passes[q].size();
         c.n_items = p.pass_items[q];
+        c.n_chunks = p.pass_chunks[q];
         c.disable = disable;
         c.live = live;
         c.n_live = cnt + 4 * q;

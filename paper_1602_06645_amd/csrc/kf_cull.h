@@ -44,9 +44,9 @@ __device__ inline float2 depth_range(const FrameConsts& c, int u0, int u1, int v
 // frame?  Its voxel centres form a parallelepiped (Eq. 5 is affine in the index), so
 // their depths lie between the corners' and, when all corners are in front of the
 // camera, their projections lie in the corners' bounding box (widened by a pixel for
-// rounding).  A colour voxel needs a depth within sigma of its own z (|p - P| >= |z - d|);
-// a geometry voxel needs a depth no more than trunc in front of it.  1 mm of slack covers
-// the single-precision rounding of z and d.
+// rounding and the approximate reciprocal).  A colour voxel needs a depth within sigma of
+// its own z (|p - P| >= |z - d|); a geometry voxel needs a depth no more than trunc in
+// front of it.  1 mm of slack covers the single-precision rounding of z and d.
 __device__ inline bool brick_live(const FrameConsts& c, bool colour, int i0, int i1, int j0, int j1,
                            int k0, int k1)
 {
@@ -67,7 +67,10 @@ __device__ inline bool brick_live(const FrameConsts& c, bool colour, int i0, int
         zmin = fminf(zmin, Z);
         zmax = fmaxf(zmax, Z);
         if (Z > 1e-3f) {
-            const float x = c.fx * (X / Z) + c.cx, y = c.fy * (Y / Z) + c.cy;
+            // hardware reciprocal (within 1 ulp): its error, ~1e-7 of the pixel coordinate,
+            // is far inside the one-pixel widening of the box below
+            const float rz = __builtin_amdgcn_rcpf(Z);
+            const float x = c.fx * (X * rz) + c.cx, y = c.fy * (Y * rz) + c.cy;
             xmin = fminf(xmin, x);
             xmax = fmaxf(xmax, x);
             ymin = fminf(ymin, y);

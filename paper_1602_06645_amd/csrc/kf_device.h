@@ -19,6 +19,7 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
 constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
 constexpr int XI_BLOCKS = 256;          // first-stage blocks of the adjoint's dxi reduction
+constexpr int CHUNK = 4;                // culling chunks: CHUNK^3 bricks of one kind
 
 // Everything one frame contributes to the per-voxel arithmetic, rounded once from the
 // double-precision values computed on the host.
@@ -56,6 +57,10 @@ struct SceneDev {
     uint32_t item_begin;              // first global brick index of this scene in the pass
     uint32_t geom_items;              // geometry bricks; colour bricks follow them
     uint32_t colour_items;
+    int32_t gchunks[3], cchunks[3];   // culling chunks per axis
+    uint32_t chunk_begin;             // first global chunk index of this scene in the pass
+    uint32_t geom_chunks;             // geometry chunks; colour chunks follow them
+    uint32_t colour_chunks;
     int32_t frame_begin;              // first entry of the frame table used by this pass
     int32_t n_frames;                 // frames of this scene in this pass (<= 32)
     int32_t fmt;                      // PixFmt
@@ -91,6 +96,7 @@ struct CullArgs {
     const FrameConsts* frames;
     int32_t n_scenes;
     uint32_t n_items;                 // bricks of all scenes of the pass
+    uint32_t n_chunks;                // culling chunks of all scenes of the pass
     int32_t disable;                  // 1: every brick is live in every frame
     uint2* live;                      // n_items entries (see IntegrateArgs)
     uint32_t* n_live;                 // [KIND]

@@ -245,6 +245,32 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
 
 // --------------------------------------------------------------- colour (Sec. IV.B)
 
+// HD pixel of a colour voxel centre (Eq. 3-5 composed into one affine map, then Eq. 4's
+// division) and its bilinear cell: inside when the cell's four pixels are in the image.
+struct HdCell {
+    bool inside;
+    int cell;        // index of the cell's top-left pixel's first channel
+    float ax, ay;    // bilinear weights along x and y
+};
+
+template <class C>
+__device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float fk)
+{
+    const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
+    const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
+    const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
+    const float iqz = 1.0f / qz;
+    const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
+    const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
+    const float x0 = floorf(xh), y0 = floorf(yh);
+    HdCell h;
+    h.inside = (qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.cwm2) & (y0 >= 0.0f) & (y0 <= c.chm2);
+    h.ax = xh - x0;
+    h.ay = yh - y0;
+    h.cell = h.inside ? ((int)y0 * c.cw + (int)x0) * 3 : 0;
+    return h;
+}
+
 // Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10, for the frames of mask.
 // Per frame, in stages over the column's eight voxels so that the loads of a stage are in
 // flight together: (1) frustum, depth and sigma tests; (2) the Eq. 8 neighbour depths of
@@ -330,19 +356,12 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                     if constexpr (MODE == MODE_STATUS) st[kk] = 4;
                     if (wv[kk] > c.gate * Wt[kk]) {
                         if constexpr (MODE == MODE_STATUS) st[kk] = 5;
-                        const float fk = (float)(col.k0 + kk);
-                        const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
-                        const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
-                        const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-                        const float iqz = 1.0f / qz;
-                        const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
-                        const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
-                        const float x0 = floorf(xh), y0 = floorf(yh);
-                        if ((qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.cwm2) & (y0 >= 0.0f) & (y0 <= c.chm2)) {
+                        const HdCell h = hd_cell(c, fi, fj, (float)(col.k0 + kk));
+                        if (h.inside) {
                             if constexpr (MODE == MODE_STATUS) st[kk] = 6;
-                            ax[kk] = xh - x0;
-                            ay[kk] = yh - y0;
-                            cell[kk] = ((int)y0 * c.cw + (int)x0) * 3;
+                            cell[kk] = h.cell;
+                            ax[kk] = h.ax;
+                            ay[kk] = h.ay;
                             upd |= 1u << kk;
                         }
                     }
@@ -416,62 +435,82 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 }  // namespace
 
-// Each block culls a chunk of CULL_CHUNK consecutive bricks, eight at a time: lanes 0-31
-// of a wave test frames 0-31 of one brick, lanes 32-63 those of the next, and a ballot
-// assembles each brick's frame mask.  The chunk's live entries are gathered in LDS and
-// appended to the list with one atomic per kind and block (geometry from the front,
-// colour from the back), which keeps the list counters uncontended.
-constexpr int CULL_CHUNK = 64;
+// One block per culling chunk (CHUNK^3 bricks of one kind).  The first 32 lanes test the
+// chunk's voxel box against frames 0-31 of the pass; the chunk's bricks are then tested,
+// eight at a time (32 lanes per brick, one per frame), only for the frames the chunk
+// passed, and a ballot assembles each brick's frame mask.  Skipping those frames is exact:
+// the chunk test is conservative for every voxel of the chunk, as the brick test is for
+// every voxel of the brick.  The live entries are gathered in LDS and appended to the
+// list with one atomic per block (geometry from the front, colour from the back).
+constexpr int CHUNK_BRICKS = CHUNK * CHUNK * CHUNK;
 
 __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 {
-    __shared__ uint2 s_ent[2][CULL_CHUNK];
-    __shared__ uint32_t s_n[2], s_base[2];
-    if (threadIdx.x < 2) s_n[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ uint2 s_ent[CHUNK_BRICKS];
+    __shared__ uint32_t s_n, s_base, s_cmask;
+    const uint32_t chunk = blockIdx.x;
+    int s = 0;
+    while (s + 1 < a.n_scenes && a.scenes[s + 1].chunk_begin <= chunk) ++s;
+    const SceneDev& sc = a.scenes[s];
+    uint32_t lc = chunk - sc.chunk_begin;
+    const bool colour = lc >= sc.geom_chunks;
+    if (colour) lc -= sc.geom_chunks;
+    const int32_t* dim = colour ? sc.cdim : sc.gdim;
+    const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
+    const int32_t* nc = colour ? sc.cchunks : sc.gchunks;
+    const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
+    const int bx0 = (int)(lc % (uint32_t)nc[0]) * CHUNK;
+    const int by0 = (int)((lc / (uint32_t)nc[0]) % (uint32_t)nc[1]) * CHUNK;
+    const int bz0 = (int)(lc / ((uint32_t)nc[0] * (uint32_t)nc[1])) * CHUNK;
+    const int nbx = min(CHUNK, nb[0] - bx0), nby = min(CHUNK, nb[1] - by0), nbz = min(CHUNK, nb[2] - bz0);
+    const FrameConsts* frames = a.frames + sc.frame_begin;
     const int lane = threadIdx.x & (WAVE - 1);
     const int f = lane & 31;
-    const uint32_t first = blockIdx.x * (uint32_t)CULL_CHUNK;
-    for (int r = 0; r < CULL_CHUNK / (BLOCK / 32); ++r) {
-        const uint32_t item = first + (uint32_t)(r * (BLOCK / 32)) + threadIdx.x / 32;
-        bool live = false, colour = false;
-        if (item < a.n_items) {
-            int s = 0;
-            while (s + 1 < a.n_scenes && a.scenes[s + 1].item_begin <= item) ++s;
-            const SceneDev& sc = a.scenes[s];
-            uint32_t li = item - sc.item_begin;
-            colour = li >= sc.geom_items;
-            if (colour) li -= sc.geom_items;
-            if (f < sc.n_frames) {
-                const int32_t* dim = colour ? sc.cdim : sc.gdim;
-                const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
-                const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
-                const int bx = (int)(li % (uint32_t)nb[0]);
-                const int by = (int)((li / (uint32_t)nb[0]) % (uint32_t)nb[1]);
-                const int bz = (int)(li / ((uint32_t)nb[0] * (uint32_t)nb[1]));
+    if (threadIdx.x < WAVE) {
+        bool live = false;
+        if (threadIdx.x < 32 && f < sc.n_frames) {
+            const int i0 = bx0 * BX, i1 = min(dim[0], (bx0 + nbx) * BX) - 1;
+            const int j0 = by0 * BY, j1 = min(dim[1], (by0 + nby) * BY) - 1;
+            const int k0 = bz0 * ZS, k1 = min(dim[2], (bz0 + nbz) * ZS) - 1;
+            live = a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1);
+        }
+        const uint32_t m = (uint32_t)__ballot(live);
+        if (threadIdx.x == 0) {
+            s_cmask = m;
+            s_n = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t cmask = s_cmask;
+    if (cmask == 0) return;   // the whole block: no brick of the chunk is live
+    const int nbr = nbx * nby * nbz;
+    for (int r = 0; r < CHUNK_BRICKS / (BLOCK / 32); ++r) {
+        const int q = r * (BLOCK / 32) + (int)(threadIdx.x / 32);   // brick within the chunk
+        bool live = false;
+        uint32_t li = 0;
+        if (q < nbr) {
+            const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = bz0 + q / (nbx * nby);
+            li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
+            if ((cmask >> f) & 1u) {
                 const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
                 const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
                 const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
-                live = a.disable || brick_live(a.frames[sc.frame_begin + f], colour, i0, i1, j0, j1, k0, k1);
+                live = a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1);
             }
         }
         const uint32_t mask = (uint32_t)(__ballot(live) >> (lane & 32));
         if (f == 0 && mask != 0) {
-            const int kind = colour ? KIND_COLOUR : KIND_GEOM;
-            s_ent[kind][atomicAdd(&s_n[kind], 1u)] = make_uint2(item, mask);
+            const uint32_t item = sc.item_begin + (colour ? sc.geom_items : 0u) + li;
+            s_ent[atomicAdd(&s_n, 1u)] = make_uint2(item, mask);
         }
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-        const uint32_t n = s_n[threadIdx.x];
-        s_base[threadIdx.x] = n ? atomicAdd(a.n_live + threadIdx.x, n) : 0u;
-    }
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(a.n_live + (colour ? KIND_COLOUR : KIND_GEOM), s_n) : 0u;
     __syncthreads();
-    for (int kind = 0; kind < 2; ++kind)
-        for (uint32_t e = threadIdx.x; e < s_n[kind]; e += BLOCK) {
-            const uint32_t pos = s_base[kind] + e;
-            a.live[kind == KIND_GEOM ? pos : a.n_items - 1u - pos] = s_ent[kind][e];
-        }
+    for (uint32_t e = threadIdx.x; e < s_n; e += BLOCK) {
+        const uint32_t pos = s_base + e;
+        a.live[colour ? a.n_items - 1u - pos : pos] = s_ent[e];
+    }
 }
 
 // ------------------------------------------------------------------- depth pyramid
@@ -657,9 +696,8 @@ hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, i
 
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
 {
-    if (a.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(cull_kernel, dim3((a.n_items + CULL_CHUNK - 1) / CULL_CHUNK), dim3(BLOCK), 0,
-                       stream, a);
+    if (a.n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(cull_kernel, dim3(a.n_chunks), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 

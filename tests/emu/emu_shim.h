@@ -150,6 +150,15 @@ inline uint32_t emu_raw_load_b32(emu_rsrc r, uint32_t off, int, int)
 }
 #define __builtin_amdgcn_raw_buffer_load_b32(r, o, s, a) emu_raw_load_b32(r, o, s, a)
 
+// hardware reciprocal (v_rcp_f32, within 1 ulp): the emulation rounds the exact quotient
+// and perturbs it by one ulp away from zero, the far end of the allowed error
+inline float emu_rcpf(float x)
+{
+    const float r = 1.0f / x;
+    return std::isfinite(r) && r != 0.0f ? std::nextafter(r, r > 0 ? INFINITY : -INFINITY) : r;
+}
+#define __builtin_amdgcn_rcpf(x) emu_rcpf(x)
+
 // ---------------------------------------------------------------- runtime API
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorNotSupported = 801 };

@@ -127,14 +127,20 @@ spec6, fr6 = configs.tiny(n_frames=6)
 fr6 = fr6.numpy()
 spec32, fr32 = configs.tiny(n_frames=32)
 fr32 = fr32.numpy()
-SPECS = [spec6, spec32]
+# a third volume with partial bricks and culling chunks on every axis (geometry bricks
+# 16x4x8, colour 8x8x8, chunks of 4^3 bricks), over a box that cuts the scene off-centre
+from kf_synth.scenes import VolumeSpec  # noqa: E402
+spec_odd = VolumeSpec((45, 37, 29), (135, 111, 87), (-0.41, -0.37, -0.46), (0.9, 0.74, 0.58))
+SPECS = [spec6, spec32, spec_odd]
 tick("inputs")
-out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb())], 32)
+out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb()),
+                                          (Vol(spec_odd), fr32)], 8)
 tick("forward")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
 out["backward_6"] = backward_case(spec6, fr6)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)
+out["backward_odd"] = backward_case(spec_odd, fr6)
 tick("backward 32")
 print("JSON:" + json.dumps(out), flush=True)
