@@ -12,8 +12,10 @@ persistent integration launches, geometry bricks then colour bricks).  The metri
 every voxel of both volumes once per frame (the swept voxel updates of KinectFusion-style
 integration).  Besides the headline line the JSON carries: the plain frame-by-frame path
 and the fused/plain speedup, forward + backward time of the differentiable form on the
-first 32 frames, the HBM roofline of the dominant kernel from algorithmic bytes counted by
-the kernel's counting instantiation, and the CPU oracle timed on a sample.
+first 32 frames, the roofline of the dominant kernels (VALU-bound: algorithmic operations
+per pass over the pass's measured duration, with the HBM fraction of the algorithmic bytes
+beside it; both from units of work counted by the kernels' counting instantiation), and the
+CPU oracle timed on a sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--frames N] [--frames-per-pass K]
 """
@@ -30,6 +32,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel updates/s (geometry+colour) & % HBM roofline; fused-vs-plain; fwd+bwd ms"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue peak of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, counting
+# one operation per lane per instruction (a fused multiply-add is one operation, packed
+# FP32 is not used); the 157.3 TFLOP/s headline counts FMA twice and packed FP32 twice.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Arithmetic operations of the method per unit of work, counted on the single-precision
+# operation sequence of the integration (each add, multiply, FMA, division, square root,
+# rounding, comparison or conversion is one operation):
+OPS = {
+    # a geometry voxel-frame in a live brick: Eq. 5 z term (3 FMA; the column terms,
+    # 6 FMA, shared by 8 voxels), 1/Z, 2 mul + 2 FMA + 2 rint, 5 frustum comparisons,
+    # pixel index, 2 validity comparisons, sdf, band comparison
+    "geom_voxel_frame": 21,
+    # a geometry update: min(1, sdf / trunc) (2), W + 1, F + (t - F) / (W + 1) (3), min
+    "geom_update": 7,
+    # a colour voxel-frame in a live brick: as the geometry one up to the depth sample,
+    # then Eq. 7 (6), the difference to the voxel (3), its squared norm (3), comparison
+    "colour_voxel_frame": 32,
+    # a colour gate evaluation (Eq. 10's W against gate * W_pre): mul + comparison
+    "colour_gate": 2,
+    # a colour update: HD pixel (Eq. 2-4 as 9 FMA, 1/q_z, 2 mul + 2 FMA, 2 floor, 5
+    # comparisons, cell index 3), bilinear sample of 3 channels of 8-bit pixels (12
+    # conversions, 12 scalings, 9 lerps of 2), Eq. 9 (alpha: 2, 3 x 2) and Eq. 10 (2)
+    "colour_update": 24 + 12 + 12 + 18 + 2 + 6 + 2,
+    # a depth pixel of the weight map (Eq. 7 at the pixel and 2 neighbours, Eq. 8 cross
+    # product, norms, dot product, square root and division): its own launch
+    "weight_map_pixel": 59,
+}
 WORKLOAD = ("kinect-like scan: geometry 256^3 + colour 512^3 (2x per axis) over 0.75 m, "
             "300 frames of 640x480 float32 depth + 1920x1080 RGB8")
 
@@ -166,7 +196,14 @@ def main() -> int:
     log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, "
         f"integrate kernels {launch_ms:.3f} ms per pass")
     per_launch_bytes = alg_bytes / len(passes)
-    achieved = per_launch_bytes / (launch_ms * 1e-3) / 1e9
+    achieved_gbs = per_launch_bytes / (launch_ms * 1e-3) / 1e9
+    # algorithmic operations of the two integration launches of one pass (the weight maps
+    # are computed by their own launch and are not part of it)
+    alg_ops = (OPS["geom_voxel_frame"] * 512 * int(cnt[6]) + OPS["geom_update"] * int(cnt[0])
+               + OPS["colour_voxel_frame"] * 512 * int(cnt[7]) + OPS["colour_gate"] * int(cnt[2])
+               + OPS["colour_update"] * int(cnt[4]))
+    per_launch_ops = alg_ops / len(passes)
+    achieved_tops = per_launch_ops / (launch_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": value,
@@ -186,8 +223,12 @@ def main() -> int:
                    "rgb": [fr.rgb.shape[2], fr.rgb.shape[1]], "rgb_format": "u8",
                    "trunc_m": fr.trunc, "w_max": fr.w_max, "sigma_m": spec.sigma,
                    "gate": spec.gate},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(K),
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
+                     "unit": "Top/s (FP32 vector operations)",
+                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": measured_traffic(K),
+                     "algorithmic_ops_per_launch": per_launch_ops,
+                     "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved_gbs / HBM_PEAK_GBS},
                      "kernel": "integrate_kernel<0,0> + integrate_kernel<0,1> (geometry and "
                                "colour persistent launches of one fused pass)",
                      "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
