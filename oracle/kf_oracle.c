@@ -297,3 +297,97 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
     free(fc32);
     free(fc64);
 }
+
+/* ---- ray casting (see kf_raycast_body.h for the steps) */
+
+void or_raycast_consts(const or_volume* vol, const double* K, const double* T_world_from_cam,
+                       double delta, or_rc64* out)
+{
+    const double fx = K[0], fy = K[4], cx = K[2], cy = K[5];
+    double R[9], t[3];
+    split_rt(T_world_from_cam, R, t);
+    for (int k = 0; k < 3; ++k) {
+        const double s = vol->extent[k] / vol->gdim[k];
+        const double sc = vol->extent[k] / vol->cdim[k];
+        /* world direction of pixel (x, y) at unit depth: R ((x - cx)/fx, (y - cy)/fy, 1) */
+        const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fy;
+        const double r0 = (R[3 * k + 2] - R[3 * k + 0] * cx / fx) - R[3 * k + 1] * cy / fy;
+        out->Ru[k] = ru;
+        out->Rv[k] = rv;
+        out->R0[k] = r0;
+        out->tw[k] = t[k];
+        /* index coordinates: (p - origin) / s - 1/2 puts voxel i's centre at i */
+        out->a[k] = (t[k] - vol->origin[k]) / s - 0.5;
+        out->Bu[k] = ru / s;
+        out->Bv[k] = rv / s;
+        out->B0[k] = r0 / s;
+        out->ac[k] = (t[k] - vol->origin[k]) / sc - 0.5;
+        out->Bcu[k] = ru / sc;
+        out->Bcv[k] = rv / sc;
+        out->Bc0[k] = r0 / sc;
+        out->inv_s[k] = 1.0 / s;
+        out->gmax[k] = (double)(vol->gdim[k] - 1);
+        out->cmax[k] = (double)(vol->cdim[k] - 1);
+    }
+    out->delta = delta;
+}
+
+#define REAL float
+#define SFX _f32
+#define FMA fmaf
+#define SQRT sqrtf
+#define FLOOR floorf
+#define CEIL ceilf
+#define FMIN fminf
+#define FMAX fmaxf
+#include "kf_raycast_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef SQRT
+#undef FLOOR
+#undef CEIL
+#undef FMIN
+#undef FMAX
+
+#define REAL double
+#define SFX _f64
+#define FMA fma
+#define SQRT sqrt
+#define FLOOR floor
+#define CEIL ceil
+#define FMIN fmin
+#define FMAX fmax
+#include "kf_raycast_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef SQRT
+#undef FLOOR
+#undef CEIL
+#undef FMIN
+#undef FMAX
+
+void or_raycast_f32(const or_volume* vol, const float* tsdf, const float* wg, const float* r,
+                    const float* g, const float* b, const float* wc, const double* K,
+                    const double* T_world_from_cam, double delta, int width,
+                    const int32_t* pixels, int64_t n_pix, float* depth, float* vertex,
+                    float* normal, float* colour)
+{
+    or_rc64 c;
+    or_raycast_consts(vol, K, T_world_from_cam, delta, &c);
+    raycast__f32(vol, &c, tsdf, wg, r, g, b, wc, width, pixels, n_pix, depth, vertex, normal,
+                 colour);
+}
+
+void or_raycast_f64(const or_volume* vol, const float* tsdf, const float* wg, const float* r,
+                    const float* g, const float* b, const float* wc, const double* K,
+                    const double* T_world_from_cam, double delta, int width,
+                    const int32_t* pixels, int64_t n_pix, float* depth, float* vertex,
+                    float* normal, float* colour)
+{
+    or_rc64 c;
+    or_raycast_consts(vol, K, T_world_from_cam, delta, &c);
+    raycast__f64(vol, &c, tsdf, wg, r, g, b, wc, width, pixels, n_pix, depth, vertex, normal,
+                 colour);
+}

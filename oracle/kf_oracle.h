@@ -106,6 +106,41 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
                      const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
                      double* d_xi);
 
+/*
+ * Ray casting of the volumes (the rendering the method uses for live feedback and the
+ * predicted surface of tracking; abstract and Sec. III).  The constants of one camera,
+ * in double before rounding: geometry- and colour-index rays q = a + t (Bu x + Bv y + B0),
+ * the world ray p = tw + t (Ru x + Rv y + R0) (t = camera depth), 1 / voxel size, dim - 1
+ * and the sample spacing delta (metres of camera depth).
+ */
+typedef struct {
+    double a[3], Bu[3], Bv[3], B0[3];
+    double ac[3], Bcu[3], Bcv[3], Bc0[3];
+    double Ru[3], Rv[3], R0[3], tw[3];
+    double inv_s[3], gmax[3], cmax[3];
+    double delta;
+} or_rc64;
+
+void or_raycast_consts(const or_volume* vol, const double* K, const double* T_world_from_cam,
+                       double delta, or_rc64* out);
+
+/*
+ * Ray cast the pixels pixels[0..n_pix) (index y * width + x) of a camera with intrinsics K
+ * and pose T_world_from_cam through the whole volume (tsdf, wg over gdim; r, g, b, wc over
+ * cdim).  Per pixel p: depth[p] (0 = miss), vertex[3p..3p+2] (world), normal[3p..] and
+ * colour[3p..] (zeros when missing).  Steps in kf_raycast_body.h.
+ */
+void or_raycast_f32(const or_volume* vol, const float* tsdf, const float* wg, const float* r,
+                    const float* g, const float* b, const float* wc, const double* K,
+                    const double* T_world_from_cam, double delta, int width,
+                    const int32_t* pixels, int64_t n_pix, float* depth, float* vertex,
+                    float* normal, float* colour);
+void or_raycast_f64(const or_volume* vol, const float* tsdf, const float* wg, const float* r,
+                    const float* g, const float* b, const float* wc, const double* K,
+                    const double* T_world_from_cam, double delta, int width,
+                    const int32_t* pixels, int64_t n_pix, float* depth, float* vertex,
+                    float* normal, float* colour);
+
 #ifdef __cplusplus
 }
 #endif

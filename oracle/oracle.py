@@ -55,6 +55,12 @@ class _FC64(C.Structure):
                           "inv_trunc", "w_max", "sigma2", "gate"]]
 
 
+class _RC64(C.Structure):
+    _fields_ = [(n, C.c_double * 3) for n in ["a", "Bu", "Bv", "B0", "ac", "Bcu", "Bcv", "Bc0",
+                                               "Ru", "Rv", "R0", "tw", "inv_s", "gmax",
+                                               "cmax"]] + [("delta", C.c_double)]
+
+
 _lib = None
 
 
@@ -75,6 +81,14 @@ def lib():
         L.or_backward_f64.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames), p, p,
                                       C.c_int, C.c_int, C.c_int, p, p]
         L.or_backward_f64.restype = None
+        for name in ("or_raycast_f32", "or_raycast_f64"):
+            fn = getattr(L, name)
+            fn.argtypes = [C.POINTER(_Volume)] + [p] * 6 + [p, p, C.c_double, C.c_int, p,
+                                                          C.c_int64, p, p, p, p]
+            fn.restype = None
+        L.or_raycast_consts.argtypes = [C.POINTER(_Volume), p, p, C.c_double,
+                                        C.POINTER(_RC64)]
+        L.or_raycast_consts.restype = None
         _lib = L
     return _lib
 
@@ -209,3 +223,41 @@ def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None,
                           int(cz[0]), int(cz[1]), int(decide_f32), d_rgb.ctypes.data,
                           d_xi.ctypes.data)
     return d_rgb, d_xi
+
+
+def raycast_consts(vol, K, T_world_from_cam, delta: float) -> dict:
+    """The per-camera constants of the ray caster, in double (exposed for tests)."""
+    out = _RC64()
+    Kc, Tc = _c(K, np.float64), _c(T_world_from_cam, np.float64)
+    lib().or_raycast_consts(C.byref(_vol(vol)), Kc.ctypes.data, Tc.ctypes.data, float(delta),
+                            C.byref(out))
+    return {n: (np.array(getattr(out, n)) if isinstance(getattr(out, n), C.Array)
+                else getattr(out, n)) for n, _ in _RC64._fields_}
+
+
+def raycast(vol, state: State, K, T_world_from_cam, width: int, height: int, delta: float,
+            pixels=None, precision: str = "f32") -> dict:
+    """Ray cast a camera (intrinsics K, pose T_world_from_cam) through the whole volume
+    held by `state` (it must cover every z-slab).  pixels: flat indices y * width + x to
+    cast (default: the whole width x height image).  Returns float32 arrays depth [n],
+    vertex, normal and colour [n, 3] (zeros where missing); the whole image is returned
+    with shape [height, width(, 3)] when pixels is None."""
+    if state.gz != (0, vol.gdim[2]) or state.cz != (0, vol.cdim[2]):
+        raise ValueError("ray casting needs the whole volume")
+    full = pixels is None
+    pix = np.arange(width * height, dtype=np.int32) if full else _c(pixels, np.int32)
+    n = pix.size
+    depth = np.zeros(n, np.float32)
+    vertex = np.zeros((n, 3), np.float32)
+    normal = np.zeros((n, 3), np.float32)
+    colour = np.zeros((n, 3), np.float32)
+    arrs = [_c(a, np.float32) for a in state.arrays()]
+    Kc, Tc = _c(K, np.float64), _c(T_world_from_cam, np.float64)
+    fn = lib().or_raycast_f32 if precision == "f32" else lib().or_raycast_f64
+    fn(C.byref(_vol(vol)), *[a.ctypes.data for a in arrs], Kc.ctypes.data, Tc.ctypes.data,
+       float(delta), int(width), pix.ctypes.data, int(n), depth.ctypes.data,
+       vertex.ctypes.data, normal.ctypes.data, colour.ctypes.data)
+    out = {"depth": depth, "vertex": vertex, "normal": normal, "colour": colour}
+    if full:
+        out = {k: v.reshape((height, width) + v.shape[1:]) for k, v in out.items()}
+    return out

@@ -18,7 +18,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 ORACLE = os.path.join(ROOT, "oracle")
-BODY, MAIN = "kf_oracle_body.h", "kf_oracle.c"
+BODY, MAIN, RC = "kf_oracle_body.h", "kf_oracle.c", "kf_raycast_body.h"
 
 # (name, file, original text, mutated text)
 MUTANTS = [
@@ -51,16 +51,28 @@ MUTANTS = [
     ("adjoint_dsy_wrong", MAIN, "double dsy = (1 - ax) * (p01 - p00) + ax * (p11 - p10);", "double dsy = (1 - ay) * (p01 - p00) + ay * (p11 - p10);"),
     ("adjoint_rotation_sign", MAIN, "xi4 += e->q[2] * a[0] - e->q[0] * a[2];", "xi4 += e->q[0] * a[2] - e->q[2] * a[0];"),
     ("adjoint_projection_z_term", MAIN, "a[2] += -gb * (dsx * fc[f].fxr * e->q[0] + dsy * fc[f].fyr * e->q[1])", "a[2] += -gb * (dsx * fc[f].fxr * e->q[0])"),
+    # ray casting
+    ("raycast_trilinear_y_uses_x_fraction", RC, "const REAL c0 = RC_FN(rc_lerp_)(c00, c10, f[1]);", "const REAL c0 = RC_FN(rc_lerp_)(c00, c10, f[0]);"),
+    ("raycast_corner_y_z_swapped", RC, "{0, 1, X, X + 1, XY, XY + 1, XY + X, XY + X + 1}", "{0, 1, XY, XY + 1, X, X + 1, XY + X, XY + X + 1}"),
+    ("raycast_back_face_crossing", RC, "prev_F > (REAL)0 && F < (REAL)0", "prev_F < (REAL)0 && F > (REAL)0"),
+    ("raycast_refinement_wrong_sample", RC, "prev_F / (prev_F - F)", "F / (prev_F - F)"),
+    ("raycast_weights_ignored", RC, "if (!(w[base + off[c]] > 0.0f)) return 0;", ""),
+    ("raycast_colour_in_geometry_index", RC, "qc[k] = FMA(t_hit, bc, c->ac[k]);", "qc[k] = FMA(t_hit, bc, c->a[k]);"),
+    ("raycast_normal_not_scaled", RC, "grad[k] = (Fp - Fm) * c->inv_s[k];", "grad[k] = (Fp - Fm);"),
+    ("raycast_no_half_voxel", MAIN, "out->a[k] = (t[k] - vol->origin[k]) / s - 0.5;", "out->a[k] = (t[k] - vol->origin[k]) / s;"),
+    ("raycast_ray_y_uses_fx", MAIN, "const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fy;", "const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fx;"),
+    ("raycast_vertex_drops_translation", RC, "c->R0[k])), c->tw[k]);", "c->R0[k])), (REAL)0);"),
 ]
 
-PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py")]
+PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py"),
+             os.path.join(HERE, "test_raycast_pins.py")]
 
 
 def _run_mutant(m, workdir):
     name, fname, old, new = m
     src = os.path.join(workdir, name)
     os.makedirs(src)
-    for f in (BODY, MAIN, "kf_oracle.h"):
+    for f in (BODY, MAIN, RC, "kf_oracle.h"):
         shutil.copy(os.path.join(ORACLE, f), src)
     path = os.path.join(src, fname)
     text = open(path).read()
