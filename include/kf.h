@@ -199,6 +199,27 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
                                 const float* grad_rgb_vol, float* d_rgb,
                                 double* d_xi, void* stream);
 
+/*
+ * Ray cast the volumes from a camera (the rendering the method uses for live feedback and
+ * the predicted surface of tracking: abstract and Sec. III).  For pixel (x, y) of a
+ * width x height image with intrinsics K (zero skew, positive focal lengths) and pose
+ * T_world_from_cam (rigid), the ray is sampled every step_m metres of camera depth inside
+ * the volume; the first two consecutive observed samples (all 8 trilinear corner weights
+ * positive) whose trilinear TSDF goes from positive to negative give the surface, refined
+ * linearly between them.  Writes, per pixel (device arrays, caller-owned):
+ *   depth:  [height][width] float32, camera depth of the surface, 0 for no surface;
+ *   vertex: [height][width][3] world point (or NULL to skip);
+ *   normal: [height][width][3] unit normal from central differences of the trilinear TSDF
+ *           (or NULL), zero where a difference sample is unobserved;
+ *   rgb:    [height][width][3] trilinear colour of the colour volume at the surface (or
+ *           NULL), zero unless its 8 corner colour weights are positive.
+ * Both volumes need at least 2 voxels per axis (KF_E_SHAPE); step_m must be finite and
+ * positive; at most 2^20 samples are taken per ray.  Asynchronous on `stream`.
+ */
+kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double K[9],
+                     const double T_world_from_cam[16], double step_m, float* depth,
+                     float* vertex, float* normal, float* rgb, void* stream);
+
 /* Message for a status code (static string). */
 const char* kf_status_str(kf_status s);
 

@@ -109,6 +109,22 @@ class Volume:
             C.c_void_p(rgb.data_ptr()), _rgb_fmt(rgb), rgb.shape[1], rgb.shape[0],
             _ptr(Kd), _ptr(Kr), _ptr(Trd), _ptr(Twc), float(trunc), float(w_max), _stream()))
 
+    def raycast(self, K, T_world_from_cam, width: int, height: int, step_m: float,
+                vertex: bool = True, normal: bool = True, rgb: bool = True) -> dict:
+        """Ray cast the volumes from a camera (kf_raycast): float32 device tensors depth
+        [H,W] (0 = no surface) and, if asked, vertex, normal and rgb [H,W,3]."""
+        dev = self.tsdf.device
+        out = {"depth": torch.empty((height, width), dtype=torch.float32, device=dev)}
+        for name, want in (("vertex", vertex), ("normal", normal), ("rgb", rgb)):
+            if want:
+                out[name] = torch.empty((height, width, 3), dtype=torch.float32, device=dev)
+        Kc, Tc = _mat(K, (3, 3)), _mat(T_world_from_cam, (4, 4))
+        ptr = lambda n: C.c_void_p(out[n].data_ptr()) if n in out else None   # noqa: E731
+        L.check(L.load().kf_raycast(self._h, int(width), int(height), _ptr(Kc), _ptr(Tc),
+                                    float(step_m), ptr("depth"), ptr("vertex"), ptr("normal"),
+                                    ptr("rgb"), _stream()))
+        return out
+
     def status(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
         """Per-voxel outcome codes of one frame (no update): (geometry, colour) uint8."""
         depth = _dev(depth, torch.float32, "depth", 2)

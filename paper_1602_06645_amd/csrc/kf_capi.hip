@@ -951,4 +951,71 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     return KF_OK;
 }
 
+kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double K[9],
+                     const double T_world_from_cam[16], double step_m, float* depth,
+                     float* vertex, float* normal, float* rgb, void* stream)
+{
+    kf_status s;
+    if ((s = check_volume(vol)) != KF_OK) return s;
+    if ((s = check_K(K, "K")) != KF_OK) return s;
+    if ((s = check_rigid(T_world_from_cam, "T_world_from_cam")) != KF_OK) return s;
+    if (!isfinite(step_m) || !(step_m > 0.0)) return fail(KF_E_ARG, "step_m must be finite and > 0");
+    if (width < 1 || height < 1) return fail(KF_E_SHAPE, "image must be at least 1x1");
+    if ((double)width * height * 3.0 > 2147483647.0) return fail(KF_E_RANGE, "image too large");
+    if (!depth) return fail(KF_E_ARG, "depth output is NULL");
+    const kf_volume_desc& d = vol->desc;
+    for (int k = 0; k < 3; ++k)
+        if (d.geom_dim[k] < 2 || d.colour_dim[k] < 2)
+            return fail(KF_E_SHAPE, "ray casting needs at least 2 voxels per axis");
+    // per-camera constants in double, each rounded once
+    const double fx = K[0], fy = K[4], cx = K[2], cy = K[5];
+    double R[9], t[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) R[3 * r + c] = T_world_from_cam[4 * r + c];
+        t[r] = T_world_from_cam[4 * r + 3];
+    }
+    kf::RaycastArgs a;
+    memset(&a, 0, sizeof a);
+    for (int k = 0; k < 3; ++k) {
+        const double sg = d.extent[k] / d.geom_dim[k];
+        const double sc = d.extent[k] / d.colour_dim[k];
+        // world direction of pixel (x, y) at unit camera depth
+        const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fy;
+        const double r0 = (R[3 * k + 2] - R[3 * k + 0] * cx / fx) - R[3 * k + 1] * cy / fy;
+        a.Ru[k] = (float)ru;
+        a.Rv[k] = (float)rv;
+        a.R0[k] = (float)r0;
+        a.tw[k] = (float)t[k];
+        // index coordinates put voxel i's centre at i: (p - origin) / s - 1/2
+        a.a[k] = (float)((t[k] - d.origin[k]) / sg - 0.5);
+        a.Bu[k] = (float)(ru / sg);
+        a.Bv[k] = (float)(rv / sg);
+        a.B0[k] = (float)(r0 / sg);
+        a.ac[k] = (float)((t[k] - d.origin[k]) / sc - 0.5);
+        a.Bcu[k] = (float)(ru / sc);
+        a.Bcv[k] = (float)(rv / sc);
+        a.Bc0[k] = (float)(r0 / sc);
+        a.inv_s[k] = (float)(1.0 / sg);
+        a.gmax[k] = (float)(d.geom_dim[k] - 1);
+        a.cmax[k] = (float)(d.colour_dim[k] - 1);
+        a.gdim[k] = d.geom_dim[k];
+        a.cdim[k] = d.colour_dim[k];
+    }
+    a.delta = (float)step_m;
+    a.width = width;
+    a.height = height;
+    a.tsdf = vol->bufs.tsdf;
+    a.wg = vol->bufs.w_geom;
+    a.r = vol->bufs.r;
+    a.g = vol->bufs.g;
+    a.b = vol->bufs.b;
+    a.wc = vol->bufs.w_col;
+    a.depth = depth;
+    a.vertex = vertex;
+    a.normal = normal;
+    a.rgb = rgb;
+    KF_HIP(kf::launch_raycast(a, (hipStream_t)stream), "ray cast launch");
+    return KF_OK;
+}
+
 }  // extern "C"

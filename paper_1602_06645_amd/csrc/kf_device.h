@@ -141,6 +141,22 @@ __device__ __forceinline__ uint32_t wave_ticket(uint32_t* queue)
     return first_lane_u32(atomicAdd(queue, rank == 0 ? 1u : 0u));
 }
 
+// Ray casting of one camera through a volume (see kf_raycast.hip), rounded once from the
+// double-precision constants the host computes.
+struct RaycastArgs {
+    float a[3], Bu[3], Bv[3], B0[3];     // geometry-index ray q = a + t (Bu x + Bv y + B0)
+    float ac[3], Bcu[3], Bcv[3], Bc0[3]; // colour-index ray
+    float Ru[3], Rv[3], R0[3], tw[3];    // world ray p = tw + t (Ru x + Rv y + R0)
+    float inv_s[3];                      // 1 / geometry voxel size
+    float gmax[3], cmax[3];              // dim - 1
+    float delta;                         // sample spacing (camera depth, metres)
+    int32_t gdim[3], cdim[3];
+    int32_t width, height;
+    const float *tsdf, *wg, *r, *g, *b, *wc;
+    float* depth;                        // [height][width]
+    float *vertex, *normal, *rgb;        // [height][width][3] each, or NULL
+};
+
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.
 __host__ __device__ inline void pyr_level_dims(int32_t w0, int32_t h0, int32_t l, int32_t* w,
                                                int32_t* h, int32_t* offset)

@@ -118,6 +118,33 @@ def status_case(spec, fr):
     return bad
 
 
+def raycast_case(spec, fr):
+    """kf_raycast on the oracle's own integration of the scan equals the oracle's ray cast
+    bit for bit (every output), from an in-scan camera and an off-scan one."""
+    st = O.State(spec, np.float32)
+    O.integrate(spec, fr, st)
+    v = Vol(spec)
+    for a, b in zip(v.arrs, st.arrays()):
+        a[:] = b
+    K = np.array([[131.25, 0, 79.5], [0, 131.25, 59.5], [0, 0, 1.0]])
+    bad = 0
+    cams = (fr.T_world_from_cam[2], fr.T_world_from_cam[0] @ np.diag([1.0, -1.0, -1.0, 1.0]))
+    for ci, T in enumerate(cams):
+        T = np.ascontiguousarray(T, np.float64)
+        W, H = 160, 120
+        outs = {n: np.zeros((H, W, 3) if n != "depth" else (H, W), np.float32)
+                for n in ("depth", "vertex", "normal", "colour")}
+        check(lib.kf_raycast(v.h, W, H, K.ctypes.data, T.ctypes.data, 0.012,
+                             outs["depth"].ctypes.data, outs["vertex"].ctypes.data,
+                             outs["normal"].ctypes.data, outs["colour"].ctypes.data, None))
+        want = O.raycast(spec, st, K, T, W, H, 0.012)
+        for n in outs:
+            bad += int(np.count_nonzero(outs[n].view(np.uint32) != want[n].view(np.uint32)))
+        if ci == 0 and np.count_nonzero(want["depth"]) < 1000:
+            bad += 1   # the in-scan camera must see the surface
+    return bad
+
+
 import time
 T0 = time.time()
 def tick(msg):
@@ -138,6 +165,8 @@ out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.
 tick("forward")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
+out["raycast_mismatches"] = raycast_case(spec6, fr6)
+tick("raycast")
 out["backward_6"] = backward_case(spec6, fr6)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)

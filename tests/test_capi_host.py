@@ -183,6 +183,43 @@ def test_timed_batch_rejects_bad_arguments():
         lib.kf_volume_destroy(h)
 
 
+def test_raycast_rejects_bad_arguments():
+    lib = L.load()
+    h = _volume()
+    try:
+        K = np.array([[131.25, 0, 79.5], [0, 131.25, 59.5], [0, 0, 1.0]])
+        T = np.eye(4)
+        out = C.c_void_p(0x4000)
+
+        def call(K=K, T=T, w=160, hgt=120, step=0.01, depth=out):
+            Kc, Tc = np.ascontiguousarray(K, np.float64), np.ascontiguousarray(T, np.float64)
+            return lib.kf_raycast(h, w, hgt, C.c_void_p(Kc.ctypes.data), C.c_void_p(Tc.ctypes.data),
+                                  step, depth, None, None, None, None)
+        assert call(step=0.0) == L.KF_E_ARG
+        assert call(step=float("nan")) == L.KF_E_ARG
+        assert call(w=0) == L.KF_E_SHAPE
+        assert call(depth=None) == L.KF_E_ARG
+        assert call(K=np.array([[131.25, 0.5, 79.5], [0, 131.25, 59.5], [0, 0, 1.0]])) == L.KF_E_ARG
+        assert call(T=np.diag([1.0, 1.0, 1.2, 1.0])) == L.KF_E_ARG
+        assert call(w=50000, hgt=50000) == L.KF_E_RANGE
+        assert lib.kf_raycast(None, 4, 4, None, None, 0.01, out, None, None, None, None) == L.KF_E_ARG
+    finally:
+        lib.kf_volume_destroy(h)
+    # a volume with a single voxel along an axis cannot be ray cast
+    d = _desc()
+    d.geom_dim[2] = 1
+    bufs = L.VolumeBuffers(*([0x1000] * 6))
+    h1 = C.c_void_p()
+    assert lib.kf_volume_create(C.byref(d), C.byref(bufs), C.byref(h1)) == L.KF_OK
+    try:
+        Kc = np.array([[131.25, 0, 79.5], [0, 131.25, 59.5], [0, 0, 1.0]])
+        Tc = np.eye(4)
+        assert lib.kf_raycast(h1, 8, 8, C.c_void_p(Kc.ctypes.data), C.c_void_p(Tc.ctypes.data),
+                              0.01, C.c_void_p(0x4000), None, None, None, None) == L.KF_E_SHAPE
+    finally:
+        lib.kf_volume_destroy(h1)
+
+
 def test_backward_rejects_bad_arguments():
     lib = L.load()
     d = _desc()
