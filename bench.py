@@ -261,6 +261,30 @@ def main() -> int:
         out["fused_vs_plain"] = plain_wall / (wall / args.steps)
         log(f"plain: {1e3 * plain_wall:.2f} ms per scan; fused speedup {out['fused_vs_plain']:.2f}x")
 
+        # ---- ray casting of the integrated volumes (the scan's poses, depth resolution)
+        step = 0.8 * fr.trunc
+        rc_poses = fr.T_world_from_cam[::10]
+        H, W = fr.depth.shape[1], fr.depth.shape[2]
+        vol.raycast(fr.K_d, rc_poses[0], W, H, step)
+        torch.cuda.synchronize()
+        rc_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(len(rc_poses))]
+        hits = []
+        for (e0, e1), T in zip(rc_ev, rc_poses):
+            e0.record()
+            img = vol.raycast(fr.K_d, T, W, H, step)
+            e1.record()
+            hits.append(img["depth"])
+        torch.cuda.synchronize()
+        rc_ms = float(np.mean([a.elapsed_time(b) for a, b in rc_ev]))
+        hit_frac = float(np.mean([float((d > 0).float().mean()) for d in hits]))
+        out["raycast"] = {"ms_per_image": rc_ms, "rays_per_s": W * H / (rc_ms * 1e-3),
+                          "image": [W, H], "step_m": step, "poses": len(rc_poses),
+                          "hit_fraction": hit_frac,
+                          "outputs": "depth, vertex, normal, rgb (float32)"}
+        log(f"ray cast: {rc_ms:.3f} ms per {W}x{H} image, {hit_frac:.2f} of the rays hit")
+        del hits
+
         # ---- differentiable form: first 32 frames as float images, forward + backward
         nb = min(32, fr.n)
         rgbf = fr.rgb[:nb].to(torch.float32) * torch.tensor(np.float32(1.0 / 255.0), device="cuda")
