@@ -1,5 +1,6 @@
 /*
- * Oracle for the volumetric integration of arXiv 1602.06645 (Sec. III, Sec. IV.A-B).
+ * Oracle for the volumetric integration of arXiv 1602.06645 (Sec. III, Sec. IV.A-B), the
+ * ray casting of its volumes and the per-polygon texture maps of Sec. IV.C (Eq. 11-14).
  *
  * TEST INFRASTRUCTURE ONLY: a plain CPU implementation used by the tests, the smoke
  * check and the benchmark's CPU-baseline leg.  The product library never links or calls
@@ -390,4 +391,88 @@ void or_raycast_f64(const or_volume* vol, const float* tsdf, const float* wg, co
     or_raycast_consts(vol, K, T_world_from_cam, delta, &c);
     raycast__f64(vol, &c, tsdf, wg, r, g, b, wc, width, pixels, n_pix, depth, vertex, normal,
                  colour);
+}
+
+/* ---- per-polygon texture maps and their atlas (see kf_texture_body.h) */
+
+int32_t or_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
+                          int32_t atlas_height, int32_t* rects)
+{
+    int32_t col_x = 0, col_w = 0, y = 0;
+    for (int32_t n = 0; n < n_tri; ++n) {
+        const float* V = tri + 9 * (size_t)n;
+        double d12 = 0.0, d13 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double e1 = (double)V[3 + k] - (double)V[k];
+            const double e2 = (double)V[6 + k] - (double)V[k];
+            d12 += e1 * e1;
+            d13 += e2 * e2;
+        }
+        /* Eq. 11-12, rounded up to whole texels, at least 2 (Eq. 13-14 divide by w-1, h-1) */
+        const double wf = ceil(sqrt(d12) / size_pixel), hf = ceil(sqrt(d13) / size_pixel);
+        if (!(wf <= 65535.0) || !(hf <= 65535.0)) return -1;
+        const int32_t w = wf < 2.0 ? 2 : (int32_t)wf;
+        const int32_t h = hf < 2.0 ? 2 : (int32_t)hf;
+        if (h > atlas_height) return -1;
+        if (y + h > atlas_height) {   /* the column is full: start the next one */
+            col_x += col_w;
+            col_w = 0;
+            y = 0;
+        }
+        rects[4 * n] = col_x;
+        rects[4 * n + 1] = y;
+        rects[4 * n + 2] = w;
+        rects[4 * n + 3] = h;
+        y += h;
+        if (w > col_w) col_w = w;
+    }
+    return col_x + col_w;
+}
+
+#define REAL float
+#define SFX _f32
+#define FMA fmaf
+#define FLOOR floorf
+#define FMIN fminf
+#define FMAX fmaxf
+#define RINT rintf
+#include "kf_texture_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef FLOOR
+#undef FMIN
+#undef FMAX
+#undef RINT
+
+#define REAL double
+#define SFX _f64
+#define FMA fma
+#define FLOOR floor
+#define FMIN fmin
+#define FMAX fmax
+#define RINT rint
+#include "kf_texture_body.h"
+#undef REAL
+#undef SFX
+#undef FMA
+#undef FLOOR
+#undef FMIN
+#undef FMAX
+#undef RINT
+
+void or_texture_generate_f32(const or_volume* vol, const float* r, const float* g,
+                             const float* b, const float* wc, int32_t n_tri, const float* tri,
+                             const int32_t* rects, int32_t atlas_width, float* atlas,
+                             uint8_t* atlas8)
+{
+    texture__f32(vol, r, g, b, wc, n_tri, tri, rects, atlas_width, atlas, atlas8);
+}
+
+void or_texture_generate_f64(const or_volume* vol, const float* r, const float* g,
+                             const float* b, const float* wc, int32_t n_tri, const float* tri,
+                             const int32_t* rects, int32_t atlas_width, float* atlas,
+                             uint8_t* atlas8)
+{
+    texture__f64(vol, r, g, b, wc, n_tri, tri, rects, atlas_width, atlas, atlas8);
 }

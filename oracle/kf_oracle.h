@@ -2,7 +2,9 @@
  * Oracle for the per-frame volumetric integration of "Creating Simplified 3D Models
  * with High Quality Textures" (arXiv 1602.06645): the TSDF geometry volume of Sec. III
  * and the asymmetric colour volume of Sec. IV.B (Eq. 5-10) with the depth-to-HD-RGB
- * mapping of Sec. IV.A (Eq. 1-4), plus the adjoint of the colour update.
+ * mapping of Sec. IV.A (Eq. 1-4), plus the adjoint of the colour update; ray casting of
+ * the two volumes (Sec. III rendering); the per-polygon texture maps of Sec. IV.C
+ * (Eq. 11-14) and their column-wise atlas.
  *
  * TEST INFRASTRUCTURE ONLY.  This is a plain, slow CPU implementation that the test
  * suite, the smoke check and the benchmark's CPU-baseline leg compare the GPU library
@@ -140,6 +142,34 @@ void or_raycast_f64(const or_volume* vol, const float* tsdf, const float* wg, co
                     const double* T_world_from_cam, double delta, int width,
                     const int32_t* pixels, int64_t n_pix, float* depth, float* vertex,
                     float* normal, float* colour);
+
+/*
+ * Per-polygon texture maps and their atlas (Sec. IV.C, Eq. 11-14 and the merging scheme).
+ * tri: [n][3][3] world vertices (V1, V2, V3) of each triangle.  Layout (double, host):
+ * w = max(2, ceil(|V1V2| / size_pixel)), h = max(2, ceil(|V1V3| / size_pixel)); the maps
+ * are placed down a column of an atlas of atlas_height texels, top to bottom, and a new
+ * column starts to the right (at the widest map of the previous column) when the next map
+ * does not fit below.  rects[4n..4n+3] = (x, y, w, h); returns the atlas width, or -1 when a
+ * map is taller than the atlas or a size exceeds 65535.
+ */
+int32_t or_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
+                          int32_t atlas_height, int32_t* rects);
+
+/*
+ * Texel colours: texel (i, j) of triangle n (i < w towards V2, j < h towards V3) is the
+ * world point V1 + i (V2 - V1)/(w - 1) + j (V3 - V1)/(h - 1) (Eq. 13-14), coloured by
+ * trilinear interpolation of the colour volume (zero unless the 8 corner colour weights are
+ * positive).  Writes atlas[(y + j) * atlas_width + x + i][3] (float) and, if atlas8 is not
+ * NULL, rint(255 * min(max(c, 0), 1)) as bytes; other texels are untouched.
+ */
+void or_texture_generate_f32(const or_volume* vol, const float* r, const float* g,
+                             const float* b, const float* wc, int32_t n_tri, const float* tri,
+                             const int32_t* rects, int32_t atlas_width, float* atlas,
+                             uint8_t* atlas8);
+void or_texture_generate_f64(const or_volume* vol, const float* r, const float* g,
+                             const float* b, const float* wc, int32_t n_tri, const float* tri,
+                             const int32_t* rects, int32_t atlas_width, float* atlas,
+                             uint8_t* atlas8);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,6 @@
 /*
  * Ray casting of the geometry and colour volumes, written once and included twice by
- * kf_raycast_oracle.c: REAL = float (the parity precision) and REAL = double (the
+ * kf_oracle.c: REAL = float (the parity precision) and REAL = double (the
  * precision of the closed-form and brute-force checks).  TEST INFRASTRUCTURE ONLY.
  *
  * The method renders the volumes it integrates for live feedback and obtains the

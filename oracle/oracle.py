@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU-baseline
 leg use this module to compute the reference results of the volumetric integration of
 arXiv 1602.06645 (Sec. III TSDF volume; Sec. IV.B colour volume, Eq. 5-10; Sec. IV.A
-depth-to-HD mapping, Eq. 1-4).  The product library never imports it.
+depth-to-HD mapping, Eq. 1-4), the ray casting of the two volumes and the per-polygon
+texture maps of Sec. IV.C (Eq. 11-14).  The product library never imports it.
 """
 from __future__ import annotations
 
@@ -89,6 +90,12 @@ def lib():
         L.or_raycast_consts.argtypes = [C.POINTER(_Volume), p, p, C.c_double,
                                         C.POINTER(_RC64)]
         L.or_raycast_consts.restype = None
+        L.or_texture_layout.argtypes = [C.c_int32, p, C.c_double, C.c_int32, p]
+        L.or_texture_layout.restype = C.c_int32
+        for name in ("or_texture_generate_f32", "or_texture_generate_f64"):
+            fn = getattr(L, name)
+            fn.argtypes = [C.POINTER(_Volume)] + [p] * 4 + [C.c_int32, p, p, C.c_int32, p, p]
+            fn.restype = None
         _lib = L
     return _lib
 
@@ -261,3 +268,41 @@ def raycast(vol, state: State, K, T_world_from_cam, width: int, height: int, del
     if full:
         out = {k: v.reshape((height, width) + v.shape[1:]) for k, v in out.items()}
     return out
+
+
+def texture_layout(tri, size_pixel: float, atlas_height: int):
+    """Texture-map sizes (Eq. 11-12, rounded up, at least 2 x 2) and their column-wise
+    placement in an atlas of atlas_height texels (Sec. IV.C merging).  tri: [n, 3, 3]
+    world vertices (V1, V2, V3).  Returns (rects int32 [n, 4] = x, y, w, h; atlas width),
+    or raises ValueError when a map does not fit."""
+    t = _c(tri, np.float32).reshape(-1, 9)
+    rects = np.zeros((t.shape[0], 4), np.int32)
+    width = lib().or_texture_layout(int(t.shape[0]), t.ctypes.data, float(size_pixel),
+                                    int(atlas_height), rects.ctypes.data)
+    if width < 0:
+        raise ValueError("a texture map is larger than the atlas or 65535 texels")
+    return rects, int(width)
+
+
+def texture(vol, state: State, tri, rects, atlas_width: int, atlas_height: int,
+            precision: str = "f32", atlas=None, atlas8=None):
+    """Texel colours of every triangle's map (Eq. 13-14 and the colour-volume lookup),
+    written at its rect of the atlas.  Returns (atlas float32 [H, W, 3], atlas8 uint8
+    [H, W, 3]); texels outside every rect keep the given arrays' values (default zero)."""
+    if state.cz != (0, vol.cdim[2]):
+        raise ValueError("texture generation needs the whole colour volume")
+    t = _c(tri, np.float32).reshape(-1, 9)
+    rc = _c(rects, np.int32).reshape(-1, 4)
+    if atlas is None:
+        atlas = np.zeros((atlas_height, atlas_width, 3), np.float32)
+    if atlas8 is None:
+        atlas8 = np.zeros((atlas_height, atlas_width, 3), np.uint8)
+    assert atlas.shape == (atlas_height, atlas_width, 3) and atlas.dtype == np.float32
+    assert atlas8.shape == atlas.shape and atlas8.dtype == np.uint8
+    assert atlas.flags.c_contiguous and atlas8.flags.c_contiguous
+    r, g, b, wc = [_c(a, np.float32) for a in state.arrays()[2:]]
+    fn = lib().or_texture_generate_f32 if precision == "f32" else lib().or_texture_generate_f64
+    fn(C.byref(_vol(vol)), r.ctypes.data, g.ctypes.data, b.ctypes.data, wc.ctypes.data,
+       int(t.shape[0]), t.ctypes.data, rc.ctypes.data, int(atlas_width),
+       atlas.ctypes.data, atlas8.ctypes.data)
+    return atlas, atlas8

@@ -18,7 +18,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 ORACLE = os.path.join(ROOT, "oracle")
-BODY, MAIN, RC = "kf_oracle_body.h", "kf_oracle.c", "kf_raycast_body.h"
+BODY, MAIN, RC, TX = "kf_oracle_body.h", "kf_oracle.c", "kf_raycast_body.h", "kf_texture_body.h"
 
 # (name, file, original text, mutated text)
 MUTANTS = [
@@ -62,17 +62,33 @@ MUTANTS = [
     ("raycast_no_half_voxel", MAIN, "out->a[k] = (t[k] - vol->origin[k]) / s - 0.5;", "out->a[k] = (t[k] - vol->origin[k]) / s;"),
     ("raycast_ray_y_uses_fx", MAIN, "const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fy;", "const double ru = R[3 * k + 0] / fx, rv = R[3 * k + 1] / fx;"),
     ("raycast_vertex_drops_translation", RC, "c->R0[k])), c->tw[k]);", "c->R0[k])), (REAL)0);"),
+    ("texture_step_divides_by_w", TX, "/ (REAL)(w - 1);   /* Eq. 13 */", "/ (REAL)w;   /* Eq. 13 */"),
+    ("texture_steps_swapped", TX, "FMA((REAL)j, s2[k], FMA((REAL)i, s1[k]", "FMA((REAL)i, s2[k], FMA((REAL)j, s1[k]"),
+    ("texture_no_half_voxel", TX, "off[k] = (REAL)(-vol->origin[k] / s - 0.5);", "off[k] = (REAL)(-vol->origin[k] / s);"),
+    ("texture_weights_ignored", TX, "if (!(w[base + off[c]] > 0.0f)) return 0;", ""),
+    ("texture_corner_y_z_swapped", TX, "{0, 1, X, X + 1, XY, XY + 1, XY + X, XY + X + 1}", "{0, 1, XY, XY + 1, X, X + 1, XY + X, XY + X + 1}"),
+    ("texture_lerp_y_uses_x_fraction", TX, "TX_FN(tx_lerp_)(c00, c10, f[1])", "TX_FN(tx_lerp_)(c00, c10, f[0])"),
+    ("texture_byte_round_half_up", TX, "RINT(FMIN(FMAX(c[m], (REAL)0), (REAL)1) * (REAL)255)", "FLOOR(FMIN(FMAX(c[m], (REAL)0), (REAL)1) * (REAL)255 + (REAL)0.5)"),
+    ("texture_byte_no_upper_clamp", TX, "RINT(FMIN(FMAX(c[m], (REAL)0), (REAL)1) * (REAL)255)", "RINT(FMIN(FMAX(c[m], (REAL)0), (REAL)2) * (REAL)127)"),
+    ("texture_size_rounds_down", MAIN, "const double wf = ceil(sqrt(d12) / size_pixel)", "const double wf = floor(sqrt(d12) / size_pixel)"),
+    ("texture_height_from_first_edge", MAIN, "const double e2 = (double)V[6 + k] - (double)V[k];", "const double e2 = (double)V[3 + k] - (double)V[k];"),
+    ("texture_layout_breaks_column_early", MAIN, "if (y + h > atlas_height) {", "if (y + h >= atlas_height) {"),
+    ("texture_layout_column_width_last_map", MAIN, "if (w > col_w) col_w = w;", "col_w = w;"),
 ]
 
 PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py"),
-             os.path.join(HERE, "test_raycast_pins.py")]
+             os.path.join(HERE, "test_raycast_pins.py"), os.path.join(HERE, "test_texture_pins.py")]
+# A mistake in a body that only one operation includes runs that operation's pins; a
+# mistake in the shared source or the integration body runs them all.
+PINS_FOR = {RC: [os.path.join(HERE, "test_raycast_pins.py")],
+            TX: [os.path.join(HERE, "test_texture_pins.py")]}
 
 
 def _run_mutant(m, workdir):
     name, fname, old, new = m
     src = os.path.join(workdir, name)
     os.makedirs(src)
-    for f in (BODY, MAIN, RC, "kf_oracle.h"):
+    for f in (BODY, MAIN, RC, TX, "kf_oracle.h"):
         shutil.copy(os.path.join(ORACLE, f), src)
     path = os.path.join(src, fname)
     text = open(path).read()
@@ -83,7 +99,7 @@ def _run_mutant(m, workdir):
                            "-shared", "-fPIC", "-o", lib, os.path.join(src, MAIN), "-lm"])
     env = dict(os.environ, KF_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        *PIN_FILES], cwd=ROOT, env=env, capture_output=True, text=True,
+                        *PINS_FOR.get(fname, PIN_FILES)], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=900)
     return name, r.returncode
 
