@@ -220,6 +220,43 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
                      const double T_world_from_cam[16], double step_m, float* depth,
                      float* vertex, float* normal, float* rgb, void* stream);
 
+/*
+ * Texture-map sizes and their place in an atlas image (Sec. IV.C: Eq. 11-12 and the
+ * merging of the maps into one image).  Host-only, no device work.
+ *   tri:   host float32 [n_tri][3][3], the world vertices (V1, V2, V3) of each triangle;
+ *          V1 maps to the map's top-left texel, V2 to its top-right, V3 to its bottom-left.
+ *   size_pixel: the size of one texel on the model, metres (finite, > 0).
+ *   rects: host int32 [n_tri][4], written: (x, y, w, h) of each map in the atlas, with
+ *          w = max(2, ceil(|V1V2| / size_pixel)) and h = max(2, ceil(|V1V3| / size_pixel))
+ *          (lengths in double from the float vertices).
+ * Maps are placed column-wise from the top-left corner: each below the previous one; when
+ * a map does not fit in the atlas_height rows that remain, a new column starts at the top,
+ * right of the widest map of the previous column.  *atlas_width receives the width the
+ * columns reach (0 for no triangles).  KF_E_RANGE if a map is taller than the atlas or
+ * wider or taller than 65535 texels (rects then holds the maps placed so far).
+ */
+kf_status kf_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
+                            int32_t atlas_height, int32_t* rects, int32_t* atlas_width);
+
+/*
+ * Texel colours of every triangle's texture map from the colour volume (Sec. IV.C,
+ * Eq. 13-14).  Texel (i, j) of the w x h map of triangle n (i < w, j < h) is the world
+ * point V1 + i (V2 - V1) / (w - 1) + j (V3 - V1) / (h - 1), coloured by trilinear
+ * interpolation of the colour volume (zero unless the point lies between the first and
+ * last voxel centres on every axis and the 8 corner colour weights are positive).
+ *   tri:   device float32 [n_tri][3][3] world vertices (as for kf_texture_layout);
+ *   rects: device int32 [n_tri][4] (x, y, w, h); a rect that leaves the atlas or has w or h
+ *          below 2 is skipped (kf_texture_layout never makes one);
+ *   atlas_rgb:  device float32 [atlas_height][atlas_width][3], or NULL;
+ *   atlas_rgb8: device uint8 [atlas_height][atlas_width][3] = rint(255 clamp(c, 0, 1)),
+ *          or NULL (not both NULL).
+ * Only the texels of the maps are written; the rest of the atlas keeps its contents.  The
+ * colour volume needs at least 2 voxels per axis (KF_E_SHAPE).  Asynchronous on `stream`.
+ */
+kf_status kf_texture_generate(kf_volume* vol, int32_t n_tri, const float* tri,
+                              const int32_t* rects, int32_t atlas_width, int32_t atlas_height,
+                              float* atlas_rgb, uint8_t* atlas_rgb8, void* stream);
+
 /* Message for a status code (static string). */
 const char* kf_status_str(kf_status s);
 

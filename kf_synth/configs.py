@@ -8,7 +8,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .scenes import (Frames, Scene, VolumeSpec, orbit_poses, random_scene, render_scan)
+from .scenes import (DEPTH_INTRINSICS, RGB_INTRINSICS, Frames, Scene, VolumeSpec, intrinsics,
+                     orbit_poses, random_scene, render_scan, surface_triangles)
 
 
 def tiny(device="cpu", n_frames: int = 10) -> tuple[VolumeSpec, Frames]:
@@ -17,13 +18,27 @@ def tiny(device="cpu", n_frames: int = 10) -> tuple[VolumeSpec, Frames]:
     10 poses evenly spaced on a 0.8 m orbit; trunc = 3 geometry voxels; w_max = 64."""
     rng = np.random.default_rng(1001)
     vol = VolumeSpec.cube(64, 2, 1.0)
+    poses = orbit_poses(n_frames)
+    fr = render_scan(_tiny_scene(), poses, (160, 120), (320, 240), 0.002, 0.0, rng,
+                     trunc=3 * vol.geom_voxel, w_max=64, device=device)
+    return vol, fr
+
+
+def _tiny_scene() -> Scene:
     sc = Scene(-0.45, np.array([[0.85, 0.8, 0.2], [0.2, 0.3, 0.75]]), noise_seed=11)
     sc.spheres.append((np.array([0.0, 0.0, -0.25]), 0.2, np.array([[0.9, 0.25, 0.2],
                                                                    [0.25, 0.8, 0.35]])))
-    poses = orbit_poses(n_frames)
-    fr = render_scan(sc, poses, (160, 120), (320, 240), 0.002, 0.0, rng,
-                     trunc=3 * vol.geom_voxel, w_max=64, device=device)
-    return vol, fr
+    return sc
+
+
+def tiny_triangles(n_tri: int = 160, edge_px: int = 6, n_frames: int = 10, seed: int = 2001):
+    """Triangles on the surfaces of the tiny() scene (three depth pixels e = 6 apart in its
+    160x120 views, about 3.7 cm at the 0.8 m orbit) and a texel size of 5 mm.  Returns
+    (float32 [n_tri, 3, 3], size_pixel)."""
+    K = intrinsics(*DEPTH_INTRINSICS[(160, 120)])
+    tri = surface_triangles(_tiny_scene(), K, 160, 120, orbit_poses(n_frames), n_tri, edge_px,
+                            np.random.default_rng(seed), box=(-0.5, 0.5))
+    return tri, 0.005
 
 
 def kinect(device="cpu", n_frames: int = 300, gdim: int = 256, ratio: int = 2,
@@ -41,6 +56,26 @@ def kinect(device="cpu", n_frames: int = 300, gdim: int = 256, ratio: int = 2,
     fr = render_scan(sc, poses, depth_size, rgb_size, 0.0012, 0.01, rng,
                      trunc=4 * vol.geom_voxel, w_max=128, device=device)
     return vol, fr
+
+
+def kinect_triangles(n_tri: int = 8192, edge_px: int = 16, n_frames: int = 300,
+                     seed: int = 2002, size: float = 0.75, scene_seed: int = 1002,
+                     device="cpu"):
+    """A mesh-like triangle set on the surfaces of the kinect() scene, for texture maps:
+    n_tri triangles whose vertices are the surface points of three depth pixels e = 16
+    pixels apart (2.4 cm across at the 0.8 m orbit, longer where the view grazes the
+    ground), seen from the first n_frames scan poses, inside the volume's box: a
+    simplified model of a few thousand polygons.  At the default sizes the maps hold
+    about 20 M texels (a 4096-row atlas about 7400 texels wide).  The texel size is the footprint of one HD pixel at the scan distance
+    (0.8 m / f_hd, Sec. IV.C: set by the HD camera's resolution and the scanning distance).
+    Returns (float32 [n_tri, 3, 3] triangles, size_pixel in metres)."""
+    rng = np.random.default_rng(scene_seed)      # the scene and poses of kinect(seed=1002)
+    sc = random_scene(rng, size, 3, 2)
+    poses = orbit_poses(300 if n_frames <= 300 else n_frames, jitter=0.05, rng=rng)[:n_frames]
+    K = intrinsics(*DEPTH_INTRINSICS[(640, 480)])
+    tri = surface_triangles(sc, K, 640, 480, poses, n_tri, edge_px,
+                            np.random.default_rng(seed), box=(-size / 2, size / 2), device=device)
+    return tri, 0.8 / RGB_INTRINSICS[(1920, 1080)][0]
 
 
 def fused(device="cpu", n_frames: int = 256) -> tuple[VolumeSpec, Frames]:

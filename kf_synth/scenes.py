@@ -324,6 +324,84 @@ def render_rgb(scene: Scene, K: np.ndarray, W: int, H: int, T_world_from_rgb: np
     return torch.round(255.0 * torch.clamp(rgb, 0.0, 1.0)).to(torch.uint8)
 
 
+def surface_triangles(scene: Scene, K: np.ndarray, W: int, H: int, poses: np.ndarray,
+                      n_tri: int, edge_px: int, rng: np.random.Generator, box=None,
+                      device="cpu") -> np.ndarray:
+    """Triangles lying on the scene's surfaces, as a mesh of the scan would: from a random
+    pose and a random pixel (x, y), the rays of pixels (x, y), (x + e, y) and (x, y + e)
+    (e = edge_px) are cast, and the three hit points become V1, V2, V3 when all three rays
+    hit the same primitive within range (and, given box = (lo, hi), inside that box, as a
+    mesh extracted from a volume would be).  float32 [n_tri, 3, 3]."""
+    dev = torch.device(device)
+    out = []
+    have = 0
+    while have < n_tri:
+        m = 4 * (n_tri - have) + 64
+        pi = rng.integers(len(poses), size=m)
+        x = rng.integers(0, W - edge_px, size=m).astype(np.float64)
+        y = rng.integers(0, H - edge_px, size=m).astype(np.float64)
+        px = np.stack([np.stack([x, y], 1), np.stack([x + edge_px, y], 1),
+                       np.stack([x, y + edge_px], 1)], 1)                 # [m, 3, 2]
+        dc = np.concatenate([(px[..., :1] - K[0, 2]) / K[0, 0], (px[..., 1:] - K[1, 2]) / K[1, 1],
+                             np.ones(px.shape[:-1] + (1,))], -1)           # [m, 3, 3]
+        R = poses[pi, :3, :3]
+        o = torch.as_tensor(np.repeat(poses[pi, :3, 3][:, None], 3, 1).reshape(-1, 3), device=dev)
+        d = torch.as_tensor(np.einsum("mij,mkj->mki", R, dc).reshape(-1, 3), device=dev)
+        t, pid = _cast_batch(scene, o, d)
+        t, pid = t.reshape(m, 3), pid.reshape(m, 3)
+        ok = (pid[:, 0] >= 0) & (pid[:, 0] == pid[:, 1]) & (pid[:, 0] == pid[:, 2]) & \
+             (t <= MAX_RANGE).all(1)
+        pts = (o + t.reshape(-1, 1) * d).reshape(m, 3, 3)[ok].cpu().numpy()
+        if box is not None:
+            lo, hi = np.asarray(box[0]), np.asarray(box[1])
+            pts = pts[((pts >= lo) & (pts <= hi)).all(axis=(1, 2))]
+        out.append(pts[:n_tri - have])
+        have += len(out[-1])
+    return np.concatenate(out).astype(np.float32)
+
+
+def _cast_batch(scene: Scene, o: torch.Tensor, d: torch.Tensor):
+    """_cast for rays with per-ray origins (o: [n, 3])."""
+    eps = 1e-9
+    dev = d.device
+    best = torch.full(d.shape[:-1], math.inf, dtype=torch.float64, device=dev)
+    pid = torch.full(d.shape[:-1], -1, dtype=torch.int64, device=dev)
+
+    def take(t, k):
+        nonlocal best, pid
+        better = t < best
+        best = torch.where(better, t, best)
+        pid = torch.where(better, torch.full_like(pid, k), pid)
+
+    dz = d[:, 2]
+    t = (scene.plane_z - o[:, 2]) / torch.where(dz.abs() < 1e-300, torch.full_like(dz, 1e-300), dz)
+    take(torch.where(t > eps, t, torch.full_like(t, math.inf)), 0)
+    k = 1
+    for c, r, _ in scene.spheres:
+        oc = o - torch.as_tensor(c, device=dev)
+        a = (d * d).sum(-1)
+        b = (d * oc).sum(-1)
+        cc = (oc * oc).sum(-1) - r * r
+        disc = b * b - a * cc
+        t = (-b - torch.sqrt(torch.clamp(disc, min=0.0))) / a
+        take(torch.where((disc >= 0) & (t > eps), t, torch.full_like(t, math.inf)), k)
+        k += 1
+    for c, h, yaw, _ in scene.boxes:
+        R = torch.as_tensor(rot_z(math.degrees(yaw)), device=dev)
+        ol = (o - torch.as_tensor(c, device=dev)) @ R
+        dl = d @ R
+        dl = torch.where(dl.abs() < 1e-12, torch.full_like(dl, 1e-12), dl)
+        hh = torch.as_tensor(h, device=dev)
+        t1 = (-hh - ol) / dl
+        t2 = (hh - ol) / dl
+        tmin = torch.minimum(t1, t2).amax(-1)
+        tmax = torch.maximum(t1, t2).amin(-1)
+        hit = (tmax >= tmin) & (tmin > eps)
+        take(torch.where(hit, tmin, torch.full_like(tmin, math.inf)), k)
+        k += 1
+    return best, pid
+
+
 def render_scan(scene: Scene, poses: np.ndarray, depth_size, rgb_size, noise_k: float,
                 dropout: float, rng: np.random.Generator, trunc: float, w_max: float,
                 device="cpu", T_rgb_from_d: np.ndarray | None = None) -> Frames:

@@ -125,6 +125,31 @@ class Volume:
                                     ptr("rgb"), _stream()))
         return out
 
+    def texture(self, tri, rects, atlas_width: int, atlas_height: int, rgb: bool = True,
+                rgb8: bool = True, out=None) -> dict:
+        """Texel colours of every triangle's map (kf_texture_generate).  tri: [n,3,3]
+        float32, rects: [n,4] int32 (from texture_layout), both on the volume's device.
+        Returns float32 'rgb' and/or uint8 'rgb8' atlases [atlas_height, atlas_width, 3];
+        texels outside every map are zero (or keep the values of the tensors in `out`)."""
+        dev = self.r.device
+        tri = _dev(tri, torch.float32, "tri", 3)
+        rects = _dev(rects, torch.int32, "rects", 2)
+        if tri.shape[1:] != (3, 3) or rects.shape != (tri.shape[0], 4):
+            raise ValueError("tri must be [n,3,3] and rects [n,4]")
+        res = dict(out or {})
+        shape = (atlas_height, atlas_width, 3)
+        for name, want, dt in (("rgb", rgb, torch.float32), ("rgb8", rgb8, torch.uint8)):
+            if want and name not in res:
+                res[name] = torch.zeros(shape, dtype=dt, device=dev)
+            if name in res and (tuple(res[name].shape) != shape or res[name].dtype != dt
+                                or not res[name].is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {dt} tensor of shape {shape}")
+        ptr = lambda n: C.c_void_p(res[n].data_ptr()) if n in res else None   # noqa: E731
+        L.check(L.load().kf_texture_generate(
+            self._h, int(tri.shape[0]), C.c_void_p(tri.data_ptr()), C.c_void_p(rects.data_ptr()),
+            int(atlas_width), int(atlas_height), ptr("rgb"), ptr("rgb8"), _stream()))
+        return res
+
     def status(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
         """Per-voxel outcome codes of one frame (no update): (geometry, colour) uint8."""
         depth = _dev(depth, torch.float32, "depth", 2)
@@ -139,6 +164,19 @@ class Volume:
             _ptr(Kd), _ptr(Kr), _ptr(Trd), _ptr(Twc), float(trunc), float(w_max),
             C.c_void_p(gs.data_ptr()), C.c_void_p(cs.data_ptr()), _stream()))
         return gs, cs
+
+
+def texture_layout(tri, size_pixel: float, atlas_height: int):
+    """Map sizes and atlas placement (kf_texture_layout, host-only): tri [n,3,3] world
+    vertices.  Returns (rects int32 [n,4] = x, y, w, h; the atlas width)."""
+    t = np.ascontiguousarray(tri.cpu().numpy() if isinstance(tri, torch.Tensor) else tri,
+                             dtype=np.float32).reshape(-1, 3, 3)
+    rects = np.zeros((t.shape[0], 4), np.int32)
+    width = C.c_int32(0)
+    L.check(L.load().kf_texture_layout(int(t.shape[0]), t.ctypes.data_as(C.c_void_p),
+                                       float(size_pixel), int(atlas_height),
+                                       rects.ctypes.data_as(C.c_void_p), C.byref(width)))
+    return rects, int(width.value)
 
 
 class Scan:

@@ -1018,4 +1018,94 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
     return KF_OK;
 }
 
+kf_status kf_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
+                            int32_t atlas_height, int32_t* rects, int32_t* atlas_width)
+{
+    if (n_tri < 0) return fail(KF_E_ARG, "n_tri must be >= 0");
+    if (!atlas_width || (n_tri > 0 && (!tri || !rects))) return fail(KF_E_ARG, "NULL pointer");
+    if (!isfinite(size_pixel) || !(size_pixel > 0.0))
+        return fail(KF_E_ARG, "size_pixel must be finite and > 0");
+    if (atlas_height < 2) return fail(KF_E_SHAPE, "atlas_height must be >= 2");
+    int64_t x = 0, y = 0, column_w = 0;
+    for (int32_t n = 0; n < n_tri; ++n) {
+        const float* V = tri + 9 * (size_t)n;
+        // squared lengths of V1V2 and V1V3, summed x, y, z in double
+        double l12 = 0.0, l13 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double a = (double)V[3 + k] - (double)V[k];
+            const double b = (double)V[6 + k] - (double)V[k];
+            l12 += a * a;
+            l13 += b * b;
+        }
+        // Eq. 11-12: a whole number of texels, rounded up, at least 2 per side
+        const double wd = ceil(sqrt(l12) / size_pixel);
+        const double hd = ceil(sqrt(l13) / size_pixel);
+        if (!(wd <= 65535.0) || !(hd <= 65535.0))
+            return fail(KF_E_RANGE, "triangle %d: map wider or taller than 65535 texels", (int)n);
+        const int64_t w = wd < 2.0 ? 2 : (int64_t)wd;
+        const int64_t h = hd < 2.0 ? 2 : (int64_t)hd;
+        if (h > atlas_height)
+            return fail(KF_E_RANGE, "triangle %d: map of %lld rows exceeds the atlas height",
+                        (int)n, (long long)h);
+        // column-wise from the top left: the next map goes below the previous one, or at the
+        // top of a new column right of the widest map of this one when it does not fit
+        if (y + h > atlas_height) {
+            x += column_w;
+            y = 0;
+            column_w = 0;
+        }
+        if (x + w > 2147483647LL) return fail(KF_E_RANGE, "atlas wider than 2^31 - 1 texels");
+        rects[4 * (size_t)n + 0] = (int32_t)x;
+        rects[4 * (size_t)n + 1] = (int32_t)y;
+        rects[4 * (size_t)n + 2] = (int32_t)w;
+        rects[4 * (size_t)n + 3] = (int32_t)h;
+        y += h;
+        column_w = w > column_w ? w : column_w;
+    }
+    *atlas_width = (int32_t)(x + column_w);
+    return KF_OK;
+}
+
+kf_status kf_texture_generate(kf_volume* vol, int32_t n_tri, const float* tri,
+                              const int32_t* rects, int32_t atlas_width, int32_t atlas_height,
+                              float* atlas_rgb, uint8_t* atlas_rgb8, void* stream)
+{
+    kf_status s;
+    if ((s = check_volume(vol)) != KF_OK) return s;
+    if (n_tri < 0) return fail(KF_E_ARG, "n_tri must be >= 0");
+    if (n_tri > 0 && (!tri || !rects)) return fail(KF_E_ARG, "NULL triangles or rects");
+    if (!atlas_rgb && !atlas_rgb8) return fail(KF_E_ARG, "both atlas outputs are NULL");
+    if (atlas_width < 0 || atlas_height < 0) return fail(KF_E_SHAPE, "negative atlas size");
+    if ((double)atlas_width * atlas_height * 3.0 > 9007199254740992.0)
+        return fail(KF_E_RANGE, "atlas too large");
+    if (n_tri > 2147483647 / 9) return fail(KF_E_RANGE, "too many triangles");
+    const kf_volume_desc& d = vol->desc;
+    for (int k = 0; k < 3; ++k)
+        if (d.colour_dim[k] < 2)
+            return fail(KF_E_SHAPE, "texture lookup needs at least 2 colour voxels per axis");
+    kf::TextureArgs a;
+    memset(&a, 0, sizeof a);
+    for (int k = 0; k < 3; ++k) {
+        const double sc = d.extent[k] / d.colour_dim[k];
+        // colour index of a world point p: p / s - (origin / s + 1/2), voxel i's centre at i
+        a.inv_s[k] = (float)(1.0 / sc);
+        a.off[k] = (float)(-d.origin[k] / sc - 0.5);
+        a.cmax[k] = (float)(d.colour_dim[k] - 1);
+        a.cdim[k] = d.colour_dim[k];
+    }
+    a.n_tri = n_tri;
+    a.atlas_width = atlas_width;
+    a.atlas_height = atlas_height;
+    a.tri = tri;
+    a.rects = rects;
+    a.r = vol->bufs.r;
+    a.g = vol->bufs.g;
+    a.b = vol->bufs.b;
+    a.wc = vol->bufs.w_col;
+    a.atlas = atlas_rgb;
+    a.atlas8 = atlas_rgb8;
+    KF_HIP(kf::launch_texture(a, (hipStream_t)stream), "texture launch");
+    return KF_OK;
+}
+
 }  // extern "C"

@@ -157,6 +157,20 @@ struct RaycastArgs {
     float *vertex, *normal, *rgb;        // [height][width][3] each, or NULL
 };
 
+struct TextureArgs {
+    float inv_s[3];                      // 1 / colour voxel size per axis
+    float off[3];                        // -origin / s - 1/2: colour index of a world point
+    float cmax[3];                       // colour dim - 1
+    int32_t cdim[3];
+    int32_t n_tri;
+    int32_t atlas_width, atlas_height;
+    const float* tri;                    // [n_tri][3][3] world vertices V1, V2, V3
+    const int32_t* rects;                // [n_tri][4]: x, y, w, h of each map in the atlas
+    const float *r, *g, *b, *wc;
+    float* atlas;                        // [atlas_height][atlas_width][3], or NULL
+    uint8_t* atlas8;                     // [atlas_height][atlas_width][3], or NULL
+};
+
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.
 __host__ __device__ inline void pyr_level_dims(int32_t w0, int32_t h0, int32_t l, int32_t* w,
                                                int32_t* h, int32_t* offset)

@@ -30,6 +30,9 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream
 // Ray cast one camera (see kf_raycast.hip).
 hipError_t launch_raycast(const RaycastArgs& a, hipStream_t stream);
 
+// Texel colours of every triangle's texture map (see kf_texture.hip).
+hipError_t launch_texture(const TextureArgs& a, hipStream_t stream);
+
 // Adjoint: cull the colour bricks, integrate the live ones backwards (persistent grid),
 // then sum the per-brick extrinsic partials in a fixed order into d_xi.
 hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipStream_t stream);

@@ -51,6 +51,7 @@ thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 #include "kf_integrate.hip"
 #include "kf_backward.hip"
 #include "kf_raycast.hip"
+#include "kf_texture.hip"
 #include "kf_capi.hip"
 
 namespace emu {

@@ -145,6 +145,51 @@ def raycast_case(spec, fr):
     return bad
 
 
+def texture_case(spec, fr):
+    """kf_texture_layout equals the oracle's layout, and kf_texture_generate on the oracle's
+    own integration of the scan equals the oracle's texels bit for bit (float and bytes),
+    for surface triangles plus triangles leaving the volume and degenerate ones; texels
+    outside the maps and the maps of rects outside the atlas stay untouched."""
+    st = O.State(spec, np.float32)
+    O.integrate(spec, fr, st)
+    v = Vol(spec)
+    for a, b in zip(v.arrs, st.arrays()):
+        a[:] = b
+    tri, size_pixel = configs.tiny_triangles()
+    rng = np.random.default_rng(22)
+    extra = rng.uniform(-0.6, 0.6, (12, 1, 3)) + rng.uniform(-0.1, 0.1, (12, 3, 3))
+    extra = extra.astype(np.float32)                                   # partly outside
+    extra[0, 1] = extra[0, 0]                                          # V1 = V2
+    extra[1, 1:] = extra[1, 0]                                         # a point
+    tri = np.ascontiguousarray(np.concatenate([tri, extra]), np.float32)
+    H = 128
+    bad = 0
+    rects = np.zeros((len(tri), 4), np.int32)
+    width = C.c_int32(0)
+    check(lib.kf_texture_layout(len(tri), tri.ctypes.data, size_pixel, H, rects.ctypes.data,
+                                C.byref(width)))
+    orects, owidth = O.texture_layout(tri, size_pixel, H)
+    bad += int(np.count_nonzero(rects != orects)) + int(width.value != owidth)
+    W = width.value
+    rects_bad = rects.copy()
+    rects_bad[3, 0] = W - 1                       # leaves the atlas: skipped
+    rects_bad[5, 2] = 1                           # narrower than 2: skipped
+    atlas = np.full((H, W, 3), -7.0, np.float32)
+    atlas8 = np.full((H, W, 3), 77, np.uint8)
+    check(lib.kf_texture_generate(v.h, len(tri), tri.ctypes.data, rects_bad.ctypes.data, W, H,
+                                  atlas.ctypes.data, atlas8.ctypes.data, None))
+    keep = np.ones(len(tri), bool)
+    keep[[3, 5]] = False
+    want = np.full((H, W, 3), -7.0, np.float32)
+    want8 = np.full((H, W, 3), 77, np.uint8)
+    O.texture(spec, st, tri[keep], orects[keep], W, H, atlas=want, atlas8=want8)
+    bad += int(np.count_nonzero(atlas.view(np.uint32) != want.view(np.uint32)))
+    bad += int(np.count_nonzero(atlas8 != want8))
+    if np.count_nonzero(want[want != -7.0]) < 20000:
+        bad += 1                                  # most surface texels must be coloured
+    return bad
+
+
 import time
 T0 = time.time()
 def tick(msg):
@@ -167,6 +212,8 @@ out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
 out["raycast_mismatches"] = raycast_case(spec6, fr6)
 tick("raycast")
+out["texture_mismatches"] = texture_case(spec6, fr6)
+tick("texture")
 out["backward_6"] = backward_case(spec6, fr6)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)

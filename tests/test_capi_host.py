@@ -220,6 +220,62 @@ def test_raycast_rejects_bad_arguments():
         lib.kf_volume_destroy(h1)
 
 
+def test_texture_layout_matches_oracle(oracle):
+    """kf_texture_layout is host logic: its rects and atlas width equal the oracle's, bit
+    for bit, for the kinect mesh in several atlas heights and for a ragged random set."""
+    from kf_synth import configs
+    from paper_1602_06645_amd import texture_layout
+    tri, size_pixel = configs.kinect_triangles(n_tri=2048)
+    rng = np.random.default_rng(41)
+    rnd = (rng.uniform(-0.5, 0.5, (500, 1, 3)) + rng.uniform(-0.05, 0.05, (500, 3, 3)))
+    for t, sp, H in ((tri, size_pixel, 4096), (tri, size_pixel, 700), (tri, 2 * size_pixel, 333),
+                     (rnd.astype(np.float32), 0.0013, 200)):
+        rects, W = texture_layout(t, sp, H)
+        orects, oW = oracle.texture_layout(t, sp, H)
+        assert W == oW and np.array_equal(rects, orects)
+        assert len(np.unique(rects[:, 0])) > 1
+
+
+def test_texture_rejects_bad_arguments():
+    lib = L.load()
+    tri = np.zeros((1, 3, 3), np.float32)
+    tri[0, 1, 0] = 1.0
+    rects = np.zeros((1, 4), np.int32)
+    W = C.c_int32(0)
+
+    def lay(n=1, sp=0.01, H=200, t=tri):
+        return lib.kf_texture_layout(n, t.ctypes.data, sp, H, rects.ctypes.data, C.byref(W))
+    assert lay() == L.KF_OK and W.value == 100 and list(rects[0]) == [0, 0, 100, 2]
+    assert lay(n=-1) == L.KF_E_ARG
+    assert lay(sp=0.0) == L.KF_E_ARG and lay(sp=float("inf")) == L.KF_E_ARG
+    assert lay(H=1) == L.KF_E_SHAPE
+    assert lay(H=100, t=tri[:, [0, 2, 1]].copy()) == L.KF_OK          # 100 rows fit exactly
+    assert lay(H=99, t=tri[:, [0, 2, 1]].copy()) == L.KF_E_RANGE      # one row too many
+    assert lay(sp=1e-5) == L.KF_E_RANGE                               # 100000 columns
+    assert lib.kf_texture_layout(0, None, 0.01, 16, None, C.byref(W)) == L.KF_OK and W.value == 0
+    assert lib.kf_texture_layout(1, None, 0.01, 16, None, C.byref(W)) == L.KF_E_ARG
+    h = _volume()
+    p = C.c_void_p(0x4000)
+    try:
+        gen = lib.kf_texture_generate
+        assert gen(h, 1, p, p, 8, 8, None, None, None) == L.KF_E_ARG    # no output
+        assert gen(h, -1, p, p, 8, 8, p, None, None) == L.KF_E_ARG
+        assert gen(h, 1, None, p, 8, 8, p, None, None) == L.KF_E_ARG
+        assert gen(h, 1, p, p, -8, 8, p, None, None) == L.KF_E_SHAPE
+        assert gen(None, 1, p, p, 8, 8, p, None, None) == L.KF_E_ARG
+    finally:
+        lib.kf_volume_destroy(h)
+    d = _desc()
+    d.colour_dim[0] = 1
+    bufs = L.VolumeBuffers(*([0x1000] * 6))
+    h1 = C.c_void_p()
+    assert lib.kf_volume_create(C.byref(d), C.byref(bufs), C.byref(h1)) == L.KF_OK
+    try:
+        assert lib.kf_texture_generate(h1, 1, p, p, 8, 8, p, None, None) == L.KF_E_SHAPE
+    finally:
+        lib.kf_volume_destroy(h1)
+
+
 def test_backward_rejects_bad_arguments():
     lib = L.load()
     d = _desc()
