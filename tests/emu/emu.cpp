@@ -207,6 +207,7 @@ static bool needs_fibers(const void* k)
         (const void*)kf::integrate_kernel<kf::MODE_INTEGRATE, kf::KIND_COLOUR>,
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_GEOM>,
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_COLOUR>,
+        (const void*)kf::texture_kernel,
         (const void*)kf::backward_kernel<32>,
         (const void*)kf::backward_kernel<64>,
     };

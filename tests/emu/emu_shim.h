@@ -128,6 +128,11 @@ inline unsigned long long __ballot(int pred)
 
 inline void __syncthreads() { emu::syncthreads(); }
 
+// every lane of the wave reaches the barrier before any lane goes on
+inline void emu_wave_barrier() { (void)__ballot(1); }
+#define __builtin_amdgcn_wave_barrier() emu_wave_barrier()
+#define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
+
 // ---------------------------------------------------------------- atomics
 inline uint32_t atomicAdd(uint32_t* p, uint32_t v) { return std::atomic_ref<uint32_t>(*p).fetch_add(v); }
 inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v)
