@@ -476,3 +476,15 @@ void or_texture_generate_f64(const or_volume* vol, const float* r, const float* 
 {
     texture__f64(vol, r, g, b, wc, n_tri, tri, rects, atlas_width, atlas, atlas8);
 }
+
+/* ---- marching cubes of the geometry volume (see kf_mesh_body.h) */
+#include "kf_mesh_body.h"
+
+int or_mc_cube_triangles(unsigned inside_mask, int32_t* tri_edges)
+{
+    int t[12][3];
+    const int n = mc_cube_triangles(inside_mask, t);
+    for (int i = 0; i < n; ++i)
+        for (int v = 0; v < 3; ++v) tri_edges[3 * i + v] = t[i][v];
+    return n;
+}

@@ -171,6 +171,22 @@ void or_texture_generate_f64(const or_volume* vol, const float* r, const float* 
                              const int32_t* rects, int32_t atlas_width, float* atlas,
                              uint8_t* atlas8);
 
+/*
+ * Marching cubes of the geometry volume (the mesh extraction of Sec. III, after
+ * KinectFusion; the definition is in kf_mesh_body.h).  tsdf, wg: [Z][Y][X] floats (host).
+ * Writes up to vcap vertices (world, [n][3]: vert32 in FP32 with the canonical operation
+ * order, vert64 in FP64; either may be NULL) and up to tcap triangles ([n][3] vertex
+ * indices); *n_vert and *n_tri receive the full counts.  Returns -1 when they exceed the
+ * capacities (call with zero capacities to size the outputs), else 0.
+ */
+int or_marching_cubes(const or_volume* vol, const float* tsdf, const float* wg, float* vert32,
+                      double* vert64, int64_t vcap, int32_t* tris, int64_t tcap, int64_t* n_vert,
+                      int64_t* n_tri);
+
+/* Triangles (as cube edge ids, [n][3]) of one cube whose inside corners are the set bits of
+ * inside_mask (corner c = x + 2y + 4z); returns n. */
+int or_mc_cube_triangles(unsigned inside_mask, int32_t* tri_edges);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,11 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [C.POINTER(_Volume)] + [p] * 4 + [C.c_int32, p, p, C.c_int32, p, p]
             fn.restype = None
+        L.or_marching_cubes.argtypes = [C.POINTER(_Volume), p, p, p, p, C.c_int64, p,
+                                        C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.or_marching_cubes.restype = C.c_int
+        L.or_mc_cube_triangles.argtypes = [C.c_uint, p]
+        L.or_mc_cube_triangles.restype = C.c_int
         _lib = L
     return _lib
 
@@ -306,3 +311,34 @@ def texture(vol, state: State, tri, rects, atlas_width: int, atlas_height: int,
        int(t.shape[0]), t.ctypes.data, rc.ctypes.data, int(atlas_width),
        atlas.ctypes.data, atlas8.ctypes.data)
     return atlas, atlas8
+
+
+def marching_cubes(vol, tsdf, wg, precision: str = "f32"):
+    """Mesh of the geometry volume (tsdf, wg: flat or [Z,Y,X] float32 arrays).  Returns
+    (vertices [nv, 3] float32 (FP32 arithmetic) or float64 (FP64 arithmetic), triangles
+    [nt, 3] int32 vertex indices)."""
+    f = _c(tsdf, np.float32).ravel()
+    w = _c(wg, np.float32).ravel()
+    assert f.size == w.size == int(np.prod(vol.gdim))
+    nv, nt = C.c_int64(0), C.c_int64(0)
+    L = lib()
+    L.or_marching_cubes(C.byref(_vol(vol)), f.ctypes.data, w.ctypes.data, None, None, 0, None,
+                        0, C.byref(nv), C.byref(nt))
+    tris = np.zeros((nt.value, 3), np.int32)
+    if precision == "f32":
+        verts = np.zeros((nv.value, 3), np.float32)
+        args = (verts.ctypes.data, None)
+    else:
+        verts = np.zeros((nv.value, 3), np.float64)
+        args = (None, verts.ctypes.data)
+    rc = L.or_marching_cubes(C.byref(_vol(vol)), f.ctypes.data, w.ctypes.data, *args,
+                             nv.value, tris.ctypes.data, nt.value, C.byref(nv), C.byref(nt))
+    assert rc == 0
+    return verts, tris
+
+
+def mc_cube_triangles(inside_mask: int) -> np.ndarray:
+    """Triangles of one cube configuration as cube edge ids [n, 3]."""
+    out = np.zeros((12, 3), np.int32)
+    n = lib().or_mc_cube_triangles(int(inside_mask), out.ctypes.data)
+    return out[:n].copy()

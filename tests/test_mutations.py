@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 ORACLE = os.path.join(ROOT, "oracle")
 BODY, MAIN, RC, TX = "kf_oracle_body.h", "kf_oracle.c", "kf_raycast_body.h", "kf_texture_body.h"
+MC = "kf_mesh_body.h"
 
 # (name, file, original text, mutated text)
 MUTANTS = [
@@ -74,21 +75,33 @@ MUTANTS = [
     ("texture_height_from_first_edge", MAIN, "const double e2 = (double)V[6 + k] - (double)V[k];", "const double e2 = (double)V[3 + k] - (double)V[k];"),
     ("texture_layout_breaks_column_early", MAIN, "if (y + h > atlas_height) {", "if (y + h >= atlas_height) {"),
     ("texture_layout_column_width_last_map", MAIN, "if (w > col_w) col_w = w;", "col_w = w;"),
+    ("mesh_zero_counts_inside", MC, "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] < 0.0f)", "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] <= 0.0f)"),
+    ("mesh_interpolation_from_far_end", MC, "const double t64 = (double)tsdf[u] / ((double)tsdf[u] - (double)tsdf[w]);", "const double t64 = (double)tsdf[w] / ((double)tsdf[w] - (double)tsdf[u]);"),
+    ("mesh_no_half_voxel", MC, "c0[k] = vol->origin[k] + 0.5 * s[k];", "c0[k] = vol->origin[k];"),
+    ("mesh_fan_reversed", MC, "tri[n][1] = loop[(c + k) % len];\n            tri[n][2] = loop[(c + k + 1) % len];", "tri[n][1] = loop[(c + k + 1) % len];\n            tri[n][2] = loop[(c + k) % len];"),
+    ("mesh_faces_walked_clockwise", MC, "coord[b] = side ? ccw_pos[i][0] : ccw_neg[i][0];\n                coord[c] = side ? ccw_pos[i][1] : ccw_neg[i][1];", "coord[b] = side ? ccw_neg[i][0] : ccw_pos[i][0];\n                coord[c] = side ? ccw_neg[i][1] : ccw_pos[i][1];"),
+    ("mesh_weights_ignored", MC, "ok &= wg[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] > 0.0f;", "ok &= 1;"),
+    ("mesh_unused_vertices_kept", MC, "if (!used) continue;", ""),
+    ("mesh_edge_id_axes_swapped", MC, "if (d == 0) return 0 + y + 2 * z;", "if (d == 0) return 0 + z + 2 * y;"),
+    ("mesh_fan_from_loop_start", MC, "for (; c < len; ++c) {", "for (; c < 0; ++c) {"),
+    ("mesh_last_cube_column_dropped", MC, "for (int64_t x = 0; x + 1 < X; ++x) {", "for (int64_t x = 0; x + 2 < X; ++x) {"),
 ]
 
 PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py"),
-             os.path.join(HERE, "test_raycast_pins.py"), os.path.join(HERE, "test_texture_pins.py")]
+             os.path.join(HERE, "test_raycast_pins.py"), os.path.join(HERE, "test_texture_pins.py"),
+             os.path.join(HERE, "test_mesh_pins.py")]
 # A mistake in a body that only one operation includes runs that operation's pins; a
 # mistake in the shared source or the integration body runs them all.
 PINS_FOR = {RC: [os.path.join(HERE, "test_raycast_pins.py")],
-            TX: [os.path.join(HERE, "test_texture_pins.py")]}
+            TX: [os.path.join(HERE, "test_texture_pins.py")],
+            MC: [os.path.join(HERE, "test_mesh_pins.py")]}
 
 
 def _run_mutant(m, workdir):
     name, fname, old, new = m
     src = os.path.join(workdir, name)
     os.makedirs(src)
-    for f in (BODY, MAIN, RC, TX, "kf_oracle.h"):
+    for f in (BODY, MAIN, RC, TX, MC, "kf_oracle.h"):
         shutil.copy(os.path.join(ORACLE, f), src)
     path = os.path.join(src, fname)
     text = open(path).read()
