@@ -285,6 +285,29 @@ def main() -> int:
         log(f"ray cast: {rc_ms:.3f} ms per {W}x{H} image, {hit_frac:.2f} of the rays hit")
         del hits
 
+        # ---- marching cubes of the integrated geometry volume
+        verts, tris = vol.mesh()
+        cap = (verts.shape[0], tris.shape[0])
+        torch.cuda.synchronize()
+        mc_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(10)]
+        tm = time.perf_counter()
+        for e0, e1 in mc_ev:
+            e0.record()
+            vol.mesh(capacity=cap)
+            e1.record()
+        torch.cuda.synchronize()
+        mc_wall = (time.perf_counter() - tm) / len(mc_ev)
+        mc_ms = float(np.mean([a.elapsed_time(b) for a, b in mc_ev]))
+        out["mesh"] = {"ms_per_mesh": mc_ms, "wall_ms_per_call": 1e3 * mc_wall,
+                       "vertices": cap[0], "triangles": cap[1],
+                       "voxels_per_s": spec.n_geom / (mc_ms * 1e-3),
+                       "note": "one kf_mesh_extract call: classify, count, scan, read the "
+                               "counts back (one synchronisation), write the mesh"}
+        log(f"marching cubes: {mc_ms:.3f} ms on the GPU ({1e3 * mc_wall:.3f} ms per call), "
+            f"{cap[0]} vertices, {cap[1]} triangles")
+        del verts, tris
+
         # ---- per-polygon texture maps from the integrated colour volume (Sec. IV.C)
         tri, size_pixel = configs.kinect_triangles(n_frames=fr.n)
         AH = 4096

@@ -221,6 +221,28 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
                      float* vertex, float* normal, float* rgb, void* stream);
 
 /*
+ * Marching cubes of the geometry volume: the triangle mesh of the zero level of the TSDF
+ * (Sec. III, after KinectFusion; the mesh the method decimates and textures per polygon).
+ * Cubes are the 2x2x2 groups of voxel centres; only cubes whose 8 voxels are observed
+ * (weight > 0) make triangles; a voxel is inside iff its TSDF is < 0.  Writes, when both
+ * output pointers are given and large enough (device arrays, caller-owned):
+ *   vertices:  float32 [n_vertices][3], world coordinates: one vertex per crossed grid
+ *              edge of a complete cube, linearly interpolated along the edge; ordered by
+ *              (linear index of the edge's lower voxel, axis x, y, z);
+ *   triangles: int32 [n_triangles][3] vertex indices, ordered by cube (linear index of its
+ *              lower corner), counter-clockwise seen from the positive-TSDF side.
+ * counts (host int64 [2]) always receives (n_vertices, n_triangles).  Call with NULL
+ * outputs to size them: returns KF_OK with only the counts; KF_E_RANGE when outputs are
+ * given but smaller than the counts (nothing is written to them).  Synchronises `stream`
+ * once (to read the counts); the outputs are written asynchronously after that.  The
+ * volume needs fewer than 2^31 / 5 voxels (KF_E_RANGE).  Uses a workspace of about 7
+ * bytes per voxel from the stream-ordered allocator.
+ */
+kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capacity,
+                          int32_t* triangles, int64_t triangle_capacity, int64_t counts[2],
+                          void* stream);
+
+/*
  * Texture-map sizes and their place in an atlas image (Sec. IV.C: Eq. 11-12 and the
  * merging of the maps into one image).  Host-only, no device work.
  *   tri:   host float32 [n_tri][3][3], the world vertices (V1, V2, V3) of each triangle;

@@ -54,6 +54,7 @@ SIGNATURES = {
                                         _P, _P, _P, _P, _P, _P, _P, _P]),
     "kf_raycast": (C.c_int, [_P, _I, _I, _P, _P, _D, _P, _P, _P, _P, _P]),
     "kf_texture_layout": (C.c_int, [_I, _P, _D, _I, _P, C.POINTER(_I)]),
+    "kf_mesh_extract": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, _P, _P]),
     "kf_texture_generate": (C.c_int, [_P, _I, _P, _P, _I, _I, _P, _P, _P]),
     "kf_status_str": (C.c_char_p, [C.c_int]),
     "kf_last_error": (C.c_char_p, []),

@@ -150,6 +150,24 @@ class Volume:
             int(atlas_width), int(atlas_height), ptr("rgb"), ptr("rgb8"), _stream()))
         return res
 
+    def mesh(self, capacity=None) -> tuple:
+        """Marching cubes of the geometry volume (kf_mesh_extract): (vertices float32
+        [n,3], triangles int32 [m,3]) device tensors.  Without `capacity` the counts are
+        queried first; with capacity = (n, m) the outputs are allocated at that size and
+        the mesh is extracted in one call (KfError if it does not fit)."""
+        dev = self.tsdf.device
+        counts = np.zeros(2, np.int64)
+        if capacity is None:
+            L.check(L.load().kf_mesh_extract(self._h, None, 0, None, 0,
+                                             counts.ctypes.data_as(C.c_void_p), _stream()))
+            capacity = (int(counts[0]), int(counts[1]))
+        verts = torch.empty((max(capacity[0], 1), 3), dtype=torch.float32, device=dev)
+        tris = torch.empty((max(capacity[1], 1), 3), dtype=torch.int32, device=dev)
+        L.check(L.load().kf_mesh_extract(self._h, C.c_void_p(verts.data_ptr()), int(capacity[0]),
+                                         C.c_void_p(tris.data_ptr()), int(capacity[1]),
+                                         counts.ctypes.data_as(C.c_void_p), _stream()))
+        return verts[:int(counts[0])], tris[:int(counts[1])]
+
     def status(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
         """Per-voxel outcome codes of one frame (no update): (geometry, colour) uint8."""
         depth = _dev(depth, torch.float32, "depth", 2)

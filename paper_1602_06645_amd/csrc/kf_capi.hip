@@ -1018,6 +1018,72 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
     return KF_OK;
 }
 
+kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capacity,
+                          int32_t* triangles, int64_t triangle_capacity, int64_t counts[2],
+                          void* stream)
+{
+    kf_status s;
+    if ((s = check_volume(vol)) != KF_OK) return s;
+    if (!counts) return fail(KF_E_ARG, "counts is NULL");
+    counts[0] = counts[1] = 0;
+    if (vertex_capacity < 0 || triangle_capacity < 0) return fail(KF_E_ARG, "negative capacity");
+    const kf_volume_desc& d = vol->desc;
+    const int64_t n = (int64_t)d.geom_dim[0] * d.geom_dim[1] * d.geom_dim[2];
+    // at most 3 vertices and 5 triangles per voxel, counted in 32 bits
+    if (5 * n > 2147483647LL) return fail(KF_E_RANGE, "volume too large for mesh extraction");
+    if (d.geom_dim[0] < 2 || d.geom_dim[1] < 2 || d.geom_dim[2] < 2) return KF_OK;   // no cubes
+    const hipStream_t st = (hipStream_t)stream;
+    kf::MeshArgs a;
+    memset(&a, 0, sizeof a);
+    for (int k = 0; k < 3; ++k) {
+        a.dim[k] = d.geom_dim[k];
+        const double sz = d.extent[k] / d.geom_dim[k];
+        a.s[k] = (float)sz;
+        a.c[k] = (float)(d.origin[k] + 0.5 * sz);     // world centre of voxel 0
+    }
+    a.n_voxels = (uint32_t)n;
+    a.n_blocks = (uint32_t)((n + 255) / 256);
+    a.tsdf = vol->bufs.tsdf;
+    a.wg = vol->bufs.w_geom;
+    // workspace: cube info, vertex/triangle info, first-vertex indices, block sums, totals
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t cube_off = 0;
+    const size_t info_off = align(cube_off + (size_t)n * sizeof(uint16_t));
+    const size_t voff_off = align(info_off + (size_t)n);
+    const size_t sums_off = align(voff_off + (size_t)n * sizeof(uint32_t));
+    const size_t tot_off = align(sums_off + (size_t)a.n_blocks * 2 * sizeof(uint32_t));
+    const size_t bytes = align(tot_off + 2 * sizeof(uint32_t));
+    unsigned char* ws = nullptr;
+    KF_HIP(hipMallocAsync((void**)&ws, bytes, st), "hipMallocAsync");
+    a.cube = (uint16_t*)(ws + cube_off);
+    a.info = ws + info_off;
+    a.voff = (uint32_t*)(ws + voff_off);
+    a.block_sums = (uint32_t*)(ws + sums_off);
+    a.totals = (uint32_t*)(ws + tot_off);
+    uint32_t totals[2] = {0, 0};
+    hipError_t e = kf::launch_mesh_count(a, st);
+    const char* what = e != hipSuccess ? "mesh count launch" : nullptr;
+    if (!what && (e = hipMemcpyAsync(totals, a.totals, sizeof totals, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        what = "mesh count copy";
+    if (!what && (e = hipStreamSynchronize(st)) != hipSuccess) what = "mesh count synchronisation";
+    bool emit = false;
+    if (!what) {
+        counts[0] = totals[0];
+        counts[1] = totals[1];
+        emit = vertices && triangles && vertex_capacity >= counts[0] && triangle_capacity >= counts[1];
+        a.vertices = vertices;
+        a.triangles = triangles;
+        if (emit && (e = kf::launch_mesh_emit(a, st)) != hipSuccess) what = "mesh emit launch";
+    }
+    const hipError_t fe = hipFreeAsync(ws, st);
+    if (what) return hip_fail(e, what);
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+    if ((vertices || triangles) && !emit)
+        return fail(KF_E_RANGE, "mesh of %lld vertices and %lld triangles exceeds the capacities",
+                    (long long)counts[0], (long long)counts[1]);
+    return KF_OK;
+}
+
 kf_status kf_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
                             int32_t atlas_height, int32_t* rects, int32_t* atlas_width)
 {

@@ -171,6 +171,20 @@ struct TextureArgs {
     uint8_t* atlas8;                     // [atlas_height][atlas_width][3], or NULL
 };
 
+struct MeshArgs {
+    int32_t dim[3];                      // geometry voxels per axis
+    uint32_t n_voxels, n_blocks;         // n_blocks = ceil(n_voxels / 256)
+    float s[3], c[3];                    // voxel size; world centre of voxel 0
+    const float *tsdf, *wg;
+    uint16_t* cube;                      // [n_voxels] complete bit | inside-corner mask
+    uint8_t* info;                       // [n_voxels] vertex axes | triangle count << 3
+    uint32_t* voff;                      // [n_voxels] index of the voxel's first vertex
+    uint32_t* block_sums;                // [n_blocks][2] vertices, triangles (then offsets)
+    uint32_t* totals;                    // [2]
+    float* vertices;                     // [n_vertices][3]
+    int32_t* triangles;                  // [n_triangles][3]
+};
+
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.
 __host__ __device__ inline void pyr_level_dims(int32_t w0, int32_t h0, int32_t l, int32_t* w,
                                                int32_t* h, int32_t* offset)

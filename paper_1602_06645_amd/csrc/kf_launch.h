@@ -33,6 +33,11 @@ hipError_t launch_raycast(const RaycastArgs& a, hipStream_t stream);
 // Texel colours of every triangle's texture map (see kf_texture.hip).
 hipError_t launch_texture(const TextureArgs& a, hipStream_t stream);
 
+// Marching cubes (see kf_mesh.hip): classify, count and scan (totals at a.totals), then
+// write vertices and triangles (needs the outputs of the count step).
+hipError_t launch_mesh_count(const MeshArgs& a, hipStream_t stream);
+hipError_t launch_mesh_emit(const MeshArgs& a, hipStream_t stream);
+
 // Adjoint: cull the colour bricks, integrate the live ones backwards (persistent grid),
 // then sum the per-brick extrinsic partials in a fixed order into d_xi.
 hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipStream_t stream);

@@ -52,6 +52,7 @@ thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 #include "kf_backward.hip"
 #include "kf_raycast.hip"
 #include "kf_texture.hip"
+#include "kf_mesh.hip"
 #include "kf_capi.hip"
 
 namespace emu {
@@ -208,6 +209,10 @@ static bool needs_fibers(const void* k)
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_GEOM>,
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_COLOUR>,
         (const void*)kf::texture_kernel,
+        (const void*)kf::mc_count_kernel,
+        (const void*)kf::mc_scan_blocks_kernel,
+        (const void*)kf::mc_vertices_kernel,
+        (const void*)kf::mc_triangles_kernel,
         (const void*)kf::backward_kernel<32>,
         (const void*)kf::backward_kernel<64>,
     };

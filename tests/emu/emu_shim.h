@@ -22,6 +22,7 @@ using std::min;
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static thread_local
+#define __constant__
 #define address_space(n)
 
 struct dim3 {
@@ -172,7 +173,7 @@ typedef struct emu_event* hipEvent_t;
 typedef struct emu_graph* hipGraph_t;
 typedef struct emu_graph_exec* hipGraphExec_t;
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 };
-enum { hipMemcpyHostToDevice = 1 };
+enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipHostMallocDefault = 0 };
 enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal = 1 };
 
@@ -198,6 +199,7 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, int f);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, int f);
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
 hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void*, void*, size_t);

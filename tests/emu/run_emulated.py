@@ -190,6 +190,44 @@ def texture_case(spec, fr):
     return bad
 
 
+def mesh_case(spec, fr, spec_rand):
+    """kf_mesh_extract equals the oracle's marching cubes bit for bit (vertex positions,
+    triangle indices, order) on the oracle's integration of the scan and on a random sign
+    field with unobserved voxels over an odd-sized volume; capacity handling."""
+    bad = 0
+    st = O.State(spec, np.float32)
+    O.integrate(spec, fr, st)
+    rng = np.random.default_rng(23)
+    n = int(np.prod(spec_rand.gdim))
+    F = rng.uniform(-1, 1, n).astype(np.float32)
+    F[rng.uniform(size=n) < 0.01] = 0.0
+    W = np.where(rng.uniform(size=n) < 0.03, 0.0, 1.0).astype(np.float32)
+    for sp, tsdf, wg in ((spec, st.tsdf, st.wg), (spec_rand, F, W)):
+        v = Vol(sp)
+        v.arrs[0][:] = tsdf
+        v.arrs[1][:] = wg
+        counts = np.zeros(2, np.int64)
+        check(lib.kf_mesh_extract(v.h, None, 0, None, 0, counts.ctypes.data, None))
+        nv, nt = int(counts[0]), int(counts[1])
+        verts = np.full((nv + 1, 3), -9.0, np.float32)
+        tris = np.full((nt + 1, 3), -9, np.int32)
+        if nt > 0 and lib.kf_mesh_extract(v.h, verts.ctypes.data, nv, tris.ctypes.data, nt - 1,
+                                          counts.ctypes.data, None) != L.KF_E_RANGE:
+            bad += 1                                    # too small: refused
+        check(lib.kf_mesh_extract(v.h, verts.ctypes.data, nv, tris.ctypes.data, nt,
+                                  counts.ctypes.data, None))
+        ov, ot = O.marching_cubes(sp, tsdf, wg, "f32")
+        if (nv, nt) != (len(ov), len(ot)):
+            bad += 1_000_000
+            continue
+        bad += int(np.count_nonzero(verts[:nv].view(np.uint32) != ov.view(np.uint32)))
+        bad += int(np.count_nonzero(tris[:nt] != ot))
+        bad += int((verts[nv] != -9.0).any()) + int((tris[nt] != -9).any())   # nothing beyond
+        if nt < 1000:
+            bad += 1                                    # the case must make a real mesh
+    return bad
+
+
 import time
 T0 = time.time()
 def tick(msg):
@@ -214,6 +252,8 @@ out["raycast_mismatches"] = raycast_case(spec6, fr6)
 tick("raycast")
 out["texture_mismatches"] = texture_case(spec6, fr6)
 tick("texture")
+out["mesh_mismatches"] = mesh_case(spec6, fr6, spec_odd)
+tick("mesh")
 out["backward_6"] = backward_case(spec6, fr6)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)
