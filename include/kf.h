@@ -231,11 +231,12 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
  *              (linear index of the edge's lower voxel, axis x, y, z);
  *   triangles: int32 [n_triangles][3] vertex indices, ordered by cube (linear index of its
  *              lower corner), counter-clockwise seen from the positive-TSDF side.
- * counts (host int64 [2]) always receives (n_vertices, n_triangles).  Call with NULL
- * outputs to size them: returns KF_OK with only the counts; KF_E_RANGE when outputs are
- * given but smaller than the counts (nothing is written to them).  Synchronises `stream`
- * once (to read the counts); the outputs are written asynchronously after that.  The
- * volume needs fewer than 2^31 / 5 voxels (KF_E_RANGE).  Uses a workspace of about 7
+ * counts (host int64 [2]) receives (n_vertices, n_triangles).  Call with both outputs
+ * NULL to size them (KF_OK, only the counts); giving one output without the other is
+ * KF_E_ARG.  When the counts exceed the capacities the call returns KF_E_RANGE and the
+ * outputs hold an incomplete mesh (nothing is written past the capacities).  Returns after
+ * synchronising `stream` (the counts are read at the end, the outputs are complete).  The
+ * volume needs fewer than 2^31 / 5 voxels (KF_E_RANGE).  Uses a workspace of about 6
  * bytes per voxel from the stream-ordered allocator.
  */
 kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capacity,

@@ -47,6 +47,32 @@ kf_status hip_fail(hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
+// Workspaces come from the device's default stream-ordered pool.  Its default release
+// threshold of 0 hands freed memory back at every synchronisation, so each call would map
+// its workspace afresh; the library raises the threshold once per device so that freed
+// workspaces stay in the pool for the next call (the pool grows to the largest workspace
+// used and keeps it until the process ends).
+hipError_t workspace_alloc(void** p, size_t bytes, hipStream_t stream)
+{
+    static std::mutex mu;
+    static bool kept[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!kept[dev]) {
+            hipMemPool_t pool;
+            if ((e = hipDeviceGetDefaultMemPool(&pool, dev)) != hipSuccess) return e;
+            uint64_t threshold = UINT64_MAX;
+            if ((e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold)) != hipSuccess)
+                return e;
+            kept[dev] = true;
+        }
+    }
+    return hipMallocAsync(p, bytes, stream);
+}
+
 // ------------------------------------------------------------------------- validation
 
 bool finite_all(const double* p, int n)
@@ -652,7 +678,7 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     uint32_t grid[2] = {0, 0};
     if ((st = resident_grid(mode, grid)) != KF_OK) return st;
     unsigned char* dev = nullptr;
-    KF_HIP(hipMallocAsync((void**)&dev, t.bytes, stream), "hipMallocAsync");
+    KF_HIP(workspace_alloc((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
     if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream, ev);
@@ -785,7 +811,7 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
     // workspace: [frame constants][weight map]
     const size_t map_off = (sizeof(kf::FrameConsts) + 255) / 256 * 256;
     unsigned char* ws = nullptr;
-    KF_HIP(hipMallocAsync((void**)&ws, map_off + (size_t)dw * dh * sizeof(float), st), "hipMallocAsync");
+    KF_HIP(workspace_alloc((void**)&ws, map_off + (size_t)dw * dh * sizeof(float), st), "hipMallocAsync");
     a.frame.wmap = (float*)(ws + map_off);
     s = staged_copy(ws, &a.frame, sizeof a.frame, st);
     hipError_t e = hipSuccess;
@@ -917,7 +943,7 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     }
     const size_t bytes = align(off);
     unsigned char* ws = nullptr;
-    KF_HIP(hipMallocAsync((void**)&ws, bytes, st), "hipMallocAsync");
+    KF_HIP(workspace_alloc((void**)&ws, bytes, st), "hipMallocAsync");
     for (int f = 0; f < n_frames; ++f) {
         fc[f].pyr = (float2*)(ws + pyr[f]);
         fc[f].wmap = (float*)(ws + wmap[f]);
@@ -1027,6 +1053,8 @@ kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capaci
     if (!counts) return fail(KF_E_ARG, "counts is NULL");
     counts[0] = counts[1] = 0;
     if (vertex_capacity < 0 || triangle_capacity < 0) return fail(KF_E_ARG, "negative capacity");
+    if ((vertices == nullptr) != (triangles == nullptr))
+        return fail(KF_E_ARG, "give both outputs or neither");
     const kf_volume_desc& d = vol->desc;
     const int64_t n = (int64_t)d.geom_dim[0] * d.geom_dim[1] * d.geom_dim[2];
     // at most 3 vertices and 5 triangles per voxel, counted in 32 bits
@@ -1042,43 +1070,45 @@ kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capaci
         a.c[k] = (float)(d.origin[k] + 0.5 * sz);     // world centre of voxel 0
     }
     a.n_voxels = (uint32_t)n;
-    a.n_blocks = (uint32_t)((n + 255) / 256);
+    a.n_blocks = (uint32_t)((n + 4095) / 4096);
     a.tsdf = vol->bufs.tsdf;
     a.wg = vol->bufs.w_geom;
-    // workspace: cube info, vertex/triangle info, first-vertex indices, block sums, totals
+    // workspace: per-voxel vertex/triangle info, first-vertex indices, block sums, totals
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t cube_off = 0;
-    const size_t info_off = align(cube_off + (size_t)n * sizeof(uint16_t));
-    const size_t voff_off = align(info_off + (size_t)n);
+    const size_t info_off = 0;
+    const size_t cfg_off = align(info_off + (size_t)n);
+    const size_t voff_off = align(cfg_off + (size_t)n);
     const size_t sums_off = align(voff_off + (size_t)n * sizeof(uint32_t));
     const size_t tot_off = align(sums_off + (size_t)a.n_blocks * 2 * sizeof(uint32_t));
     const size_t bytes = align(tot_off + 2 * sizeof(uint32_t));
     unsigned char* ws = nullptr;
-    KF_HIP(hipMallocAsync((void**)&ws, bytes, st), "hipMallocAsync");
-    a.cube = (uint16_t*)(ws + cube_off);
+    KF_HIP(workspace_alloc((void**)&ws, bytes, st), "hipMallocAsync");
     a.info = ws + info_off;
+    a.cfg = ws + cfg_off;
     a.voff = (uint32_t*)(ws + voff_off);
     a.block_sums = (uint32_t*)(ws + sums_off);
     a.totals = (uint32_t*)(ws + tot_off);
+    // with outputs, every kernel is enqueued at once (writes past the capacities are
+    // dropped on the device) and the counts are read at the end; without, only the count
+    // kernels run
+    const bool emit = vertices != nullptr;
+    a.vertices = vertices;
+    a.triangles = triangles;
+    a.vcap = (uint32_t)(vertex_capacity < 4294967295LL ? vertex_capacity : 4294967295LL);
+    a.tcap = (uint32_t)(triangle_capacity < 4294967295LL ? triangle_capacity : 4294967295LL);
     uint32_t totals[2] = {0, 0};
     hipError_t e = kf::launch_mesh_count(a, st);
     const char* what = e != hipSuccess ? "mesh count launch" : nullptr;
+    if (!what && emit && (e = kf::launch_mesh_emit(a, st)) != hipSuccess) what = "mesh emit launch";
     if (!what && (e = hipMemcpyAsync(totals, a.totals, sizeof totals, hipMemcpyDeviceToHost, st)) != hipSuccess)
         what = "mesh count copy";
-    if (!what && (e = hipStreamSynchronize(st)) != hipSuccess) what = "mesh count synchronisation";
-    bool emit = false;
-    if (!what) {
-        counts[0] = totals[0];
-        counts[1] = totals[1];
-        emit = vertices && triangles && vertex_capacity >= counts[0] && triangle_capacity >= counts[1];
-        a.vertices = vertices;
-        a.triangles = triangles;
-        if (emit && (e = kf::launch_mesh_emit(a, st)) != hipSuccess) what = "mesh emit launch";
-    }
     const hipError_t fe = hipFreeAsync(ws, st);
+    if (!what && (e = hipStreamSynchronize(st)) != hipSuccess) what = "mesh synchronisation";
     if (what) return hip_fail(e, what);
     if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
-    if ((vertices || triangles) && !emit)
+    counts[0] = totals[0];
+    counts[1] = totals[1];
+    if (emit && (counts[0] > vertex_capacity || counts[1] > triangle_capacity))
         return fail(KF_E_RANGE, "mesh of %lld vertices and %lld triangles exceeds the capacities",
                     (long long)counts[0], (long long)counts[1]);
     return KF_OK;

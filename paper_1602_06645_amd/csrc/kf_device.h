@@ -173,16 +173,17 @@ struct TextureArgs {
 
 struct MeshArgs {
     int32_t dim[3];                      // geometry voxels per axis
-    uint32_t n_voxels, n_blocks;         // n_blocks = ceil(n_voxels / 256)
+    uint32_t n_voxels, n_blocks;         // n_blocks = ceil(n_voxels / 4096)
     float s[3], c[3];                    // voxel size; world centre of voxel 0
     const float *tsdf, *wg;
-    uint16_t* cube;                      // [n_voxels] complete bit | inside-corner mask
     uint8_t* info;                       // [n_voxels] vertex axes | triangle count << 3
-    uint32_t* voff;                      // [n_voxels] index of the voxel's first vertex
+    uint8_t* cfg;                        // [n_voxels] inside corners (cubes with triangles only)
+    uint32_t* voff;                      // [n_voxels] first vertex index (vertex owners only)
     uint32_t* block_sums;                // [n_blocks][2] vertices, triangles (then offsets)
     uint32_t* totals;                    // [2]
-    float* vertices;                     // [n_vertices][3]
-    int32_t* triangles;                  // [n_triangles][3]
+    float* vertices;                     // [vcap][3]: slots at or past vcap are not written
+    int32_t* triangles;                  // [tcap][3]
+    uint32_t vcap, tcap;
 };
 
 // Tiles of level l of a pyramid whose level 0 has w0 x h0 tiles.

@@ -14,9 +14,9 @@
 //     first vertex whose edge shares no face with a non-neighbouring vertex's edge;
 //     triangles face towards positive F; cubes in linear order.
 // The per-configuration triangles are generated at compile time from that rule
-// (build_table).  Extraction is a stream compaction over voxels: classify the cubes,
-// count each voxel's vertices and triangles, scan the counts (per block, then over the
-// blocks), then write vertices and triangles at their scanned offsets.
+// (build_table).  Extraction is a stream compaction over voxels: classify the cubes and
+// count each voxel's vertices and triangles (tiles in LDS), sum the counts per linear
+// block, scan the block sums, then write vertices and triangles at their scanned offsets.
 #include <hip/hip_runtime.h>
 
 #include "kf_device.h"
@@ -124,194 +124,300 @@ constexpr McTable build_table()
 
 __constant__ McTable kMc = build_table();
 
-constexpr int MC_BLOCK = 256;
+// Classification works on tiles of 32 x 8 x 8 voxels staged in LDS with a one-voxel
+// halo; compaction works on linear blocks of 4096 voxels (16 per thread), so that the
+// vertex and triangle order follows the linear voxel index.
+constexpr int TX = 32, TY = 8, TZ = 8;
+constexpr int BX = TX + 2, BY = TY + 2, BZ = TZ + 2;     // voxels: tile - 1 .. tile end + 1
+constexpr int CX = TX + 1, CY = TY + 1, CZ = TZ + 1;     // cubes: lower corners tile - 1 .. tile end
+constexpr int MC_THREADS = 256;
+constexpr int LB = 4096, PER = LB / MC_THREADS;          // linear block, voxels per thread
+static_assert(MC_THREADS == 256, "one thread per cube configuration when tables are staged");
 
-// Per voxel (cube with lower corner u): bit 8 = complete, bits 0-7 = inside corners.
-__global__ __launch_bounds__(MC_BLOCK) void mc_classify_kernel(MeshArgs a)
+// Per voxel of a tile: info = (axes whose edge from the voxel carries a vertex) |
+// (triangles of the cube at the voxel) << 3.
+__global__ __launch_bounds__(MC_THREADS) void mc_classify_kernel(MeshArgs a)
 {
-    const uint32_t v = blockIdx.x * MC_BLOCK + threadIdx.x;
-    if (v >= a.n_voxels) return;
-    const uint32_t X = (uint32_t)a.dim[0], Y = (uint32_t)a.dim[1], Z = (uint32_t)a.dim[2];
-    const uint32_t x = v % X, y = (v / X) % Y, z = v / (X * Y);
-    uint16_t info = 0;
-    if (x + 1 < X && y + 1 < Y && z + 1 < Z) {
-        bool complete = true;
-        uint32_t cfg = 0;
+    // voxel codes: bit 0 observed, bit 1 inside; cube codes: bit 7 complete | triangles
+    __shared__ uint8_t code[BZ * BY * BX];
+    __shared__ uint8_t cube[CZ * CY * CX];
+    __shared__ uint8_t count[256];                 // triangles per configuration
+    count[threadIdx.x] = kMc.count[threadIdx.x];
+    const int X = a.dim[0], Y = a.dim[1], Z = a.dim[2];
+    const int ntx = (X + TX - 1) / TX, nty = (Y + TY - 1) / TY;
+    const int t = (int)blockIdx.x;
+    const int ox = (t % ntx) * TX - 1, oy = ((t / ntx) % nty) * TY - 1, oz = (t / (ntx * nty)) * TZ - 1;
+    // the voxel box (voxels outside the volume are unobserved); every load of the thread is
+    // issued before the first is used
+    constexpr int NBOX = BX * BY * BZ, ITER = (NBOX + MC_THREADS - 1) / MC_THREADS;
+    float fv[ITER], wv[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int i = (int)threadIdx.x + it * MC_THREADS;
+        const int gx = ox + i % BX, gy = oy + (i / BX) % BY, gz = oz + i / (BX * BY);
+        fv[it] = 0.0f;
+        wv[it] = 0.0f;
+        if (i < NBOX && gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z) {
+            const uint32_t v = (uint32_t)gx + (uint32_t)X * ((uint32_t)gy + (uint32_t)Y * (uint32_t)gz);
+            fv[it] = a.tsdf[v];
+            wv[it] = a.wg[v];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int i = (int)threadIdx.x + it * MC_THREADS;
+        if (i < NBOX) code[i] = (uint8_t)((wv[it] > 0.0f ? 1u : 0u) | (fv[it] < 0.0f ? 2u : 0u));
+    }
+    __syncthreads();
+    // the cubes (one reaching outside the volume has an unobserved corner)
+    for (int i = (int)threadIdx.x; i < CX * CY * CZ; i += MC_THREADS) {
+        const int cx = i % CX, cy = (i / CX) % CY, cz = i / (CX * CY);
+        const int b0 = cx + BX * (cy + BY * cz);
+        uint32_t all = 1u, cfg = 0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const uint32_t i = v + (c & 1) + ((c >> 1) & 1) * X + ((c >> 2) & 1) * X * Y;
-            complete &= a.wg[i] > 0.0f;
-            cfg |= (a.tsdf[i] < 0.0f ? 1u : 0u) << c;
+            const uint32_t k = code[b0 + (c & 1) + ((c >> 1) & 1) * BX + ((c >> 2) & 1) * BX * BY];
+            all &= k;
+            cfg |= ((k >> 1) & 1u) << c;
         }
-        info = complete ? (uint16_t)(0x100u | cfg) : 0;
-    }
-    a.cube[v] = info;
-}
-
-// Per voxel: bits 0-2 = axes whose edge from the voxel carries a vertex, bits 3-5 = the
-// voxel's cube's triangle count; per block: the sums of vertices and triangles.
-__global__ __launch_bounds__(MC_BLOCK) void mc_count_kernel(MeshArgs a)
-{
-    __shared__ uint32_t red[2][MC_BLOCK / 64];
-    const uint32_t v = blockIdx.x * MC_BLOCK + threadIdx.x;
-    uint32_t nv = 0, nt = 0;
-    if (v < a.n_voxels) {
-        const uint32_t X = (uint32_t)a.dim[0], Y = (uint32_t)a.dim[1], Z = (uint32_t)a.dim[2];
-        const uint32_t xyz[3] = {v % X, (v / X) % Y, v / (X * Y)};
-        const uint32_t dims[3] = {X, Y, Z};
-        const uint32_t step[3] = {1u, X, X * Y};
-        const uint16_t own = a.cube[v];
-        nt = (own & 0x100u) ? kMc.count[own & 0xFFu] : 0u;
-        const float f0 = a.tsdf[v];
-        const bool obs0 = a.wg[v] > 0.0f;
-        uint32_t mask = 0;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (!obs0 || xyz[ax] + 1 >= dims[ax]) continue;
-            const uint32_t w = v + step[ax];
-            if (!(a.wg[w] > 0.0f) || ((f0 < 0.0f) == (a.tsdf[w] < 0.0f))) continue;
-            // the four cubes holding the edge have lower corners v - db e_b - dc e_c
-            const int b = (ax + 1) % 3, c = (ax + 2) % 3;
-            bool used = false;
-#pragma unroll
-            for (int db = 0; db < 2; ++db)
-#pragma unroll
-                for (int dc = 0; dc < 2; ++dc) {
-                    if ((db && xyz[b] == 0) || (dc && xyz[c] == 0)) continue;
-                    used |= (a.cube[v - db * step[b] - dc * step[c]] & 0x100u) != 0;
-                }
-            if (used) mask |= 1u << ax;
-        }
-        nv = (uint32_t)__builtin_popcount(mask);
-        a.info[v] = (uint8_t)(mask | (nt << 3));
-    }
-    // block sums
-    for (int o = 32; o > 0; o >>= 1) {
-        nv += __shfl_xor(nv, o);
-        nt += __shfl_xor(nt, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = nv;
-        red[1][threadIdx.x >> 6] = nt;
+        cube[i] = all ? (uint8_t)(0x80u | count[cfg]) : (uint8_t)0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t sv = 0, st = 0;
-        for (int w = 0; w < MC_BLOCK / 64; ++w) {
-            sv += red[0][w];
-            st += red[1][w];
+    // each thread: one (x, y) of the tile, all 8 z
+    const int x = (int)threadIdx.x % TX, y = (int)threadIdx.x / TX;
+    const int gx = ox + 1 + x, gy = oy + 1 + y;
+    if (gx >= X || gy >= Y) return;
+    const int bstep[3] = {1, BX, BX * BY}, cstep[3] = {1, CX, CX * CY};
+    for (int z = 0; z < TZ; ++z) {
+        const int gz = oz + 1 + z;
+        if (gz >= Z) break;
+        const int b = (x + 1) + BX * ((y + 1) + BY * (z + 1));
+        const int c = (x + 1) + CX * ((y + 1) + CY * (z + 1));   // the cube at this voxel
+        uint32_t info = (uint32_t)(cube[c] & 0x7Fu) << 3;
+        const uint32_t vg = (uint32_t)gx + (uint32_t)X * ((uint32_t)gy + (uint32_t)Y * (uint32_t)gz);
+        if (info) {
+            // the configuration of a cube with triangles, for the triangle pass
+            uint32_t cfg = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                cfg |= ((code[b + (k & 1) + ((k >> 1) & 1) * BX + ((k >> 2) & 1) * BX * BY] >> 1) & 1u) << k;
+            a.cfg[vg] = (uint8_t)cfg;
         }
-        a.block_sums[2 * blockIdx.x] = sv;
-        a.block_sums[2 * blockIdx.x + 1] = st;
+        const uint32_t k0 = code[b];
+        if (k0 & 1u) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const uint32_t k1 = code[b + bstep[ax]];
+                if (!(k1 & 1u) || ((k0 ^ k1) & 2u) == 0) continue;
+                // the four cubes holding the edge: lower corners v - db e_p - dc e_q
+                const int p = (ax + 1) % 3, q = (ax + 2) % 3;
+                const uint32_t used = cube[c] | cube[c - cstep[p]] | cube[c - cstep[q]] |
+                                      cube[c - cstep[p] - cstep[q]];
+                if (used & 0x80u) info |= 1u << ax;
+            }
+        }
+        a.info[vg] = (uint8_t)info;
     }
 }
 
-// One workgroup: exclusive scan of the per-block sums (in place) and the totals.
+__device__ __forceinline__ uint32_t vertices_of(uint32_t info) { return (uint32_t)__builtin_popcount(info & 7u); }
+__device__ __forceinline__ uint32_t triangles_of(uint32_t info) { return info >> 3; }
+
+// The 16 info bytes of this thread's voxels in linear block b (zero past the volume).
+__device__ __forceinline__ void load_run(const MeshArgs& a, uint32_t b, uint8_t* run)
+{
+    const uint32_t v0 = b * LB + threadIdx.x * PER;
+    if (v0 + PER <= a.n_voxels) {
+        uint4 w;
+        __builtin_memcpy(&w, a.info + v0, 16);
+        __builtin_memcpy(run, &w, 16);
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) run[k] = v0 + k < a.n_voxels ? a.info[v0 + k] : 0;
+    }
+}
+
+// Inclusive scan over the workgroup of one value per thread (thread order).
+__device__ __forceinline__ uint32_t block_inclusive(uint32_t x, uint32_t* lds)
+{
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += lds[w];
+    __syncthreads();
+    return base + x;
+}
+
+// Per linear block: total vertices and triangles.
+__global__ __launch_bounds__(MC_THREADS) void mc_block_sums_kernel(MeshArgs a)
+{
+    __shared__ uint32_t lds[MC_THREADS / 64];
+    uint8_t run[PER];
+    load_run(a, blockIdx.x, run);
+    uint32_t nv = 0, nt = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        nv += vertices_of(run[k]);
+        nt += triangles_of(run[k]);
+    }
+    // pack both sums (each below 2^16 per block: 3 and 5 per voxel, 4096 voxels)
+    const uint32_t tot = block_inclusive(nv | (nt << 16), lds);
+    if (threadIdx.x == MC_THREADS - 1) {
+        a.block_sums[2 * blockIdx.x] = tot & 0xFFFFu;
+        a.block_sums[2 * blockIdx.x + 1] = tot >> 16;
+    }
+}
+
+// One workgroup: exclusive scan of the block sums in place, and the totals.
 __global__ __launch_bounds__(1024) void mc_scan_blocks_kernel(MeshArgs a)
 {
-    __shared__ uint32_t part[2][1024];
-    const uint32_t nb = a.n_blocks, per = (nb + 1023) / 1024;
-    const uint32_t b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
-    uint32_t sv = 0, st = 0;
-    for (uint32_t b = b0; b < b1; ++b) {
-        sv += a.block_sums[2 * b];
-        st += a.block_sums[2 * b + 1];
-    }
-    part[0][threadIdx.x] = sv;
-    part[1][threadIdx.x] = st;
-    __syncthreads();
-    // inclusive Hillis-Steele scan over the 1024 partial sums
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t pv = threadIdx.x >= (unsigned)o ? part[0][threadIdx.x - o] : 0u;
-        const uint32_t pt = threadIdx.x >= (unsigned)o ? part[1][threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[0][threadIdx.x] += pv;
-        part[1][threadIdx.x] += pt;
-        __syncthreads();
-    }
-    uint32_t ov = part[0][threadIdx.x] - sv, ot = part[1][threadIdx.x] - st;
-    for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t cv = a.block_sums[2 * b], ct = a.block_sums[2 * b + 1];
-        a.block_sums[2 * b] = ov;
-        a.block_sums[2 * b + 1] = ot;
-        ov += cv;
-        ot += ct;
-    }
-    if (threadIdx.x == 1023) {
-        a.totals[0] = part[0][1023];
-        a.totals[1] = part[1][1023];
-    }
-}
-
-// Exclusive prefix of `val` over the workgroup (in voxel order) plus the block offset.
-__device__ __forceinline__ uint32_t block_exclusive(uint32_t val, uint32_t* lds)
-{
-    lds[threadIdx.x] = val;
-    __syncthreads();
-    for (int o = 1; o < MC_BLOCK; o <<= 1) {
-        const uint32_t p = threadIdx.x >= (unsigned)o ? lds[threadIdx.x - o] : 0u;
-        __syncthreads();
-        lds[threadIdx.x] += p;
-        __syncthreads();
-    }
-    const uint32_t incl = lds[threadIdx.x];
-    __syncthreads();
-    return incl - val;
-}
-
-// Vertices: positions at their scanned slots, and each voxel's first vertex index.
-__global__ __launch_bounds__(MC_BLOCK) void mc_vertices_kernel(MeshArgs a)
-{
-    __shared__ uint32_t lds[MC_BLOCK];
-    const uint32_t v = blockIdx.x * MC_BLOCK + threadIdx.x;
-    const uint32_t mask = v < a.n_voxels ? (a.info[v] & 7u) : 0u;
-    const uint32_t first = a.block_sums[2 * blockIdx.x] +
-                           block_exclusive((uint32_t)__builtin_popcount(mask), lds);
-    if (v >= a.n_voxels) return;
-    a.voff[v] = first;
-    if (!mask) return;
-    const uint32_t X = (uint32_t)a.dim[0], Y = (uint32_t)a.dim[1];
-    const uint32_t xyz[3] = {v % X, (v / X) % Y, v / (X * Y)};
-    const uint32_t step[3] = {1u, X, X * Y};
-    const float f0 = a.tsdf[v];
-    uint32_t slot = first;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (!((mask >> ax) & 1)) continue;
-        const float t = f0 / (f0 - a.tsdf[v + step[ax]]);
-        float* out = a.vertices + 3 * (size_t)slot;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float q = k == ax ? (float)xyz[k] + t : (float)xyz[k];
-            out[k] = fmaf(q, a.s[k], a.c[k]);
+    __shared__ uint32_t lds[2][1024 / 64];
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    uint32_t carry_v = 0, carry_t = 0;
+    for (uint32_t base = 0; base < a.n_blocks; base += 1024) {
+        const uint32_t b = base + threadIdx.x;
+        uint32_t v = b < a.n_blocks ? a.block_sums[2 * b] : 0u;
+        uint32_t t = b < a.n_blocks ? a.block_sums[2 * b + 1] : 0u;
+        uint32_t iv = v, it = t;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t yv = __shfl_up(iv, o), yt = __shfl_up(it, o);
+            if (lane >= o) {
+                iv += yv;
+                it += yt;
+            }
         }
-        ++slot;
+        if (lane == 63) {
+            lds[0][wave] = iv;
+            lds[1][wave] = it;
+        }
+        __syncthreads();
+        uint32_t pv = carry_v, pt = carry_t;
+        for (int w = 0; w < wave; ++w) {
+            pv += lds[0][w];
+            pt += lds[1][w];
+        }
+        uint32_t sum_v = 0, sum_t = 0;
+        for (int w = 0; w < 1024 / 64; ++w) {
+            sum_v += lds[0][w];
+            sum_t += lds[1][w];
+        }
+        __syncthreads();
+        if (b < a.n_blocks) {
+            a.block_sums[2 * b] = pv + iv - v;
+            a.block_sums[2 * b + 1] = pt + it - t;
+        }
+        carry_v += sum_v;
+        carry_t += sum_t;
+    }
+    if (threadIdx.x == 0) {
+        a.totals[0] = carry_v;
+        a.totals[1] = carry_t;
     }
 }
 
-// Triangles at their scanned slots, corners as vertex indices.
-__global__ __launch_bounds__(MC_BLOCK) void mc_triangles_kernel(MeshArgs a)
+// The voxels of this thread's run that have outputs (count(info) > 0), gathered for the
+// workgroup in voxel order: list[i] = (voxel offset in the block) | (first output slot
+// relative to the block's first, << 12).  Returns the list length.
+template <class Count>
+__device__ __forceinline__ uint32_t gather_active(const uint8_t* run, Count count, uint32_t* list,
+                                                  uint32_t* lds)
 {
-    __shared__ uint32_t lds[MC_BLOCK];
-    const uint32_t v = blockIdx.x * MC_BLOCK + threadIdx.x;
-    const uint32_t nt = v < a.n_voxels ? (uint32_t)(a.info[v] >> 3) : 0u;
-    const uint32_t first = a.block_sums[2 * blockIdx.x + 1] + block_exclusive(nt, lds);
-    if (v >= a.n_voxels || nt == 0) return;
-    const uint32_t X = (uint32_t)a.dim[0], Y = (uint32_t)a.dim[1];
-    const uint32_t cfg = a.cube[v] & 0xFFu;
-    for (uint32_t i = 0; i < nt; ++i) {
-        int32_t* out = a.triangles + 3 * (size_t)(first + i);
+    uint32_t n = 0, m = 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int e = kMc.edge[cfg][3 * i + k];
-            const int ax = e >> 2, lo = e & 1, hi = (e >> 1) & 1;
-            // the edge's lower end: the cube corner offset by (lo, hi) on the other axes
-            const uint32_t ox = ax == 0 ? 0u : (uint32_t)lo;
-            const uint32_t oy = ax == 0 ? (uint32_t)lo : ax == 1 ? 0u : (uint32_t)hi;
-            const uint32_t oz = ax == 2 ? 0u : (uint32_t)hi;
-            const uint32_t owner = v + ox + oy * X + oz * X * Y;
-            const uint32_t below = a.info[owner] & ((1u << ax) - 1u);
-            out[k] = (int32_t)(a.voff[owner] + (uint32_t)__builtin_popcount(below));
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t c = count(run[k]);
+        n += c;
+        m += c ? 1u : 0u;
+    }
+    // both prefixes in one scan (outputs below 2^15, active voxels below 2^13 per block)
+    const uint32_t incl = block_inclusive(n | (m << 16), lds);
+    uint32_t slot = (incl & 0xFFFFu) - n;
+    uint32_t pos = (incl >> 16) - m;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t c = count(run[k]);
+        if (c) {
+            list[pos++] = (threadIdx.x * PER + k) | (slot << 12);
+            slot += c;
+        }
+    }
+    if (threadIdx.x == MC_THREADS - 1) lds[0] = incl >> 16;
+    __syncthreads();
+    return lds[0];
+}
+
+// Vertices at their scanned slots (those below the capacity); each vertex-owning voxel's
+// first vertex index.
+__global__ __launch_bounds__(MC_THREADS) void mc_vertices_kernel(MeshArgs a)
+{
+    __shared__ uint32_t lds[MC_THREADS / 64];
+    __shared__ uint32_t list[LB];
+    uint8_t run[PER];
+    load_run(a, blockIdx.x, run);
+    const uint32_t n_active = gather_active(run, [](uint32_t i) { return vertices_of(i); }, list, lds);
+    const uint32_t base = a.block_sums[2 * blockIdx.x];
+    const uint32_t X = (uint32_t)a.dim[0], Y = (uint32_t)a.dim[1];
+    const uint32_t step[3] = {1u, X, X * Y};
+    for (uint32_t e = threadIdx.x; e < n_active; e += MC_THREADS) {
+        const uint32_t v = blockIdx.x * LB + (list[e] & 0xFFFu);
+        uint32_t slot = base + (list[e] >> 12);
+        const uint32_t mask = a.info[v] & 7u;
+        a.voff[v] = slot;
+        const uint32_t xyz[3] = {v % X, (v / X) % Y, v / (X * Y)};
+        const float f0 = a.tsdf[v];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (!((mask >> ax) & 1)) continue;
+            if (slot < a.vcap) {
+                const float t = f0 / (f0 - a.tsdf[v + step[ax]]);
+                float* out = a.vertices + 3 * (size_t)slot;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float q = j == ax ? (float)xyz[j] + t : (float)xyz[j];
+                    out[j] = fmaf(q, a.s[j], a.c[j]);
+                }
+            }
+            ++slot;
+        }
+    }
+}
+
+// Triangles at their scanned slots (those below the capacity), corners as vertex indices.
+__global__ __launch_bounds__(MC_THREADS) void mc_triangles_kernel(MeshArgs a)
+{
+    __shared__ uint32_t lds[MC_THREADS / 64];
+    __shared__ uint32_t list[LB];
+    __shared__ uint8_t table[256 * 15];            // the cube table's triangle edges
+    for (int i = (int)threadIdx.x; i < 256 * 15; i += MC_THREADS) table[i] = kMc.edge[i / 15][i % 15];
+    uint8_t run[PER];
+    load_run(a, blockIdx.x, run);
+    const uint32_t n_active = gather_active(run, [](uint32_t i) { return triangles_of(i); }, list, lds);
+    const uint32_t base = a.block_sums[2 * blockIdx.x + 1];
+    const uint32_t X = (uint32_t)a.dim[0], XY = (uint32_t)a.dim[0] * (uint32_t)a.dim[1];
+    for (uint32_t e = threadIdx.x; e < n_active; e += MC_THREADS) {
+        const uint32_t v = blockIdx.x * LB + (list[e] & 0xFFFu);
+        uint32_t slot = base + (list[e] >> 12);
+        const uint32_t nt = triangles_of(a.info[v]);
+        const uint32_t cfg = a.cfg[v];
+        for (uint32_t i = 0; i < nt; ++i, ++slot) {
+            if (slot >= a.tcap) continue;
+            int32_t* out = a.triangles + 3 * (size_t)slot;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int ed = table[15 * cfg + 3 * i + j];
+                const int ax = ed >> 2, lo = ed & 1, hi = (ed >> 1) & 1;
+                // the edge's lower end: the cube corner offset by (lo, hi) on the other axes
+                const uint32_t ox = ax == 0 ? 0u : (uint32_t)lo;
+                const uint32_t oy = ax == 0 ? (uint32_t)lo : ax == 1 ? 0u : (uint32_t)hi;
+                const uint32_t oz = ax == 2 ? 0u : (uint32_t)hi;
+                const uint32_t owner = v + ox + oy * X + oz * XY;
+                const uint32_t below = a.info[owner] & ((1u << ax) - 1u);
+                out[j] = (int32_t)(a.voff[owner] + (uint32_t)__builtin_popcount(below));
+            }
         }
     }
 }
@@ -320,16 +426,18 @@ __global__ __launch_bounds__(MC_BLOCK) void mc_triangles_kernel(MeshArgs a)
 
 hipError_t launch_mesh_count(const MeshArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(mc_classify_kernel, dim3(a.n_blocks), dim3(MC_BLOCK), 0, stream, a);
-    hipLaunchKernelGGL(mc_count_kernel, dim3(a.n_blocks), dim3(MC_BLOCK), 0, stream, a);
+    const uint32_t tiles = (uint32_t)(((a.dim[0] + TX - 1) / TX) * ((a.dim[1] + TY - 1) / TY) *
+                                      ((a.dim[2] + TZ - 1) / TZ));
+    hipLaunchKernelGGL(mc_classify_kernel, dim3(tiles), dim3(MC_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(mc_block_sums_kernel, dim3(a.n_blocks), dim3(MC_THREADS), 0, stream, a);
     hipLaunchKernelGGL(mc_scan_blocks_kernel, dim3(1), dim3(1024), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_mesh_emit(const MeshArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(mc_vertices_kernel, dim3(a.n_blocks), dim3(MC_BLOCK), 0, stream, a);
-    hipLaunchKernelGGL(mc_triangles_kernel, dim3(a.n_blocks), dim3(MC_BLOCK), 0, stream, a);
+    hipLaunchKernelGGL(mc_vertices_kernel, dim3(a.n_blocks), dim3(MC_THREADS), 0, stream, a);
+    hipLaunchKernelGGL(mc_triangles_kernel, dim3(a.n_blocks), dim3(MC_THREADS), 0, stream, a);
     return hipGetLastError();
 }
 

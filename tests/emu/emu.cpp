@@ -209,7 +209,8 @@ static bool needs_fibers(const void* k)
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_GEOM>,
         (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_COLOUR>,
         (const void*)kf::texture_kernel,
-        (const void*)kf::mc_count_kernel,
+        (const void*)kf::mc_classify_kernel,
+        (const void*)kf::mc_block_sums_kernel,
         (const void*)kf::mc_scan_blocks_kernel,
         (const void*)kf::mc_vertices_kernel,
         (const void*)kf::mc_triangles_kernel,

@@ -91,6 +91,15 @@ inline T __shfl_xor(T v, int mask, int width = 64)
     return emu_bcast_from(v, lane ^ mask);
 }
 
+template <class T>
+inline T __shfl_up(T v, unsigned delta, int width = 64)
+{
+    (void)width;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int src = lane - (int)delta;
+    return emu_bcast_from(v, src < 0 ? lane : src);
+}
+
 // like the builtin: takes and returns a signed 32-bit int
 #define __builtin_amdgcn_readfirstlane(v) emu_readfirstlane((int)(v))
 inline int emu_readfirstlane(int v)
@@ -199,6 +208,10 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, int f);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, int f);
+typedef struct emu_pool* hipMemPool_t;
+enum hipMemPoolAttr { hipMemPoolAttrReleaseThreshold = 4 };
+inline hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t* p, int) { *p = nullptr; return hipSuccess; }
+inline hipError_t hipMemPoolSetAttribute(hipMemPool_t, hipMemPoolAttr, void*) { return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode m);
 hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
