@@ -276,6 +276,35 @@ def test_texture_rejects_bad_arguments():
         lib.kf_volume_destroy(h1)
 
 
+def test_mesh_rejects_bad_arguments():
+    lib = L.load()
+    counts = np.zeros(2, np.int64)
+    cp = counts.ctypes.data_as(C.c_void_p)
+    p = C.c_void_p(0x4000)
+    assert lib.kf_mesh_extract(None, None, 0, None, 0, cp, None) == L.KF_E_ARG
+    h = _volume()
+    try:
+        assert lib.kf_mesh_extract(h, None, 0, None, 0, None, None) == L.KF_E_ARG
+        assert lib.kf_mesh_extract(h, p, -1, p, 4, cp, None) == L.KF_E_ARG
+        assert lib.kf_mesh_extract(h, p, 4, None, 0, cp, None) == L.KF_E_ARG     # one output
+    finally:
+        lib.kf_volume_destroy(h)
+    bufs = L.VolumeBuffers(*([0x1000] * 6))
+    for dims, code in (((1, 16, 16), L.KF_OK), ((1024, 1024, 512), L.KF_E_RANGE)):
+        d = _desc()
+        d.geom_dim[0], d.geom_dim[1], d.geom_dim[2] = dims
+        h1 = C.c_void_p()
+        assert lib.kf_volume_create(C.byref(d), C.byref(bufs), C.byref(h1)) == L.KF_OK
+        try:
+            counts[:] = 7
+            # a volume without cubes has an empty mesh (no device work); one of 2^29 voxels
+            # would overflow the 32-bit counts
+            assert lib.kf_mesh_extract(h1, None, 0, None, 0, cp, None) == code
+            assert (counts == 0).all()
+        finally:
+            lib.kf_volume_destroy(h1)
+
+
 def test_backward_rejects_bad_arguments():
     lib = L.load()
     d = _desc()
