@@ -106,6 +106,7 @@ class VolumeSpec:
     extent: tuple
     sigma: float = 0.020    # colour distance threshold, 20 mm (Sec. IV.B)
     gate: float = 0.8       # colour weight gate (Sec. IV.B)
+    hd_sampling: str = "bilinear"   # or "nearest": the HD pixel nearest the projection
 
     @staticmethod
     def cube(g: int, ratio: int, size: float, **kw) -> "VolumeSpec":

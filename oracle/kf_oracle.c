@@ -86,6 +86,7 @@ void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc
     out->w_max = fr->w_max;
     out->sigma2 = vol->sigma * vol->sigma;
     out->gate = vol->gate;
+    out->hd_nearest = vol->hd_nearest ? 1.0 : 0.0;
 }
 
 static or_fc64* all_consts(const or_volume* vol, const or_frames* fr)
@@ -190,6 +191,7 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
                      const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
                      double* d_xi)
 {
+    if (vol->hd_nearest) return;
     int n = fr->n_frames;
     or_fc64* fc64 = all_consts(vol, fr);
     or_fc__f64* fc = (or_fc__f64*)malloc(sizeof(or_fc__f64) * (size_t)(n > 0 ? n : 1));

@@ -45,6 +45,7 @@ typedef struct {
     double origin[3], extent[3];
     double sigma;  /* colour distance threshold in metres (paper: 20 mm) */
     double gate;   /* colour weight gate factor (paper: 0.8)             */
+    int32_t hd_nearest;  /* 1: the HD pixel nearest the projection; 0: bilinear */
 } or_volume;
 
 typedef struct {
@@ -65,6 +66,7 @@ typedef struct {
     double fx, fy, cx, cy, inv_fx, inv_fy;
     double fxr, fyr, cxr, cyr;
     double trunc, inv_trunc, w_max, sigma2, gate;
+    double hd_nearest;   /* 1.0 for nearest-pixel HD sampling, 0.0 for bilinear */
 } or_fc64;
 
 void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc64* out);
@@ -103,6 +105,8 @@ void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, d
  * decide_f32 = 0: every step in FP64 (the adjoint of the FP64 forward).
  * decide_f32 = 1: the integer decisions (depth pixel, the tests of Sec. IV.B, the
  * bilinear cell) are those of the FP32 forward; the values stay FP64.
+ * Defined for bilinear HD sampling only (vol->hd_nearest == 0); otherwise nothing is
+ * written.
  */
 void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
                      const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,

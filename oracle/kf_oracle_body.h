@@ -25,6 +25,7 @@ typedef struct {
     REAL fx, fy, cx, cy, inv_fx, inv_fy;  /* K_c and the diagonal of K_c^-1 (Eq. 6, 7) */
     REAL fxr, fyr, cxr, cyr;               /* K_hd (Eq. 4)                            */
     REAL trunc, inv_trunc, w_max, sigma2, gate;
+    int hd_nearest;                        /* nearest-pixel HD sampling (else bilinear) */
 } OR_T(or_fc_);
 
 static void OR_FN(round_consts_)(const or_fc64* in, OR_T(or_fc_)* out)
@@ -47,6 +48,7 @@ static void OR_FN(round_consts_)(const or_fc64* in, OR_T(or_fc_)* out)
     out->trunc = (REAL)in->trunc; out->inv_trunc = (REAL)in->inv_trunc;
     out->w_max = (REAL)in->w_max; out->sigma2 = (REAL)in->sigma2;
     out->gate = (REAL)in->gate;
+    out->hd_nearest = in->hd_nearest != 0.0;
 }
 
 /* A depth pixel is a measurement iff it is a positive finite number; zero marks a
@@ -125,8 +127,9 @@ typedef struct {
     REAL w;           /* normal-times-view weight W (Sec. IV.B, Eq. 8)           */
     REAL q[3];        /* voxel centre in HD camera coordinates (Eq. 5 then 3)    */
     REAL xh, yh;      /* HD image coordinates (Eq. 4 with perspective division) */
-    int x0, y0;       /* top-left pixel of the bilinear cell                     */
+    int x0, y0;       /* top-left pixel of the bilinear cell, or the nearest pixel */
     REAL ax, ay;      /* bilinear fractions                                      */
+    int nearest;      /* sample the single pixel (x0, y0)                        */
 } OR_T(or_ceval_);
 
 /* Colour-volume tests of Sec. IV.B in the paper's order: frustum, depth, distance
@@ -179,6 +182,18 @@ static void OR_FN(colour_eval_)(const OR_T(or_fc_)* c, const float* D, int W, in
     REAL iqz = (REAL)1 / e->q[2];
     e->xh = FMA(c->fxr, e->q[0] * iqz, c->cxr);
     e->yh = FMA(c->fyr, e->q[1] * iqz, c->cyr);
+    e->nearest = c->hd_nearest;
+    if (c->hd_nearest) {
+        /* the pixel whose centre is nearest (ties to even), inside the image */
+        REAL rx = RINT(e->xh), ry = RINT(e->yh);
+        if (!(rx >= (REAL)0 && rx <= (REAL)(CW - 1) && ry >= (REAL)0 && ry <= (REAL)(CH - 1)))
+            return;
+        e->x0 = (int)rx;
+        e->y0 = (int)ry;
+        e->ax = e->ay = (REAL)0;
+        e->status = OR_ST_UPDATED;
+        return;
+    }
     REAL fx0 = FLOOR(e->xh), fy0 = FLOOR(e->yh);
     if (!(fx0 >= (REAL)0 && fx0 <= (REAL)(CW - 2) && fy0 >= (REAL)0 && fy0 <= (REAL)(CH - 2)))
         return;
@@ -194,6 +209,7 @@ static REAL OR_FN(hd_sample_)(const OR_T(or_ceval_)* e, const uint8_t* rgb8,
                               const float* rgbf, int CW, int ch)
 {
     size_t r0 = (size_t)e->y0 * (size_t)CW, r1 = r0 + (size_t)CW;
+    if (e->nearest) return OR_FN(hd_px_)(rgb8, rgbf, (r0 + (size_t)e->x0) * 3 + (size_t)ch);
     REAL p00 = OR_FN(hd_px_)(rgb8, rgbf, (r0 + (size_t)e->x0) * 3 + (size_t)ch);
     REAL p10 = OR_FN(hd_px_)(rgb8, rgbf, (r0 + (size_t)e->x0 + 1) * 3 + (size_t)ch);
     REAL p01 = OR_FN(hd_px_)(rgb8, rgbf, (r1 + (size_t)e->x0) * 3 + (size_t)ch);

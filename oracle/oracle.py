@@ -36,7 +36,7 @@ def build(force: bool = True, src_dir: str = HERE, out: str = DEFAULT_LIB_PATH) 
 class _Volume(C.Structure):
     _fields_ = [("gdim", C.c_int32 * 3), ("cdim", C.c_int32 * 3),
                 ("origin", C.c_double * 3), ("extent", C.c_double * 3),
-                ("sigma", C.c_double), ("gate", C.c_double)]
+                ("sigma", C.c_double), ("gate", C.c_double), ("hd_nearest", C.c_int32)]
 
 
 class _Frames(C.Structure):
@@ -53,7 +53,7 @@ class _FC64(C.Structure):
                 (n, C.c_double * 3) if n.startswith("b") else (n, C.c_double)
                 for n in ["Ag", "bg", "Ac", "bc", "Ah", "bh", "fx", "fy", "cx", "cy",
                           "inv_fx", "inv_fy", "fxr", "fyr", "cxr", "cyr", "trunc",
-                          "inv_trunc", "w_max", "sigma2", "gate"]]
+                          "inv_trunc", "w_max", "sigma2", "gate", "hd_nearest"]]
 
 
 class _RC64(C.Structure):
@@ -113,6 +113,7 @@ def _vol(vol) -> _Volume:
     v.extent[:] = [float(a) for a in vol.extent]
     v.sigma = float(vol.sigma)
     v.gate = float(vol.gate)
+    v.hd_nearest = 1 if getattr(vol, "hd_sampling", "bilinear") == "nearest" else 0
     return v
 
 
@@ -222,7 +223,10 @@ def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None,
     """FP64 adjoint: d L / d RGB ([n][ch][cw][3]) and d L / d xi (6) for
     L = sum g[ch][v] C_N(v)_ch over colour slabs cz; g has shape (3, n_slab_voxels).
     decide_f32: take the integer decisions (pixel, masks, gate, bilinear cell) of the
-    FP32 forward, as the GPU kernel does; otherwise everything is FP64."""
+    FP32 forward, as the GPU kernel does; otherwise everything is FP64.  Defined for
+    bilinear HD sampling only."""
+    if getattr(vol, "hd_sampling", "bilinear") != "bilinear":
+        raise ValueError("the adjoint is defined for bilinear HD sampling")
     keep: list = []
     f = _frames(fr, keep)
     cz = cz or (0, vol.cdim[2])

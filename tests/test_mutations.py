@@ -75,6 +75,9 @@ MUTANTS = [
     ("texture_height_from_first_edge", MAIN, "const double e2 = (double)V[6 + k] - (double)V[k];", "const double e2 = (double)V[3 + k] - (double)V[k];"),
     ("texture_layout_breaks_column_early", MAIN, "if (y + h > atlas_height) {", "if (y + h >= atlas_height) {"),
     ("texture_layout_column_width_last_map", MAIN, "if (w > col_w) col_w = w;", "col_w = w;"),
+    ("nearest_rounds_down", BODY, "REAL rx = RINT(e->xh), ry = RINT(e->yh);", "REAL rx = FLOOR(e->xh), ry = FLOOR(e->yh);"),
+    ("nearest_bilinear_bounds", BODY, "rx <= (REAL)(CW - 1) && ry >= (REAL)0 && ry <= (REAL)(CH - 1)", "rx <= (REAL)(CW - 2) && ry >= (REAL)0 && ry <= (REAL)(CH - 2)"),
+    ("nearest_ignored", MAIN, "out->hd_nearest = vol->hd_nearest ? 1.0 : 0.0;", "out->hd_nearest = 0.0;"),
     ("mesh_zero_counts_inside", MC, "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] < 0.0f)", "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] <= 0.0f)"),
     ("mesh_interpolation_from_far_end", MC, "const double t64 = (double)tsdf[u] / ((double)tsdf[u] - (double)tsdf[w]);", "const double t64 = (double)tsdf[w] / ((double)tsdf[w] - (double)tsdf[u]);"),
     ("mesh_no_half_voxel", MC, "c0[k] = vol->origin[k] + 0.5 * s[k];", "c0[k] = vol->origin[k];"),
@@ -89,7 +92,7 @@ MUTANTS = [
 
 PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py"),
              os.path.join(HERE, "test_raycast_pins.py"), os.path.join(HERE, "test_texture_pins.py"),
-             os.path.join(HERE, "test_mesh_pins.py")]
+             os.path.join(HERE, "test_mesh_pins.py"), os.path.join(HERE, "test_nearest_pins.py")]
 # A mistake in a body that only one operation includes runs that operation's pins; a
 # mistake in the shared source or the integration body runs them all.
 PINS_FOR = {RC: [os.path.join(HERE, "test_raycast_pins.py")],
