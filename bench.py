@@ -261,6 +261,24 @@ def main() -> int:
         out["fused_vs_plain"] = plain_wall / (wall / args.steps)
         log(f"plain: {1e3 * plain_wall:.2f} ms per scan; fused speedup {out['fused_vs_plain']:.2f}x")
 
+        # ---- the nearest-pixel HD sampling variant: the same scan and launch configuration
+        import dataclasses
+        spec_n = dataclasses.replace(spec, hd_sampling="nearest")
+        vol_n = kf.Volume(spec_n)
+
+        def nearest_step():
+            vol_n.reset()
+            kf.integrate_batch([(vol_n, scan)], frames_per_pass=K, use_graph=True)
+        nearest_step()
+        torch.cuda.synchronize()
+        tn = time.perf_counter()
+        for _ in range(3):
+            nearest_step()
+        torch.cuda.synchronize()
+        out["nearest_ms_per_step"] = 1e3 * (time.perf_counter() - tn) / 3
+        log(f"nearest-pixel HD sampling: {out['nearest_ms_per_step']:.2f} ms per scan")
+        del vol_n
+
         # ---- ray casting of the integrated volumes (the scan's poses, depth resolution)
         step = 0.8 * fr.trunc
         rc_poses = fr.T_world_from_cam[::10]

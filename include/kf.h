@@ -51,6 +51,16 @@ typedef enum {
     KF_RGBF32 = 1  /* float32 HWC, colour in [0,1] (any finite value works)  */
 } kf_pixfmt;
 
+/* How the colour update reads the HD image at the projection (x_hd, y_hd) of a colour
+ * voxel centre (Eq. 9).  Bilinear: between the four surrounding pixel centres (both must
+ * lie in the image: 0 <= floor(x_hd) <= CW-2, likewise y); the adjoint is defined for it.
+ * Nearest: the pixel whose centre is nearest (rint, ties to even), inside the image
+ * (0 <= rint(x_hd) <= CW-1, likewise y); the adjoint returns KF_E_UNSUPPORTED for it. */
+typedef enum {
+    KF_HD_BILINEAR = 0,
+    KF_HD_NEAREST = 1
+} kf_hd_sampling;
+
 /* Volume description.  Both volumes cover the same axis-aligned box (Sec. IV.B: the
  * colour volume has a higher dimension but the same size); voxel (i,j,k) has its centre
  * at origin + (i+1/2, j+1/2, k+1/2) * extent / dim; storage is x fastest.  Limits
@@ -64,6 +74,7 @@ typedef struct {
     double colour_band;     /* sigma: max distance from the measured surface point (m);
                                the paper uses 20 mm (Sec. IV.B)                           */
     double colour_gate;     /* update only if W > colour_gate * W_pre; paper: 0.8         */
+    int32_t hd_sampling;    /* kf_hd_sampling: how Eq. 9 reads HD(x_hd, y_hd)             */
 } kf_volume_desc;
 
 /* Six caller-owned device arrays of float32 (structure of arrays):

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libkfvol.so")
 
 KF_OK, KF_E_ARG, KF_E_SHAPE, KF_E_RANGE, KF_E_DEVICE, KF_E_UNSUPPORTED = range(6)
 KF_RGB8, KF_RGBF32 = 0, 1
+KF_HD_BILINEAR, KF_HD_NEAREST = 0, 1
 
 
 class KfError(RuntimeError):
@@ -20,7 +21,8 @@ class KfError(RuntimeError):
 class VolumeDesc(C.Structure):
     _fields_ = [("geom_dim", C.c_int32 * 3), ("colour_dim", C.c_int32 * 3),
                 ("origin", C.c_double * 3), ("extent", C.c_double * 3),
-                ("colour_band", C.c_double), ("colour_gate", C.c_double)]
+                ("colour_band", C.c_double), ("colour_gate", C.c_double),
+                ("hd_sampling", C.c_int32)]
 
 
 class VolumeBuffers(C.Structure):

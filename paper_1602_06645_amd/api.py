@@ -57,6 +57,10 @@ def volume_desc(spec) -> L.VolumeDesc:
     d.extent[:] = [float(x) for x in spec.extent]
     d.colour_band = float(spec.sigma)
     d.colour_gate = float(spec.gate)
+    mode = getattr(spec, "hd_sampling", "bilinear")
+    if mode not in ("bilinear", "nearest"):
+        raise ValueError(f"unknown HD sampling {mode!r}")
+    d.hd_sampling = L.KF_HD_NEAREST if mode == "nearest" else L.KF_HD_BILINEAR
     return d
 
 

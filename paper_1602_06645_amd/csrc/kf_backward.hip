@@ -62,7 +62,7 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     const float iqz = 1.0f / qz;
     const float x0 = floorf(fmaf(c.fxr, qx * iqz, c.cxr));
     const float y0 = floorf(fmaf(c.fyr, qy * iqz, c.cyr));
-    if (!(x0 >= 0.0f && x0 <= c.cwm2 && y0 >= 0.0f && y0 <= c.chm2)) return 0.0f;
+    if (!(x0 >= 0.0f && x0 <= c.hd_xmax && y0 >= 0.0f && y0 <= c.hd_ymax)) return 0.0f;
     return w;
 }
 

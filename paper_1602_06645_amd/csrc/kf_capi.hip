@@ -130,6 +130,8 @@ kf_status check_desc(const kf_volume_desc* d)
         return fail(KF_E_ARG, "colour_band must be finite and > 0");
     if (!isfinite(d->colour_gate) || d->colour_gate < 0.0)
         return fail(KF_E_ARG, "colour_gate must be finite and >= 0");
+    if (d->hd_sampling != KF_HD_BILINEAR && d->hd_sampling != KF_HD_NEAREST)
+        return fail(KF_E_ARG, "hd_sampling must be KF_HD_BILINEAR or KF_HD_NEAREST");
     return KF_OK;
 }
 
@@ -231,8 +233,11 @@ void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_r
     out->sigma = (float)vd.colour_band;
     out->wm1 = (float)(dw - 1);
     out->hm1 = (float)(dh - 1);
-    out->cwm2 = (float)(cw - 2);
-    out->chm2 = (float)(ch - 2);
+    // the last pixel a sample may start from: the cell's top-left (bilinear) or the pixel
+    const bool nearest = vd.hd_sampling == KF_HD_NEAREST;
+    out->hd_nearest = nearest ? 1 : 0;
+    out->hd_xmax = (float)(nearest ? cw - 1 : cw - 2);
+    out->hd_ymax = (float)(nearest ? ch - 1 : ch - 2);
     out->dw = dw;
     out->dh = dh;
     out->cw = cw;
@@ -886,6 +891,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
 {
     kf_status s = check_desc(desc);
     if (s != KF_OK) return s;
+    if (desc->hd_sampling != KF_HD_BILINEAR)
+        return fail(KF_E_UNSUPPORTED, "the adjoint is defined for bilinear HD sampling");
     if (n_frames < 0) return fail(KF_E_ARG, "n_frames < 0");
     if (n_frames > 64) return fail(KF_E_UNSUPPORTED, "the adjoint replays at most 64 frames per call");
     if (!grad_rgb_vol || !d_xi || (n_frames > 0 && !d_rgb))

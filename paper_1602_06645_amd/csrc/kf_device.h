@@ -31,7 +31,8 @@ struct FrameConsts {
     float fxr, fyr, cxr, cyr;              // K_hd
     float trunc, inv_trunc, w_max, sigma2, gate, sigma;
     float wm1, hm1;       // depth image W-1, H-1 (exact in float)
-    float cwm2, chm2;     // HD image CW-2, CH-2
+    float hd_xmax, hd_ymax;  // largest first pixel of an HD sample: CW-2, CH-2 (bilinear)
+                             // or CW-1, CH-1 (nearest pixel)
     int32_t dw, dh, cw, ch;
     const float* depth;   // [dh][dw]
     const void* rgb;      // [ch][cw][3], uint8 or float
@@ -39,6 +40,7 @@ struct FrameConsts {
     float* wmap;          // [dh][dw] colour weight W of each depth pixel (Eq. 8 normal and
                           // the viewing ray), or kNoNormal
     int32_t pyr_w0, pyr_h0, pyr_levels;
+    int32_t hd_nearest;   // 1: Eq. 9 reads the nearest HD pixel; 0: the bilinear sample
 };
 
 // Weight-map entry of a pixel without a normal (no depth at the pixel or a neighbour, a

@@ -40,11 +40,13 @@ __device__ __forceinline__ float hd_px(const void* rgb, int idx)
         return ((const float*)rgb)[idx];
 }
 
-// Bilinear HD sample of channel ch at the cell whose top-left pixel's first channel is
-// at `cell`: Eq. 9's HD(x_hd, y_hd) read between pixel centres.
-__device__ __forceinline__ float hd_sample(const void* rgb, int fmt, int cell, int row, int ch,
-                                           float ax, float ay)
+// HD sample of channel ch (Eq. 9's HD(x_hd, y_hd)): bilinear between pixel centres at the
+// cell whose top-left pixel's first channel is at `cell`, or (nearest) that pixel alone.
+__device__ __forceinline__ float hd_sample(const void* rgb, int fmt, bool nearest, int cell, int row,
+                                           int ch, float ax, float ay)
 {
+    if (nearest)
+        return fmt == FMT_RGB8 ? hd_px<FMT_RGB8>(rgb, cell + ch) : hd_px<FMT_RGBF32>(rgb, cell + ch);
     float p00, p10, p01, p11;
     if (fmt == FMT_RGB8) {
         p00 = hd_px<FMT_RGB8>(rgb, cell + ch);
@@ -246,7 +248,8 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
 // --------------------------------------------------------------- colour (Sec. IV.B)
 
 // HD pixel of a colour voxel centre (Eq. 3-5 composed into one affine map, then Eq. 4's
-// division) and its bilinear cell: inside when the cell's four pixels are in the image.
+// division) and its bilinear cell (inside when the cell's four pixels are in the image),
+// or the nearest pixel (inside when it is in the image).
 struct HdCell {
     bool inside;
     int cell;        // index of the cell's top-left pixel's first channel
@@ -262,9 +265,9 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
     const float iqz = 1.0f / qz;
     const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
     const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
-    const float x0 = floorf(xh), y0 = floorf(yh);
+    const float x0 = c.hd_nearest ? rintf(xh) : floorf(xh), y0 = c.hd_nearest ? rintf(yh) : floorf(yh);
     HdCell h;
-    h.inside = (qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.cwm2) & (y0 >= 0.0f) & (y0 <= c.chm2);
+    h.inside = (qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.hd_xmax) & (y0 >= 0.0f) & (y0 <= c.hd_ymax);
     h.ax = xh - x0;
     h.ay = yh - y0;
     h.cell = h.inside ? ((int)y0 * c.cw + (int)x0) * 3 : 0;
@@ -384,12 +387,13 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                     cl |= needc;
                 }
                 const int row = c.cw * 3;
+                const bool nearest = c.hd_nearest != 0;
 #pragma unroll
                 for (int kk = 0; kk < ZS; ++kk) {
                     if ((upd >> kk) & 1u) {
-                        const float s0 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 0, ax[kk], ay[kk]);
-                        const float s1 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 1, ax[kk], ay[kk]);
-                        const float s2 = hd_sample(c.rgb, sc.fmt, cell[kk], row, 2, ax[kk], ay[kk]);
+                        const float s0 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 0, ax[kk], ay[kk]);
+                        const float s1 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 1, ax[kk], ay[kk]);
+                        const float s2 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 2, ax[kk], ay[kk]);
                         const float alpha = wv[kk] / (Wt[kk] + wv[kk]);
                         R[kk] = fmaf(alpha, s0 - R[kk], R[kk]);
                         G[kk] = fmaf(alpha, s1 - G[kk], G[kk]);

@@ -55,12 +55,12 @@ def scene(vol, fr, keep):
     return s
 
 
-def forward_case(pairs, K):
+def forward_case(pairs, K, specs=None):
     keep = []
     arr = (L.Scene * len(pairs))(*[scene(v, f, keep) for v, f in pairs])
     check(lib.kf_integrate_batch(arr, len(pairs), K, 0, None))
     worst = 0
-    for (v, fr), spec in zip(pairs, SPECS):
+    for (v, fr), spec in zip(pairs, specs or SPECS):
         st = O.State(spec, np.float32)
         O.integrate(spec, fr, st)
         for a, b in zip(v.arrs, st.arrays()):
@@ -248,6 +248,13 @@ out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.
 tick("forward")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
+# nearest-pixel HD sampling: an 8-bit scan and a float one on the odd volume
+import dataclasses  # noqa: E402
+near6, near_odd = (dataclasses.replace(s_, hd_sampling="nearest") for s_ in (spec6, spec_odd))
+out["nearest_mismatches"] = forward_case([(Vol(near6), fr6), (Vol(near_odd), fr32.as_float_rgb())], 8,
+                                         [near6, near_odd])
+out["nearest_status_mismatches"] = status_case(near6, fr6)
+tick("nearest")
 out["raycast_mismatches"] = raycast_case(spec6, fr6)
 tick("raycast")
 out["texture_mismatches"] = texture_case(spec6, fr6)

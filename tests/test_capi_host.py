@@ -276,6 +276,22 @@ def test_texture_rejects_bad_arguments():
         lib.kf_volume_destroy(h1)
 
 
+def test_hd_sampling_is_validated():
+    lib = L.load()
+    out = (C.c_size_t * 6)()
+    for mode, code in ((L.KF_HD_BILINEAR, L.KF_OK), (L.KF_HD_NEAREST, L.KF_OK), (2, L.KF_E_ARG),
+                       (-1, L.KF_E_ARG)):
+        d = _desc()
+        d.hd_sampling = mode
+        assert lib.kf_volume_buffer_bytes(C.byref(d), out) == code
+    # the adjoint is defined for bilinear sampling only
+    d = _desc()
+    d.hd_sampling = L.KF_HD_NEAREST
+    args = [C.byref(d), None, 1, C.c_void_p(0x1), C.c_void_p(0x1), 640, 480, 1920, 1080,
+            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None]
+    assert lib.kf_integrate_backward(*args) == L.KF_E_UNSUPPORTED
+
+
 def test_mesh_rejects_bad_arguments():
     lib = L.load()
     counts = np.zeros(2, np.int64)

@@ -48,6 +48,7 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert res["status_mismatches"] == 0
     assert res["raycast_mismatches"] == 0
     assert res["texture_mismatches"] == 0
+    assert res["nearest_mismatches"] == 0 and res["nearest_status_mismatches"] == 0
     assert res["mesh_mismatches"] == 0
     for case in ("backward_6", "backward_32", "backward_odd"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
