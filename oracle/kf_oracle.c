@@ -189,9 +189,24 @@ static void colour_values_f64(const or_fc__f64* c, const float* D, int W, int u,
 
 void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
                      const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
-                     double* d_xi)
+                     double* d_xi, double* d_pose)
 {
     if (vol->hd_nearest) return;
+    /* world -> HD camera rotation of each frame, R_rd R_wc^T, for the pose gradient */
+    double* Rqw = (double*)calloc((size_t)(fr->n_frames > 0 ? fr->n_frames : 1) * 9, sizeof(double));
+    for (int f = 0; f < fr->n_frames; ++f) {
+        const double* Tw = fr->T_world_from_cam + 16 * (size_t)f;
+        const double* Td = fr->T_rgb_from_d;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int m = 0; m < 3; ++m) acc += Td[4 * r + m] * Tw[4 * c + m];   /* R_wc^T[m][c] */
+                Rqw[9 * f + 3 * r + c] = acc;
+            }
+    }
+    if (d_pose) memset(d_pose, 0, sizeof(double) * 6 * (size_t)(fr->n_frames > 0 ? fr->n_frames : 0));
+    double cs[3];
+    for (int q = 0; q < 3; ++q) cs[q] = vol->extent[q] / vol->cdim[q];
     int n = fr->n_frames;
     or_fc64* fc64 = all_consts(vol, fr);
     or_fc__f64* fc = (or_fc__f64*)malloc(sizeof(or_fc__f64) * (size_t)(n > 0 ? n : 1));
@@ -287,6 +302,25 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
                         xi3 += e->q[1] * a[2] - e->q[2] * a[1];
                         xi4 += e->q[2] * a[0] - e->q[0] * a[2];
                         xi5 += e->q[0] * a[1] - e->q[1] * a[0];
+                        if (d_pose) {
+                            /* T_world_from_cam <- exp(xi) T_world_from_cam moves the voxel's
+                             * camera point by -R_cw (rho + phi x p_w), so dq = -R_qw (rho +
+                             * phi x p_w): with b = R_qw^T a, dL/drho = -b, dL/dphi = b x p_w */
+                            const double* R = Rqw + 9 * (size_t)f;
+                            double b[3], pw[3];
+                            for (int m = 0; m < 3; ++m)
+                                b[m] = R[m] * a[0] + R[3 + m] * a[1] + R[6 + m] * a[2];
+                            pw[0] = vol->origin[0] + ((double)i + 0.5) * cs[0];
+                            pw[1] = vol->origin[1] + ((double)j + 0.5) * cs[1];
+                            pw[2] = vol->origin[2] + ((double)k + 0.5) * cs[2];
+                            double* dp = d_pose + 6 * (size_t)f;
+                            const double v6[6] = {-b[0], -b[1], -b[2], b[1] * pw[2] - b[2] * pw[1],
+                                                  b[2] * pw[0] - b[0] * pw[2], b[0] * pw[1] - b[1] * pw[0]};
+                            for (int m = 0; m < 6; ++m) {
+                                #pragma omp atomic
+                                dp[m] += v6[m];
+                            }
+                        }
                     }
                 }
             }
@@ -299,6 +333,7 @@ void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc
     free(fc);
     free(fc32);
     free(fc64);
+    free(Rqw);
 }
 
 /* ---- ray casting (see kf_raycast_body.h for the steps) */

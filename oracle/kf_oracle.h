@@ -105,12 +105,16 @@ void or_integrate_f64(const or_volume* vol, const or_frames* fr, double* tsdf, d
  * decide_f32 = 0: every step in FP64 (the adjoint of the FP64 forward).
  * decide_f32 = 1: the integer decisions (depth pixel, the tests of Sec. IV.B, the
  * bilinear cell) are those of the FP32 forward; the values stay FP64.
+ * d_pose (NULL to skip): [n][6], dL/dxi_n for the depth-camera poses, xi_n = (rho, phi) a
+ * left perturbation in world coordinates T_world_from_cam[n] <- exp(xi_n^) T_world_from_cam[n]
+ * at xi_n = 0, with the integer decisions held (the derivative wherever no decision
+ * changes): only the HD sample position of each update moves with the pose.
  * Defined for bilinear HD sampling only (vol->hd_nearest == 0); otherwise nothing is
  * written.
  */
 void or_backward_f64(const or_volume* vol, const or_frames* fr, const double* wc0,
                      const double* g, int cz0, int cz1, int decide_f32, double* d_rgb,
-                     double* d_xi);
+                     double* d_xi, double* d_pose);
 
 /*
  * Ray casting of the volumes (the rendering the method uses for live feedback and the

@@ -80,7 +80,7 @@ def lib():
                 [C.c_int] * 6 + [p, p, p]
             fn.restype = None
         L.or_backward_f64.argtypes = [C.POINTER(_Volume), C.POINTER(_Frames), p, p,
-                                      C.c_int, C.c_int, C.c_int, p, p]
+                                      C.c_int, C.c_int, C.c_int, p, p, p]
         L.or_backward_f64.restype = None
         for name in ("or_raycast_f32", "or_raycast_f64"):
             fn = getattr(L, name)
@@ -219,12 +219,13 @@ def status(vol, fr, state: State, frame: int):
 
 
 def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None,
-             decide_f32: bool = False):
+             decide_f32: bool = False, pose: bool = False):
     """FP64 adjoint: d L / d RGB ([n][ch][cw][3]) and d L / d xi (6) for
     L = sum g[ch][v] C_N(v)_ch over colour slabs cz; g has shape (3, n_slab_voxels).
     decide_f32: take the integer decisions (pixel, masks, gate, bilinear cell) of the
-    FP32 forward, as the GPU kernel does; otherwise everything is FP64.  Defined for
-    bilinear HD sampling only."""
+    FP32 forward, as the GPU kernel does; otherwise everything is FP64.  pose: also
+    return d L / d xi_n (n, 6) for the depth-camera poses (left perturbations in world
+    coordinates, decisions held).  Defined for bilinear HD sampling only."""
     if getattr(vol, "hd_sampling", "bilinear") != "bilinear":
         raise ValueError("the adjoint is defined for bilinear HD sampling")
     keep: list = []
@@ -234,11 +235,12 @@ def backward(vol, fr, g: np.ndarray, cz=None, wc0: np.ndarray | None = None,
     d_rgb = np.zeros((f.n_frames, f.ch, f.cw, 3), np.float64)
     d_xi = np.zeros(6, np.float64)
     w0 = None if wc0 is None else _c(wc0, np.float64)
+    d_pose = np.zeros((f.n_frames, 6), np.float64)
     lib().or_backward_f64(C.byref(_vol(vol)), C.byref(f),
                           None if w0 is None else w0.ctypes.data, g.ctypes.data,
                           int(cz[0]), int(cz[1]), int(decide_f32), d_rgb.ctypes.data,
-                          d_xi.ctypes.data)
-    return d_rgb, d_xi
+                          d_xi.ctypes.data, d_pose.ctypes.data if pose else None)
+    return (d_rgb, d_xi, d_pose) if pose else (d_rgb, d_xi)
 
 
 def raycast_consts(vol, K, T_world_from_cam, delta: float) -> dict:

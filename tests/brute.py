@@ -195,7 +195,7 @@ def _colour(vol, fr, m, wc0, record):
         status[f] = st
         if record:
             rec.append(dict(upd=hd, alpha=alpha, xh=xh, yh=yh, q=q, gx=gx, gy=gy,
-                            x0=x0, y0=y0, ax=ax, ay=ay))
+                            x0=x0, y0=y0, ax=ax, ay=ay, u=u, v=v))
     out = dict(r=C[:, 0], g=C[:, 1], b=C[:, 2], wc=Wc, ambiguous=amb, status=status)
     if record:
         out["frames"] = rec

@@ -182,3 +182,74 @@ def test_fp32_decision_mode_agrees_away_from_ties(oracle):
     assert np.abs(x64).max() > 1e-2
     np.testing.assert_allclose(x32, x64, rtol=1e-3, atol=1e-3 * np.abs(x64).max())
     np.testing.assert_allclose(r32, r64, rtol=1e-3, atol=1e-3 * np.abs(r64).max())
+
+
+# ---- depth-camera poses: T_world_from_cam[n] <- exp(xi_n^) T_world_from_cam[n]
+
+def _pose_perturbed(fr, f, xi):
+    fr2 = fr.select(slice(0, fr.n))
+    fr2.T_world_from_cam = fr.T_world_from_cam.copy()
+    fr2.T_world_from_cam[f] = expm(hat(xi)) @ fr.T_world_from_cam[f]
+    return fr2
+
+
+def test_depth_pose_gradient_central_differences(oracle):
+    """64 seeded voxels whose depth pixels, update masks and bilinear cells stay put under
+    every +-h perturbation of every frame's pose; per-frame gradients against FP64 central
+    differences."""
+    vol, fr = _scan(n=3, g=24, ratio=2)
+    h = 1e-4
+    base = brute.colour(vol, fr, record=True)
+    keep = base["wc"] > 0
+    for f in range(fr.n):
+        for k in range(6):
+            for sgn in (-1, 1):
+                e = np.zeros(6)
+                e[k] = sgn * h
+                rec = brute.colour(vol, _pose_perturbed(fr, f, e), record=True)["frames"]
+                for r0, r1 in zip(base["frames"], rec):
+                    keep &= r0["upd"] == r1["upd"]
+                    keep &= ~r0["upd"] | ((r0["x0"] == r1["x0"]) & (r0["y0"] == r1["y0"]) &
+                                          (r0["u"] == r1["u"]) & (r0["v"] == r1["v"]))
+    for r0 in base["frames"]:
+        keep &= ~r0["upd"] | ((r0["ax"] > 0.02) & (r0["ax"] < 0.98) & (r0["ay"] > 0.02) & (r0["ay"] < 0.98))
+    cand = np.flatnonzero(keep)
+    assert len(cand) >= 64
+    rng = np.random.default_rng(5006)
+    sel = rng.choice(cand, 64, replace=False)
+    g = np.zeros((3, vol.n_colour))
+    g[:, sel] = rng.standard_normal((3, 64))
+    _, _, d_pose = oracle.backward(vol, fr, g, pose=True)
+    fd = np.zeros((fr.n, 6))
+    for f in range(fr.n):
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = h
+            lp = _loss(oracle, vol, _pose_perturbed(fr, f, e), g)[0]
+            lm = _loss(oracle, vol, _pose_perturbed(fr, f, -e), g)[0]
+            fd[f, k] = (lp - lm) / (2 * h)
+    assert np.abs(fd).max() > 1e-3
+    np.testing.assert_allclose(d_pose, fd, rtol=1e-3, atol=1e-3 * np.abs(fd).max())
+
+
+def test_depth_pose_and_extrinsic_adjoints_agree(oracle):
+    """With one frame, perturbing the pose by xi moves the HD-camera point as perturbing the
+    extrinsic by -Ad(T_hd_from_world) xi: d_pose = -Ad^T d_xi (two derivations of the same
+    chain: through the world point, and through the HD-camera point)."""
+    vol, fr = _scan(n=1, g=24, ratio=2)
+    g = np.random.default_rng(12).standard_normal((3, vol.n_colour))
+    _, d_xi, d_pose = oracle.backward(vol, fr, g, pose=True)
+    T = fr.T_rgb_from_d @ np.linalg.inv(fr.T_world_from_cam[0])
+    R, t = T[:3, :3], T[:3, 3]
+    tx = np.array([[0, -t[2], t[1]], [t[2], 0, -t[0]], [-t[1], t[0], 0]])
+    Ad = np.block([[R, tx @ R], [np.zeros((3, 3)), R]])
+    assert np.abs(d_xi).max() > 1e-2
+    np.testing.assert_allclose(d_pose[0], -Ad.T @ d_xi, rtol=1e-9, atol=1e-9 * np.abs(d_xi).max())
+
+
+def test_constant_image_has_zero_depth_pose_gradient(oracle):
+    vol, fr = _scan()
+    fr.rgb = np.full_like(fr.rgb, 0.4)
+    g = np.random.default_rng(9).standard_normal((3, vol.n_colour))
+    _, _, d_pose = oracle.backward(vol, fr, g, pose=True)
+    assert d_pose.shape == (fr.n, 6) and (d_pose == 0).all()

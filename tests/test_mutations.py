@@ -78,6 +78,9 @@ MUTANTS = [
     ("nearest_rounds_down", BODY, "REAL rx = RINT(e->xh), ry = RINT(e->yh);", "REAL rx = FLOOR(e->xh), ry = FLOOR(e->yh);"),
     ("nearest_bilinear_bounds", BODY, "rx <= (REAL)(CW - 1) && ry >= (REAL)0 && ry <= (REAL)(CH - 1)", "rx <= (REAL)(CW - 2) && ry >= (REAL)0 && ry <= (REAL)(CH - 2)"),
     ("nearest_ignored", MAIN, "out->hd_nearest = vol->hd_nearest ? 1.0 : 0.0;", "out->hd_nearest = 0.0;"),
+    ("pose_rho_sign", MAIN, "const double v6[6] = {-b[0], -b[1], -b[2],", "const double v6[6] = {b[0], b[1], b[2],"),
+    ("pose_rotation_transposed", MAIN, "b[m] = R[m] * a[0] + R[3 + m] * a[1] + R[6 + m] * a[2];", "b[m] = R[3 * m] * a[0] + R[3 * m + 1] * a[1] + R[3 * m + 2] * a[2];"),
+    ("pose_no_half_voxel", MAIN, "pw[0] = vol->origin[0] + ((double)i + 0.5) * cs[0];", "pw[0] = vol->origin[0] + (double)i * cs[0];"),
     ("mesh_zero_counts_inside", MC, "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] < 0.0f)", "if (tsdf[LIN(x + (c & 1), y + ((c >> 1) & 1), z + ((c >> 2) & 1))] <= 0.0f)"),
     ("mesh_interpolation_from_far_end", MC, "const double t64 = (double)tsdf[u] / ((double)tsdf[u] - (double)tsdf[w]);", "const double t64 = (double)tsdf[w] / ((double)tsdf[w] - (double)tsdf[u]);"),
     ("mesh_no_half_voxel", MC, "c0[k] = vol->origin[k] + 0.5 * s[k];", "c0[k] = vol->origin[k];"),
@@ -90,9 +93,9 @@ MUTANTS = [
     ("mesh_last_cube_column_dropped", MC, "for (int64_t x = 0; x + 1 < X; ++x) {", "for (int64_t x = 0; x + 2 < X; ++x) {"),
 ]
 
-PIN_FILES = [os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_backward_pins.py"),
-             os.path.join(HERE, "test_raycast_pins.py"), os.path.join(HERE, "test_texture_pins.py"),
-             os.path.join(HERE, "test_mesh_pins.py"), os.path.join(HERE, "test_nearest_pins.py")]
+PIN_FILES = [os.path.join(HERE, n) for n in (
+    "test_oracle_pins.py", "test_nearest_pins.py", "test_raycast_pins.py", "test_texture_pins.py",
+    "test_mesh_pins.py", "test_backward_pins.py")]     # slowest last (each run stops at a failure)
 # A mistake in a body that only one operation includes runs that operation's pins; a
 # mistake in the shared source or the integration body runs them all.
 PINS_FOR = {RC: [os.path.join(HERE, "test_raycast_pins.py")],
