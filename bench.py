@@ -374,6 +374,19 @@ def main() -> int:
         out["fwd_bwd_ms"] = 1e3 * (time.perf_counter() - tb) / reps
         out["fwd_bwd_config"] = f"first {nb} frames, float32 RGB, full volume, g ~ N(0,1) on every colour voxel"
         log(f"forward+backward ({nb} frames): {out['fwd_bwd_ms']:.2f} ms")
+
+        def fwd_bwd_pose():
+            vol.reset()
+            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
+            return kf.integrate_backward(spec, scan32, g, pose=True)
+        fwd_bwd_pose()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(reps):
+            fwd_bwd_pose()
+        torch.cuda.synchronize()
+        out["fwd_bwd_pose_ms"] = 1e3 * (time.perf_counter() - tb) / reps
+        log(f"forward+backward with the {nb} depth-pose gradients: {out['fwd_bwd_pose_ms']:.2f} ms")
         del rgbf, scan32, g
 
     if not args.no_cpu:

@@ -196,7 +196,13 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
  * weights w_col0 (device, prod(colour_dim) floats, or NULL for zeros), writes
  *   d_rgb: device float32 [n][ch][cw][3], overwritten with dL/dRGB;
  *   d_xi:  device float64 [6], overwritten with dL/dxi, xi = (rho, phi) the se(3) left
- *          perturbation T_rgb_from_d <- exp(xi^) T_rgb_from_d at xi = 0.
+ *          perturbation T_rgb_from_d <- exp(xi^) T_rgb_from_d at xi = 0;
+ *   d_pose: device float64 [n][6] or NULL, overwritten with dL/dxi_n for the depth-camera
+ *          poses, xi_n the left perturbation in world coordinates T_world_from_cam[n] <-
+ *          exp(xi_n^) T_world_from_cam[n] at xi_n = 0.  The depth pixel, the tests of
+ *          Sec. IV.B and the bilinear cell are held (the derivative wherever none of them
+ *          changes); the pose then moves only where each update samples the HD image, and
+ *          d_pose[n] = -Ad(T_hd_from_world[n])^T of frame n's extrinsic contribution.
  * The per-frame blending weights are recomputed from the depth maps (nothing from the
  * forward is stored).  The geometry volume and the colour weights do not depend on the
  * HD images or the extrinsic (except where a sample leaves the HD image), so they have no
@@ -208,7 +214,7 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
                                 const double K_d[9], const double K_rgb[9],
                                 const double T_rgb_from_d[16], const double* T_world_from_cam,
                                 const float* grad_rgb_vol, float* d_rgb,
-                                double* d_xi, void* stream);
+                                double* d_xi, double* d_pose, void* stream);
 
 /*
  * Ray cast the volumes from a camera (the rendering the method uses for live feedback and

@@ -53,7 +53,7 @@ SIGNATURES = {
                                            C.POINTER(C.c_void_p), _I, _P]),
     "kf_debug_status": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P, _P, _P]),
     "kf_integrate_backward": (C.c_int, [C.POINTER(VolumeDesc), _P, _I, _P, _P, _I, _I, _I, _I,
-                                        _P, _P, _P, _P, _P, _P, _P, _P]),
+                                        _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "kf_raycast": (C.c_int, [_P, _I, _I, _P, _P, _D, _P, _P, _P, _P, _P]),
     "kf_texture_layout": (C.c_int, [_I, _P, _D, _I, _P, C.POINTER(_I)]),
     "kf_mesh_extract": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, _P, _P]),

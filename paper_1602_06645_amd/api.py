@@ -276,9 +276,11 @@ def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:
     return cnt.cpu().numpy()
 
 
-def integrate_backward(spec, scan: Scan, grad: torch.Tensor, w_col0: torch.Tensor | None = None):
+def integrate_backward(spec, scan: Scan, grad: torch.Tensor, w_col0: torch.Tensor | None = None,
+                       pose: bool = False):
     """dL/dRGB [n,CH,CW,3] float32 and dL/dxi [6] float64 (device) for
-    L = sum grad[c][v] C_N(v)_c; scan.rgb must be float32."""
+    L = sum grad[c][v] C_N(v)_c; scan.rgb must be float32.  pose: also dL/dxi_n [n,6]
+    float64 for the depth-camera poses (left perturbations in world coordinates)."""
     if scan.fmt != L.KF_RGBF32:
         raise ValueError("the adjoint takes float32 images")
     nc = int(np.prod(spec.cdim))
@@ -292,6 +294,7 @@ def integrate_backward(spec, scan: Scan, grad: torch.Tensor, w_col0: torch.Tenso
     n = scan.depth.shape[0]
     d_rgb = torch.empty_like(scan.rgb)
     d_xi = torch.empty(6, dtype=torch.float64, device=scan.rgb.device)
+    d_pose = torch.empty((n, 6), dtype=torch.float64, device=scan.rgb.device) if pose else None
     desc = volume_desc(spec)
     L.check(L.load().kf_integrate_backward(
         C.byref(desc), None if w_col0 is None else C.c_void_p(w_col0.data_ptr()), n,
@@ -299,5 +302,5 @@ def integrate_backward(spec, scan: Scan, grad: torch.Tensor, w_col0: torch.Tenso
         scan.depth.shape[2], scan.depth.shape[1], scan.rgb.shape[2], scan.rgb.shape[1],
         _ptr(scan.K_d), _ptr(scan.K_rgb), _ptr(scan.T_rgb_from_d), _ptr(scan.T_world_from_cam),
         C.c_void_p(grad.data_ptr()), C.c_void_p(d_rgb.data_ptr()), C.c_void_p(d_xi.data_ptr()),
-        _stream()))
-    return d_rgb, d_xi
+        None if d_pose is None else C.c_void_p(d_pose.data_ptr()), _stream()))
+    return (d_rgb, d_xi, d_pose) if pose else (d_rgb, d_xi)

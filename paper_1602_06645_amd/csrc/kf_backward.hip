@@ -139,12 +139,16 @@ __global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
 }
 
 // HIST: LDS floats per lane for the alpha history (at least the frames of the call).
-template <int HIST>
+// POSE: also the per-frame extrinsic partials of each brick (for the depth-pose adjoint),
+// summed per frame in the wave's LDS and written as one row per brick.
+template <int HIST, bool POSE>
 __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
 {
     __shared__ float s_alpha[BLOCK * HIST];   // lane t of wave w: [w][f][t]
+    __shared__ double s_pose[POSE ? (BLOCK / WAVE) * HIST * 6 : 1];
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     float* hist = s_alpha + wave * WAVE * HIST + lane;
+    double* facc = s_pose + (POSE ? wave * HIST * 6 : 0);
     const size_t nvox = (size_t)a.cdim[0] * (size_t)a.cdim[1] * (size_t)a.cdim[2];
     const uint32_t n_live = *a.n_live;
     for (;;) {
@@ -159,6 +163,12 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
         const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
         const int i = bx * CBX + lane % CBX, j = by * CBY + lane / CBX, k0 = bz * ZS;
         double xi[6] = {0, 0, 0, 0, 0, 0};
+        if constexpr (POSE) {
+            for (int q = lane; q < a.n_frames * 6; q += WAVE) facc[q] = 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         if (i < a.cdim[0] && j < a.cdim[1]) {
             const float fi = (float)i, fj = (float)j;
             const int kn = min(ZS, a.cdim[2] - k0);
@@ -230,6 +240,15 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
                     xi[3] += (double)qy * dqz - (double)qz * dqy;
                     xi[4] += (double)qz * dqx - (double)qx * dqz;
                     xi[5] += (double)qx * dqy - (double)qy * dqx;
+                    if constexpr (POSE) {
+                        double* fa = facc + f * 6;
+                        atomicAdd(fa + 0, dqx);
+                        atomicAdd(fa + 1, dqy);
+                        atomicAdd(fa + 2, dqz);
+                        atomicAdd(fa + 3, (double)qy * dqz - (double)qz * dqy);
+                        atomicAdd(fa + 4, (double)qz * dqx - (double)qx * dqz);
+                        atomicAdd(fa + 5, (double)qx * dqy - (double)qy * dqx);
+                    }
                 }
             }
         }
@@ -241,6 +260,47 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
         const int q = lane % 6;
         const double sq = q == 0 ? s0 : q == 1 ? s1 : q == 2 ? s2 : q == 3 ? s3 : q == 4 ? s4 : s5;
         a.partials[(size_t)li * 6 + q] = sq;
+        if constexpr (POSE) {
+            // the brick's per-frame partials, one row per brick (indexed by the brick, so the
+            // reduction order does not depend on scheduling)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double* row = a.pose_partials + (size_t)li * (size_t)a.n_frames * 6;
+            for (int c = lane; c < a.n_frames * 6; c += WAVE) row[c] = facc[c];
+        }
+    }
+}
+
+// Column sums of a [n_rows][width] double array over rows [b * span, (b + 1) * span) for
+// block b: thread t adds columns t, t + 256, ... row by row in order (deterministic).
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const double* rows, uint32_t n_rows,
+                                                          uint32_t width, uint32_t span, double* out)
+{
+    const uint32_t r0 = blockIdx.x * span, r1 = min(n_rows, r0 + span);
+    for (uint32_t c = threadIdx.x; c < width; c += 256) {
+        double acc = 0.0;
+        for (uint32_t r = r0; r < r1; ++r) acc += rows[(size_t)r * width + c];
+        out[(size_t)blockIdx.x * width + c] = acc;
+    }
+}
+
+// d_pose[f] = -Ad(T_f)^T x_f for the frame's extrinsic partial x_f = (x_rho, x_phi) and
+// T_f = T_hd_from_world = (R, t): rho part -R^T x_rho, phi part R^T (t x x_rho - x_phi).
+__global__ __launch_bounds__(64) void pose_adjoint_kernel(const double* x, const double* T,
+                                                          int32_t n_frames, double* d_pose)
+{
+    const int f = (int)(blockIdx.x * 64 + threadIdx.x);
+    if (f >= n_frames) return;
+    const double* R = T + 12 * (size_t)f;
+    const double* t = R + 9;
+    const double* xr = x + 6 * (size_t)f;
+    const double* xp = xr + 3;
+    const double c[3] = {t[1] * xr[2] - t[2] * xr[1] - xp[0], t[2] * xr[0] - t[0] * xr[2] - xp[1],
+                         t[0] * xr[1] - t[1] * xr[0] - xp[2]};
+    for (int m = 0; m < 3; ++m) {
+        d_pose[6 * (size_t)f + m] = -(R[m] * xr[0] + R[3 + m] * xr[1] + R[6 + m] * xr[2]);
+        d_pose[6 * (size_t)f + 3 + m] = R[m] * c[0] + R[3 + m] * c[1] + R[6 + m] * c[2];
     }
 }
 
@@ -268,21 +328,23 @@ __global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, 
     if (threadIdx.x < 6) out[(size_t)blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-template <int HIST>
+template <int HIST, bool POSE>
 static hipError_t launch_backward_hist(const BackwardArgs& a, int device, hipStream_t stream)
 {
     int n_cu = 0, per_cu = 0;
     hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_kernel<HIST>, BLOCK, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_kernel<HIST, POSE>, BLOCK, 0);
     if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)(n_cu * (per_cu > 0 ? per_cu : 1));
-    hipLaunchKernelGGL(backward_kernel<HIST>, dim3(grid), dim3(BLOCK), 0, stream, a);
+    hipLaunchKernelGGL((backward_kernel<HIST, POSE>), dim3(grid), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipStream_t stream)
+hipError_t launch_backward(const BackwardArgs& a, double* d_xi, double* d_pose, int device,
+                           hipStream_t stream)
 {
+    const bool pose = d_pose != nullptr && a.pose_partials != nullptr;
     if (a.n_frames > BWD_MAX_FRAMES) return hipErrorInvalidValue;
     if (a.n_items > 0) {
         const uint32_t chunks = (uint32_t)((a.cbricks[0] + CHUNK - 1) / CHUNK) *
@@ -291,8 +353,27 @@ hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipS
         hipLaunchKernelGGL(backward_cull_kernel, dim3(chunks), dim3(BLOCK), 0, stream, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = a.n_frames <= 32 ? launch_backward_hist<32>(a, device, stream)
-                             : launch_backward_hist<64>(a, device, stream);
+        if (pose)
+            e = a.n_frames <= 32 ? launch_backward_hist<32, true>(a, device, stream)
+                                 : launch_backward_hist<64, true>(a, device, stream);
+        else
+            e = a.n_frames <= 32 ? launch_backward_hist<32, false>(a, device, stream)
+                                 : launch_backward_hist<64, false>(a, device, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (pose && a.n_frames > 0) {
+        // per-frame column sums over the bricks (two fixed-order stages), then the adjoint map
+        const uint32_t width = (uint32_t)a.n_frames * 6;
+        double* stage = a.pose_partials + (size_t)a.n_items * width;
+        double* sums = stage + (size_t)XI_BLOCKS * width;
+        const uint32_t span = (a.n_items + XI_BLOCKS - 1) / XI_BLOCKS;
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(XI_BLOCKS), dim3(256), 0, stream,
+                           (const double*)a.pose_partials, a.n_items, width, span > 0 ? span : 1u, stage);
+        hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, stream, (const double*)stage,
+                           (uint32_t)XI_BLOCKS, width, (uint32_t)XI_BLOCKS, sums);
+        hipLaunchKernelGGL(pose_adjoint_kernel, dim3((a.n_frames + 63) / 64), dim3(64), 0, stream,
+                           (const double*)sums, a.pose_adjoint, a.n_frames, d_pose);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     // stage 1 writes XI_BLOCKS block sums after the partials (a.partials holds room for them)

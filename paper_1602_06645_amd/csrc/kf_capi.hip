@@ -887,7 +887,7 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
                                 const double K_d[9], const double K_rgb[9],
                                 const double T_rgb_from_d[16], const double* T_world_from_cam,
                                 const float* grad_rgb_vol, float* d_rgb, double* d_xi,
-                                void* stream)
+                                double* d_pose, void* stream)
 {
     kf_status s = check_desc(desc);
     if (s != KF_OK) return s;
@@ -932,7 +932,13 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     const size_t live_off = align(counters_off + 2 * sizeof(uint32_t));
     const size_t partials_off = align(live_off + (size_t)a.n_items * sizeof(uint4));
     // per-brick partials, then the block sums of the first reduction stage
-    const size_t pyr_off = align(partials_off + ((size_t)a.n_items + kf::XI_BLOCKS) * 6 * sizeof(double));
+    const size_t pose_t_off = align(partials_off + ((size_t)a.n_items + kf::XI_BLOCKS) * 6 * sizeof(double));
+    // depth-pose adjoint: per-frame T_hd_from_world, then per-brick per-frame partials,
+    // the first-stage block sums and the per-frame sums
+    const bool pose = d_pose != nullptr && n_frames > 0;
+    const size_t width = (size_t)n_frames * 6;
+    const size_t pose_p_off = align(pose_t_off + (pose ? (size_t)n_frames * 12 * sizeof(double) : 0));
+    const size_t pyr_off = align(pose_p_off + (pose ? ((size_t)a.n_items + kf::XI_BLOCKS + 1) * width * sizeof(double) : 0));
     size_t off = pyr_off;
     int32_t max_tiles0 = 0;
     std::vector<size_t> pyr(fc.size(), 0);
@@ -960,7 +966,31 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     a.queue = a.n_live + 1;
     a.live = (uint4*)(ws + live_off);
     a.partials = (double*)(ws + partials_off);
+    std::vector<double> pose_t;
+    if (pose) {
+        // T_hd_from_world = T_rgb_from_d T_world_from_cam^-1 of each frame, in double
+        pose_t.resize((size_t)n_frames * 12);
+        for (int f = 0; f < n_frames; ++f) {
+            const double* Tw = T_world_from_cam + 16 * (size_t)f;
+            double Rcw[9], tcw[3];
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c) Rcw[3 * r + c] = Tw[4 * c + r];
+                tcw[r] = -(Tw[r] * Tw[3] + Tw[4 + r] * Tw[7] + Tw[8 + r] * Tw[11]);
+            }
+            double* out = pose_t.data() + 12 * (size_t)f;
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c)
+                    out[3 * r + c] = T_rgb_from_d[4 * r] * Rcw[c] + T_rgb_from_d[4 * r + 1] * Rcw[3 + c] +
+                                     T_rgb_from_d[4 * r + 2] * Rcw[6 + c];
+                out[9 + r] = T_rgb_from_d[4 * r] * tcw[0] + T_rgb_from_d[4 * r + 1] * tcw[1] +
+                             T_rgb_from_d[4 * r + 2] * tcw[2] + T_rgb_from_d[4 * r + 3];
+            }
+        }
+        a.pose_adjoint = (const double*)(ws + pose_t_off);
+        a.pose_partials = (double*)(ws + pose_p_off);
+    }
     s = staged_copy(ws + frames_off, fc.data(), fc.size() * sizeof(kf::FrameConsts), st);
+    if (s == KF_OK && pose) s = staged_copy(ws + pose_t_off, pose_t.data(), pose_t.size() * sizeof(double), st);
     hipError_t e = hipSuccess;
     const char* what = nullptr;
     if (s == KF_OK && n_frames > 0) {
@@ -968,6 +998,9 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
         else if ((e = kf::launch_fill_u32((uint32_t*)(ws + counters_off), 2, 0u, st)) != hipSuccess) what = "counter reset";
         else if ((e = kf::launch_fill_u32((uint32_t*)a.partials, (size_t)a.n_items * 12, 0u, st)) != hipSuccess)
             what = "partial reset";
+        else if (pose && (e = kf::launch_fill_u32((uint32_t*)a.pose_partials, (size_t)a.n_items * width * 2, 0u,
+                                                  st)) != hipSuccess)
+            what = "pose partial reset";
         else if ((e = kf::launch_pyramids(a.frames, n_frames, max_tiles0, st)) != hipSuccess) what = "pyramid launch";
         else if ((e = kf::launch_weight_maps(a.frames, n_frames, dw * dh, st)) != hipSuccess)
             what = "weight map launch";
@@ -975,7 +1008,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     if (s == KF_OK && !what) {
         int device = 0;
         if ((e = hipGetDevice(&device)) != hipSuccess) what = "hipGetDevice";
-        else if ((e = kf::launch_backward(a, d_xi, device, st)) != hipSuccess) what = "backward launch";
+        else if ((e = kf::launch_backward(a, d_xi, pose ? d_pose : nullptr, device, st)) != hipSuccess)
+            what = "backward launch";
     }
     if (s == KF_OK && what) s = hip_fail(e, what);
     hipError_t fe = hipFreeAsync(ws, st);

@@ -121,6 +121,12 @@ struct BackwardArgs {
     uint4* live;                      // (brick, frame mask low, frame mask high, 0)
     uint32_t* n_live;
     uint32_t* queue;
+    double* pose_partials;            // NULL, or [n_items][n_frames][6] per-frame extrinsic
+                                      // partials (zero for bricks never live), then
+                                      // [XI_BLOCKS][n_frames][6] block sums and the
+                                      // [n_frames][6] sums
+    const double* pose_adjoint;       // [n_frames][12]: R (row-major) and t of each frame's
+                                      // T_hd_from_world, for d_pose = -Ad^T (frame partial)
 };
 
 // The first active lane's value of a 32-bit unsigned quantity.  The builtin takes and

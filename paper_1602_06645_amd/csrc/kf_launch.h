@@ -40,6 +40,7 @@ hipError_t launch_mesh_emit(const MeshArgs& a, hipStream_t stream);
 
 // Adjoint: cull the colour bricks, integrate the live ones backwards (persistent grid),
 // then sum the per-brick extrinsic partials in a fixed order into d_xi.
-hipError_t launch_backward(const BackwardArgs& a, double* d_xi, int device, hipStream_t stream);
+hipError_t launch_backward(const BackwardArgs& a, double* d_xi, double* d_pose, int device,
+                           hipStream_t stream);
 
 }  // namespace kf

@@ -214,8 +214,10 @@ static bool needs_fibers(const void* k)
         (const void*)kf::mc_scan_blocks_kernel,
         (const void*)kf::mc_vertices_kernel,
         (const void*)kf::mc_triangles_kernel,
-        (const void*)kf::backward_kernel<32>,
-        (const void*)kf::backward_kernel<64>,
+        (const void*)kf::backward_kernel<32, false>,
+        (const void*)kf::backward_kernel<64, false>,
+        (const void*)kf::backward_kernel<32, true>,
+        (const void*)kf::backward_kernel<64, true>,
     };
     for (const void* p : list)
         if (p == k) return true;

@@ -150,6 +150,7 @@ inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v)
     return std::atomic_ref<unsigned long long>(*p).fetch_add(v);
 }
 inline float unsafeAtomicAdd(float* p, float v) { return std::atomic_ref<float>(*p).fetch_add(v); }
+inline double atomicAdd(double* p, double v) { return std::atomic_ref<double>(*p).fetch_add(v); }
 
 // ---------------------------------------------------------------- buffer resources
 struct emu_rsrc { const char* p; uint32_t bytes; };

@@ -68,7 +68,7 @@ def forward_case(pairs, K, specs=None):
     return worst
 
 
-def backward_case(spec, fr):
+def backward_case(spec, fr, pose=False):
     fr = fr.as_float_rgb()
     d = np.ascontiguousarray(fr.depth, np.float32)
     rgb = np.ascontiguousarray(fr.rgb, np.float32)
@@ -77,16 +77,21 @@ def backward_case(spec, fr):
     g = configs.gradient_weights(spec.n_colour).numpy()
     d_rgb = np.empty_like(rgb)
     d_xi = np.empty(6, np.float64)
+    d_pose = np.full((d.shape[0], 6), np.nan)
     desc = volume_desc(spec)
     check(lib.kf_integrate_backward(
         C.byref(desc), None, d.shape[0], d.ctypes.data, rgb.ctypes.data, d.shape[2],
         d.shape[1], rgb.shape[2], rgb.shape[1], *[m.ctypes.data for m in mats], g.ctypes.data,
-        d_rgb.ctypes.data, d_xi.ctypes.data, None))
-    want_rgb, want_xi = O.backward(spec, fr, g.astype(np.float64), decide_f32=True)
+        d_rgb.ctypes.data, d_xi.ctypes.data, d_pose.ctypes.data if pose else None, None))
+    want_rgb, want_xi, want_pose = O.backward(spec, fr, g.astype(np.float64), decide_f32=True,
+                                              pose=True)
     def rel(got, want):
         floor = 1e-3 * np.abs(want).max()
         return float((np.abs(got - want) / (1e-3 * np.abs(want) + floor)).max())
-    return {"rgb": rel(d_rgb, want_rgb), "xi": rel(d_xi, want_xi)}
+    out = {"rgb": rel(d_rgb, want_rgb), "xi": rel(d_xi, want_xi)}
+    if pose:
+        out["pose"] = rel(d_pose, want_pose)
+    return out
 
 
 def status_case(spec, fr):
@@ -261,9 +266,9 @@ out["texture_mismatches"] = texture_case(spec6, fr6)
 tick("texture")
 out["mesh_mismatches"] = mesh_case(spec6, fr6, spec_odd)
 tick("mesh")
-out["backward_6"] = backward_case(spec6, fr6)
+out["backward_6"] = backward_case(spec6, fr6, pose=True)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)
-out["backward_odd"] = backward_case(spec_odd, fr6)
+out["backward_odd"] = backward_case(spec_odd, fr6, pose=True)
 tick("backward 32")
 print("JSON:" + json.dumps(out), flush=True)

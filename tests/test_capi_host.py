@@ -288,7 +288,7 @@ def test_hd_sampling_is_validated():
     d = _desc()
     d.hd_sampling = L.KF_HD_NEAREST
     args = [C.byref(d), None, 1, C.c_void_p(0x1), C.c_void_p(0x1), 640, 480, 1920, 1080,
-            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None]
+            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None, None]
     assert lib.kf_integrate_backward(*args) == L.KF_E_UNSUPPORTED
 
 
@@ -325,7 +325,7 @@ def test_backward_rejects_bad_arguments():
     lib = L.load()
     d = _desc()
     args = [C.byref(d), None, 65, C.c_void_p(0x1), C.c_void_p(0x1), 640, 480, 1920, 1080,
-            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None]
+            None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None, None]
     assert lib.kf_integrate_backward(*args) == L.KF_E_UNSUPPORTED
     args[2] = 4
     assert lib.kf_integrate_backward(*args) == L.KF_E_ARG     # K_d is NULL

@@ -52,3 +52,5 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert res["mesh_mismatches"] == 0
     for case in ("backward_6", "backward_32", "backward_odd"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
+    for case in ("backward_6", "backward_odd"):      # with the depth-pose adjoint
+        assert res[case]["pose"] <= 1.0, res

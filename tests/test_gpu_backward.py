@@ -153,3 +153,52 @@ def test_backward_full_size_sampled_slabs(oracle, n_frames):
     assert np.abs(want_xi).max() > 0
     _close(d_xi.cpu().numpy(), want_xi)
     _close(d_rgb.cpu().numpy(), want_rgb)
+
+
+def test_depth_pose_adjoint_matches_oracle(oracle, scan):
+    """Per-frame depth-pose gradients against the oracle's direct chain rule (FP32
+    decisions), with and without initial weights; d_rgb and d_xi unchanged by asking for
+    them; deterministic."""
+    spec, fr = scan
+    say("backward: depth-pose adjoint, tiny, 6 frames")
+    g = configs.gradient_weights(spec.n_colour)
+    s = kf.Scan.from_frames(fr.to(DEV))
+    d_rgb, d_xi, d_pose = kf.integrate_backward(spec, s, g.to(DEV), pose=True)
+    _, _, d_pose2 = kf.integrate_backward(spec, s, g.to(DEV), pose=True)
+    d_rgb0, d_xi0 = kf.integrate_backward(spec, s, g.to(DEV))
+    want_rgb, want_xi, want_pose = oracle.backward(spec, fr, g.numpy().astype(np.float64),
+                                                   decide_f32=True, pose=True)
+    torch.cuda.synchronize()
+    assert d_pose.shape == (fr.n, 6)
+    _close(d_pose.cpu().numpy(), want_pose)
+    assert np.abs(want_pose).max() > 1e-3
+    assert torch.equal(d_pose, d_pose2), "pose gradient is not deterministic"
+    assert torch.equal(d_xi, d_xi0)
+    torch.testing.assert_close(d_rgb, d_rgb0, rtol=1e-5, atol=1e-6)
+    _close(d_xi.cpu().numpy(), want_xi)
+
+
+@pytest.mark.parametrize("n_frames", [6, 40])
+def test_depth_pose_adjoint_full_size(oracle, n_frames):
+    """The kinect volume with g on two seeded colour slabs: per-frame pose gradients (40
+    frames use the 64-frame history and masks beyond bit 31)."""
+    say(f"backward: depth-pose adjoint, full size, {n_frames} frames")
+    spec, fr = configs.kinect(device=DEV, n_frames=n_frames)
+    fr = fr.as_float_rgb()
+    rng = np.random.default_rng(92)
+    nxy = spec.cdim[0] * spec.cdim[1]
+    g = torch.zeros((3, spec.n_colour), dtype=torch.float32, device=DEV)
+    gsl = []
+    for z0 in (int(rng.integers(40, 120)), int(rng.integers(130, 220))):
+        part = configs.gradient_weights(nxy * 3, seed=6006 + z0)
+        g[:, z0 * nxy:(z0 + 3) * nxy] = part.to(DEV)
+        gsl.append((z0, part.numpy().astype(np.float64)))
+    _, _, d_pose = kf.integrate_backward(spec, kf.Scan.from_frames(fr), g, pose=True)
+    want = 0.0
+    frn = fr.numpy()
+    for z0, part in gsl:
+        say(f"  oracle adjoint on colour slab z[{z0},{z0 + 3})")
+        want = want + oracle.backward(spec, frn, part, cz=(z0, z0 + 3), decide_f32=True, pose=True)[2]
+    torch.cuda.synchronize()
+    assert np.abs(want).max() > 0
+    _close(d_pose.cpu().numpy(), want)
