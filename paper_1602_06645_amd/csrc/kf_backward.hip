@@ -40,7 +40,7 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     const float Yc = fmaf(c.Ac[5], fk, fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1])));
     const float Zc = fmaf(c.Ac[8], fk, fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2])));
     if (!(Zc > 0.0f)) return 0.0f;
-    const float iz = 1.0f / Zc;
+    const float iz = recip(Zc);
     const float u = rintf(fmaf(c.fx, Xc * iz, c.cx));
     const float v = rintf(fmaf(c.fy, Yc * iz, c.cy));
     if (!(u >= 0.0f && u <= c.wm1 && v >= 0.0f && v <= c.hm1)) return 0.0f;
@@ -59,7 +59,7 @@ __device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, f
     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
     const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
     if (!(qz > 0.0f)) return 0.0f;
-    const float iqz = 1.0f / qz;
+    const float iqz = recip(qz);
     const float x0 = floorf(fmaf(c.fxr, qx * iqz, c.cxr));
     const float y0 = floorf(fmaf(c.fyr, qy * iqz, c.cyr));
     if (!(x0 >= 0.0f && x0 <= c.hd_xmax && y0 >= 0.0f && y0 <= c.hd_ymax)) return 0.0f;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
                     const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
                     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
                     const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-                    const float iqz = 1.0f / qz;
+                    const float iqz = recip(qz);
                     const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
                     const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
                     const float x0 = floorf(xh), y0 = floorf(yh);

@@ -141,7 +141,7 @@ template <class C>
 __device__ __forceinline__ Pixel project(const C& c, float X, float Y, float Z)
 {
     Pixel p;
-    const float iz = 1.0f / Z;
+    const float iz = recip(Z);
     p.u = rintf(fmaf(c.fx, X * iz, c.cx));
     p.v = rintf(fmaf(c.fy, Y * iz, c.cy));
     p.inside = (Z > 0.0f) & (p.u >= 0.0f) & (p.u <= c.wm1) & (p.v >= 0.0f) & (p.v <= c.hm1);
@@ -262,7 +262,7 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
     const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
     const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-    const float iqz = 1.0f / qz;
+    const float iqz = recip(qz);
     const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
     const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
     const float x0 = c.hd_nearest ? rintf(xh) : floorf(xh), y0 = c.hd_nearest ? rintf(yh) : floorf(yh);

