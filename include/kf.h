@@ -134,8 +134,8 @@ typedef struct {
 
 /*
  * Integrate several independent scans (different volumes, sizes and frame counts).
- * Each voxel keeps its state on chip for frames_per_pass (K, 1 <= K; values above 32 act
- * as 32) consecutive frames of its scan, so a voxel's state is read and written at most
+ * Each voxel keeps its state on chip for frames_per_pass (K, 1 <= K; values above 64 act
+ * as 64) consecutive frames of its scan, so a voxel's state is read and written at most
  * once per pass instead of once per frame; all scans advance together, one pass at a
  * time: a culling launch lists the (scan, brick) work items that can be updated in some
  * frame of the pass, and two persistent launches (geometry bricks, then colour bricks)

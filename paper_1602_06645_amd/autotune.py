@@ -14,7 +14,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING = os.path.join(HERE, "tuning.json")
-CANDIDATES = (4, 8, 16, 32)
+CANDIDATES = (4, 8, 16, 32, 48, 64)
 
 
 def tune(vol, scan_passes, reps: int = 3) -> dict:

@@ -373,8 +373,8 @@ struct BatchPlan {
     std::vector<uint32_t> pass_chunks;
 };
 
-// Frames a pass can hold: one bit per frame in a brick's live mask.
-constexpr int32_t kMaxFramesPerPass = 32;
+// Frames a pass can hold: one bit per frame in a brick's 64-bit live mask.
+constexpr int32_t kMaxFramesPerPass = 64;
 
 kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchPlan* plan)
 {
@@ -463,7 +463,7 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
     uint32_t max_items = 0;
     for (uint32_t n : p.pass_items) max_items = n > max_items ? n : max_items;
     t->live_off = off;
-    off = align(off + (size_t)max_items * sizeof(uint2));
+    off = align(off + (size_t)max_items * sizeof(uint4));
     t->pyr_off = off;
     for (const auto& fc : p.frames) {
         t->frame_pyr_off.push_back(off);
@@ -526,7 +526,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
            "weight map launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
     KF_HIP(kf::launch_fill_u32(cnt, 4 * (p.passes.size() + 1), 0u, stream), "counter reset");
-    uint2* live = (uint2*)(dev + t.live_off);
+    uint4* live = (uint4*)(dev + t.live_off);
     const int disable = cull_disabled() ? 1 : 0;
     for (size_t q = 0; q < p.passes.size(); ++q) {
         if (p.pass_items[q] == 0) continue;
@@ -539,6 +539,8 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         c.n_items = p.pass_items[q];
         c.n_chunks = p.pass_chunks[q];
         c.disable = disable;
+        c.max_frames = 0;
+        for (const kf::SceneDev& d : p.passes[q]) c.max_frames = d.n_frames > c.max_frames ? d.n_frames : c.max_frames;
         c.live = live;
         c.n_live = cnt + 4 * q;
         KF_HIP(kf::launch_cull(c, stream), "cull launch");

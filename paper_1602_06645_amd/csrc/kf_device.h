@@ -64,7 +64,7 @@ struct SceneDev {
     uint32_t geom_chunks;             // geometry chunks; colour chunks follow them
     uint32_t colour_chunks;
     int32_t frame_begin;              // first entry of the frame table used by this pass
-    int32_t n_frames;                 // frames of this scene in this pass (<= 32)
+    int32_t n_frames;                 // frames of this scene in this pass (<= 64)
     int32_t fmt;                      // PixFmt
 };
 
@@ -77,8 +77,9 @@ struct IntegrateArgs {
     const SceneDev* scenes;           // table of n_scenes
     const FrameConsts* frames;        // frame table
     int32_t n_scenes;
-    const uint2* live;                // (brick, frame mask): geometry entries from the
-                                      // front, colour entries from the back
+    const uint4* live;                // (brick, frame mask low, frame mask high, 0):
+                                      // geometry entries from the front, colour entries
+                                      // from the back
     uint32_t cap;                     // entries `live` can hold (bricks of the pass)
     const uint32_t* n_live;           // [KIND]: entries of each kind
     uint32_t* queue;                  // [KIND]: next entry to take
@@ -100,7 +101,8 @@ struct CullArgs {
     uint32_t n_items;                 // bricks of all scenes of the pass
     uint32_t n_chunks;                // culling chunks of all scenes of the pass
     int32_t disable;                  // 1: every brick is live in every frame
-    uint2* live;                      // n_items entries (see IntegrateArgs)
+    int32_t max_frames;               // frames of the pass's longest scene (<= 64)
+    uint4* live;                      // n_items entries (see IntegrateArgs)
     uint32_t* n_live;                 // [KIND]
 };
 

@@ -1,10 +1,10 @@
 // Forward integration kernels for gfx950: TSDF geometry volume (Sec. III) and asymmetric
 // colour volume (Sec. IV.B, Eq. 5-10, with the depth-to-HD mapping of Eq. 1-4).
 //
-// A pass applies up to 32 consecutive frames of every scan in the launch:
+// A pass applies up to 64 consecutive frames of every scan in the launch:
 //   1. pyramid kernels: per frame, min/max of the valid depths over 8x8-pixel tiles and
 //      their 2x2 reductions (built once per batch call for all frames);
-//   2. cull kernel: one lane per brick decides, frame by frame, whether any voxel of the
+//   2. cull kernel: one thread per (brick, frame) decides whether any voxel of the
 //      brick can pass the depth tests (conservatively, from the brick's corners and the
 //      pyramid) and appends (brick, frame mask) of the live bricks to a list;
 //   3. integrate kernels (one launch for geometry bricks, one for colour bricks):
@@ -163,7 +163,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(float* p, const Colu
 // eight depth samples of the column are fetched before any of them is used.  MODE_STATUS
 // writes the outcome code of the (single) frame instead.
 template <int MODE, class Scene, class FramePtr>
-__device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uint32_t mask,
+__device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
                                            uint32_t li, uint8_t* status, Counts& cnt)
 {
     const Column col = column<GBX, GBY>(sc.gdim, sc.gbricks, li);
@@ -174,8 +174,8 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uin
     for (int kk = 0; kk < ZS; ++kk) F[kk] = W[kk] = 0.0f;
     uint32_t loaded = 0;
     unsigned long long n_upd = 0;
-    for (uint32_t m = mask; m; m &= m - 1) {
-        const auto& c = frames[__builtin_ctz(m)];
+    for (unsigned long long m = mask; m; m &= m - 1) {
+        const auto& c = frames[__builtin_ctzll(m)];
         const __amdgpu_buffer_rsrc_t depth = image_rsrc(c.depth, (uint32_t)(c.dw * c.dh) * 4u);
         // Eq. 5 for this column; the z term is added per voxel.
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
@@ -281,7 +281,7 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
 // weight of the voxels that reach the gate; (4) gate, HD pixel, Eq. 9 and Eq. 10.  The
 // column's colour state lives in registers for the whole pass.
 template <int MODE, class Scene, class FramePtr>
-__device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, uint32_t mask,
+__device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
                                              uint32_t li, uint8_t* status, Counts& cnt)
 {
     const Column col = column<CBX, CBY>(sc.cdim, sc.cbricks, li);
@@ -293,8 +293,8 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
     uint32_t wl = 0;   // colour weight read
     uint32_t cl = 0;   // colour read and updated (stored at the end)
     unsigned long long n_eval = 0, n_upd = 0;
-    for (uint32_t m = mask; m; m &= m - 1) {
-        const auto& c = frames[__builtin_ctz(m)];
+    for (unsigned long long m = mask; m; m &= m - 1) {
+        const auto& c = frames[__builtin_ctzll(m)];
         const __amdgpu_buffer_rsrc_t depth = image_rsrc(c.depth, (uint32_t)(c.dw * c.dh) * 4u);
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
@@ -439,19 +439,22 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 }  // namespace
 
-// One block per culling chunk (CHUNK^3 bricks of one kind).  The first 32 lanes test the
-// chunk's voxel box against frames 0-31 of the pass; the chunk's bricks are then tested,
-// eight at a time (32 lanes per brick, one per frame), only for the frames the chunk
-// passed, and a ballot assembles each brick's frame mask.  Skipping those frames is exact:
-// the chunk test is conservative for every voxel of the chunk, as the brick test is for
-// every voxel of the brick.  The live entries are gathered in LDS and appended to the
-// list with one atomic per block (geometry from the front, colour from the back).
+// One block per culling chunk (CHUNK^3 bricks of one kind).  The first wave tests the
+// chunk's voxel box against the frames of the pass (one lane per frame) and lists the
+// frames it passed; the block then tests the (brick, listed frame) pairs, one per thread,
+// and ORs each live pair's frame bit into its brick's mask in LDS.  Skipping the other
+// frames is exact: the chunk test is conservative for every voxel of the chunk, as the
+// brick test is for every voxel of the brick.  The first wave appends the bricks with a
+// non-empty mask to the list in brick order, with one atomic per block (geometry from
+// the front, colour from the back).
 constexpr int CHUNK_BRICKS = CHUNK * CHUNK * CHUNK;
+static_assert(CHUNK_BRICKS <= WAVE, "one lane per brick of a chunk in the append");
 
 __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 {
-    __shared__ uint2 s_ent[CHUNK_BRICKS];
-    __shared__ uint32_t s_n, s_base, s_cmask;
+    __shared__ unsigned long long s_mask[CHUNK_BRICKS];
+    __shared__ uint8_t s_frame[64];
+    __shared__ uint32_t s_nf;
     const uint32_t chunk = blockIdx.x;
     int s = 0;
     while (s + 1 < a.n_scenes && a.scenes[s + 1].chunk_begin <= chunk) ++s;
@@ -469,51 +472,52 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
     const int nbx = min(CHUNK, nb[0] - bx0), nby = min(CHUNK, nb[1] - by0), nbz = min(CHUNK, nb[2] - bz0);
     const FrameConsts* frames = a.frames + sc.frame_begin;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int f = lane & 31;
     if (threadIdx.x < WAVE) {
         bool live = false;
-        if (threadIdx.x < 32 && f < sc.n_frames) {
+        if (lane < sc.n_frames) {
             const int i0 = bx0 * BX, i1 = min(dim[0], (bx0 + nbx) * BX) - 1;
             const int j0 = by0 * BY, j1 = min(dim[1], (by0 + nby) * BY) - 1;
             const int k0 = bz0 * ZS, k1 = min(dim[2], (bz0 + nbz) * ZS) - 1;
-            live = a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1);
+            live = a.disable || brick_live(frames[lane], colour, i0, i1, j0, j1, k0, k1);
         }
-        const uint32_t m = (uint32_t)__ballot(live);
-        if (threadIdx.x == 0) {
-            s_cmask = m;
-            s_n = 0;
-        }
+        const unsigned long long m = __ballot(live);
+        if (live) s_frame[__builtin_popcountll(m & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+        if (lane == 0) s_nf = (uint32_t)__builtin_popcountll(m);
+        if (lane < CHUNK_BRICKS) s_mask[lane] = 0ull;
     }
     __syncthreads();
-    const uint32_t cmask = s_cmask;
-    if (cmask == 0) return;   // the whole block: no brick of the chunk is live
-    const int nbr = nbx * nby * nbz;
-    for (int r = 0; r < CHUNK_BRICKS / (BLOCK / 32); ++r) {
-        const int q = r * (BLOCK / 32) + (int)(threadIdx.x / 32);   // brick within the chunk
-        bool live = false;
-        uint32_t li = 0;
-        if (q < nbr) {
-            const int bx = bx0 + q % nbx, by = by0 + (q / nbx) % nby, bz = bz0 + q / (nbx * nby);
-            li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
-            if ((cmask >> f) & 1u) {
-                const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
-                const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
-                const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
-                live = a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1);
-            }
-        }
-        const uint32_t mask = (uint32_t)(__ballot(live) >> (lane & 32));
-        if (f == 0 && mask != 0) {
+    const uint32_t nf = s_nf;
+    if (nf == 0) return;   // the whole block: no brick of the chunk is live
+    const uint32_t nbr = (uint32_t)(nbx * nby * nbz);
+    for (uint32_t t = threadIdx.x; t < nbr * nf; t += BLOCK) {
+        const uint32_t q = t / nf;                    // brick within the chunk
+        const int f = s_frame[t - q * nf];
+        const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
+        const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
+        const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
+        const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
+        const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
+        if (a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1))
+            atomicOr(&s_mask[q], 1ull << f);
+    }
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        const uint32_t q = (uint32_t)lane;
+        const unsigned long long mask = q < nbr ? s_mask[q] : 0ull;
+        const unsigned long long has = __ballot(mask != 0ull);
+        if (has == 0ull) return;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.n_live + (colour ? KIND_COLOUR : KIND_GEOM),
+                                        (uint32_t)__builtin_popcountll(has));
+        base = __shfl(base, 0, WAVE);
+        if (mask != 0ull) {
+            const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
+            const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
+            const uint32_t li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
             const uint32_t item = sc.item_begin + (colour ? sc.geom_items : 0u) + li;
-            s_ent[atomicAdd(&s_n, 1u)] = make_uint2(item, mask);
+            const uint32_t pos = base + (uint32_t)__builtin_popcountll(has & ((1ull << lane) - 1ull));
+            a.live[colour ? a.n_items - 1u - pos : pos] = make_uint4(item, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
         }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(a.n_live + (colour ? KIND_COLOUR : KIND_GEOM), s_n) : 0u;
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < s_n; e += BLOCK) {
-        const uint32_t pos = s_base + e;
-        a.live[colour ? a.n_items - 1u - pos : pos] = s_ent[e];
     }
 }
 
@@ -618,8 +622,9 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
         const uint32_t e = wave_ticket(a.queue + KIND);
         if (e >= n_live) break;
         const uint32_t pos = KIND == KIND_COLOUR ? a.cap - 1u - e : e;
-        const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 2 * (size_t)pos;
-        const uint32_t item = ent[0], fmask = ent[1];
+        const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 4 * (size_t)pos;
+        const uint32_t item = ent[0];
+        const unsigned long long fmask = ent[1] | (unsigned long long)ent[2] << 32;
         int s = 0;
         while (s + 1 < a.n_scenes && scenes[s + 1].item_begin <= item) ++s;
         const auto& sc = scenes[s];
@@ -627,10 +632,10 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
         const uint32_t li = item - sc.item_begin;
         if constexpr (KIND == KIND_GEOM) {
             geom_brick<MODE>(sc, frames, fmask, li, nullptr, cnt);
-            if constexpr (MODE == MODE_COUNT) cnt.g_bricks += (unsigned)__builtin_popcount(fmask);
+            if constexpr (MODE == MODE_COUNT) cnt.g_bricks += (unsigned)__builtin_popcountll(fmask);
         } else {
             colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, nullptr, cnt);
-            if constexpr (MODE == MODE_COUNT) cnt.c_bricks += (unsigned)__builtin_popcount(fmask);
+            if constexpr (MODE == MODE_COUNT) cnt.c_bricks += (unsigned)__builtin_popcountll(fmask);
         }
     }
     if constexpr (MODE == MODE_COUNT) {
@@ -701,6 +706,7 @@ hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, i
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
 {
     if (a.n_chunks == 0) return hipSuccess;
+    if (a.max_frames > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(cull_kernel, dim3(a.n_chunks), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }

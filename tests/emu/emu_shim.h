@@ -92,6 +92,13 @@ inline T __shfl_xor(T v, int mask, int width = 64)
 }
 
 template <class T>
+inline T __shfl(T v, int src, int width = 64)
+{
+    (void)width;
+    return emu_bcast_from(v, src & 63);
+}
+
+template <class T>
 inline T __shfl_up(T v, unsigned delta, int width = 64)
 {
     (void)width;
@@ -148,6 +155,10 @@ inline uint32_t atomicAdd(uint32_t* p, uint32_t v) { return std::atomic_ref<uint
 inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v)
 {
     return std::atomic_ref<unsigned long long>(*p).fetch_add(v);
+}
+inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v)
+{
+    return std::atomic_ref<unsigned long long>(*p).fetch_or(v);
 }
 inline float unsafeAtomicAdd(float* p, float v) { return std::atomic_ref<float>(*p).fetch_add(v); }
 inline double atomicAdd(double* p, double v) { return std::atomic_ref<double>(*p).fetch_add(v); }

@@ -251,6 +251,13 @@ tick("inputs")
 out["forward_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb()),
                                           (Vol(spec_odd), fr32)], 8)
 tick("forward")
+# passes of more than 32 frames (64-bit frame masks, one wave per brick in the culling):
+# 40 frames at 36 per pass (a wide pass, then a narrow one) beside the 6-frame scan
+spec40, fr40 = configs.tiny(n_frames=40)
+fr40 = fr40.numpy()
+out["wide_pass_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec40), fr40)], 36,
+                                           [spec6, spec40])
+tick("wide passes")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
 # nearest-pixel HD sampling: an 8-bit scan and a float one on the odd volume

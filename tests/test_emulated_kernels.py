@@ -4,7 +4,8 @@ them, bounds-checked buffer loads) and run under AddressSanitizer and UBSan.  Ch
 without a GPU that the kernels' logic equals the oracle (bit for bit in the forward, to
 the adjoint tolerance in the backward) and touches no memory outside its buffers: two
 scans and an odd-sized volume (partial bricks and culling chunks) in one batch (RGB8 and
-float images, 6 and 32 frames, 8 frames per pass), the
+float images, 6 and 32 frames, 8 frames per pass), passes of more than 32 frames (40
+frames at 36 per pass), the
 per-voxel outcome codes of every frame of a scan, the ray cast of an integrated volume, and
 the adjoint over 6 and 32 frames (a
 live frame in bit 31 of a brick's frame mask)."""
@@ -45,6 +46,7 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert r.returncode == 0, r.stderr[-4000:]
     res = json.loads(r.stdout.split("JSON:", 1)[1])
     assert res["forward_mismatches"] == 0
+    assert res["wide_pass_mismatches"] == 0
     assert res["status_mismatches"] == 0
     assert res["raycast_mismatches"] == 0
     assert res["texture_mismatches"] == 0

@@ -131,3 +131,31 @@ def test_culling_changes_nothing(kinect8, monkeypatch):
     kf.integrate_batch([(b, scan)], frames_per_pass=8)
     monkeypatch.delenv("KF_DISABLE_CULL")
     assert_bitwise(to_host(a), to_host(b), "cull vs no cull: ")
+
+
+def test_kinect_full_size_wide_passes(oracle, monkeypatch):
+    """The full-size workload, 70 frames in passes of 64 frames (64 + 6) replayed from a
+    graph: seeded z-slabs equal the oracle's, and culling changes nothing."""
+    say("generating Kinect-like scan (70 frames) on the GPU")
+    spec, fr = configs.kinect(device=DEV, n_frames=70)
+    scan = kf.Scan.from_frames(fr)
+    vol = kf.Volume(spec)
+    kf.integrate_batch([(vol, scan)], frames_per_pass=64, use_graph=True)
+    got = to_host(vol)
+    rng = np.random.default_rng(78)
+    g0 = int(rng.integers(24, 150))
+    c0 = int(rng.integers(24, 150))
+    gz, cz = (g0, g0 + 4), (c0, c0 + 4)
+    say(f"  oracle slabs geometry z{gz} colour z{cz}")
+    st = _oracle_slabs(oracle, spec, fr, gz, cz)
+    for name, g, w, dims, z in zip(["tsdf", "w_geom", "r", "g", "b", "w_col"], got, st.arrays(),
+                                   [spec.gdim] * 2 + [spec.cdim] * 4, [gz] * 2 + [cz] * 4):
+        assert np.array_equal(_slab(g, dims, z).view(np.uint32), w.view(np.uint32)), \
+            f"{name} slab {z} differs"
+    assert int((st.wc > 0).sum()) > 1000 and int((st.wg > 0).sum()) > 1000
+    say("  culling off")
+    monkeypatch.setenv("KF_DISABLE_CULL", "1")
+    b = kf.Volume(spec)
+    kf.integrate_batch([(b, scan)], frames_per_pass=64)
+    monkeypatch.delenv("KF_DISABLE_CULL")
+    assert_bitwise(got, to_host(b), "cull vs no cull, 64 frames per pass: ")
