@@ -441,8 +441,8 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 // One block per culling chunk (CHUNK^3 bricks of one kind).  The first wave tests the
 // chunk's voxel box against the frames of the pass (one lane per frame) and lists the
-// frames it passed; the block then tests the (brick, listed frame) pairs, one per thread,
-// and ORs each live pair's frame bit into its brick's mask in LDS.  Skipping the other
+// frames it passed; the block then tests the (brick, listed frame) pairs, one per thread
+// (frame-major), and ORs each live pair's frame bit into its brick's mask in LDS.  Skipping the other
 // frames is exact: the chunk test is conservative for every voxel of the chunk, as the
 // brick test is for every voxel of the brick.  The first wave appends the bricks with a
 // non-empty mask to the list in brick order, with one atomic per block (geometry from
@@ -490,8 +490,11 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
     if (nf == 0) return;   // the whole block: no brick of the chunk is live
     const uint32_t nbr = (uint32_t)(nbx * nby * nbz);
     for (uint32_t t = threadIdx.x; t < nbr * nf; t += BLOCK) {
-        const uint32_t q = t / nf;                    // brick within the chunk
-        const int f = s_frame[t - q * nf];
+        // frame-major: the lanes of a wave share a frame (its constants are read once per
+        // wave) and OR into different bricks' masks
+        const uint32_t r = t / nbr;
+        const uint32_t q = t - r * nbr;               // brick within the chunk
+        const int f = s_frame[r];
         const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
         const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
         const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;

@@ -34,6 +34,24 @@ def test_multi_scene_uneven_equals_per_scene_plain(oracle):
         assert_bitwise(to_host(vols[q]), st.arrays(), f"scene {q} vs oracle: ")
 
 
+def test_mixed_scans_in_wide_passes(oracle):
+    """A 70-frame scan and a 12-frame scan (float images) on different volumes in one batch
+    of 64-frame passes: the first pass holds 64 + 12 frames, the second 6 + 0; each scan
+    equals the oracle."""
+    spec_a, fr_a = configs.tiny(n_frames=70)
+    spec_b = VolumeSpec((45, 37, 29), (90, 74, 58), (-0.41, -0.37, -0.46), (0.9, 0.74, 0.58))
+    fr_b = fr_a.select(slice(20, 32)).as_float_rgb()
+    say("mixed batch: 70 frames on 64^3/128^3 + 12 float frames on 45x37x29, K=64")
+    va, vb = kf.Volume(spec_a), kf.Volume(spec_b)
+    kf.integrate_batch([(va, kf.Scan.from_frames(fr_a.to(DEV))),
+                        (vb, kf.Scan.from_frames(fr_b.to(DEV)))], frames_per_pass=64)
+    for vol, spec, fr, name in ((va, spec_a, fr_a, "70-frame"), (vb, spec_b, fr_b, "12-frame")):
+        st = oracle.State(spec, np.float32)
+        oracle.integrate(spec, fr.numpy(), st)
+        assert int((st.wc > 0).sum()) > 1000
+        assert_bitwise(to_host(vol), st.arrays(), f"{name} scan vs oracle: ")
+
+
 def test_graph_replays_match_eager():
     """The graph is recorded on first use and replayed afterwards; every replay (with
     eager work and synchronisation in between) equals the eager batch."""
