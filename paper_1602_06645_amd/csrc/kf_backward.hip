@@ -30,40 +30,63 @@ constexpr int BWD_MAX_FRAMES = 64;
 
 namespace {
 
-// Forward decision of one colour voxel for one frame; returns the weight W (> 0) if the
-// frame updates the voxel given the current weight, 0 otherwise.  Same operation
-// sequence as the forward kernel.
-__device__ __forceinline__ float colour_weight(const FrameConsts& c, float fi, float fj,
-                                               float fk, float Wc)
+// Image reads of the replay go through bounds-checked buffer resources: an offset past
+// the image reads 0, so a voxel outside the frustum needs no branch around its reads.
+constexpr uint32_t kOffImage = 0x7FFFFFF0u;
+
+__device__ __forceinline__ float image_load(const void* p, uint32_t bytes, uint32_t byte_off)
 {
-    const float Xc = fmaf(c.Ac[2], fk, fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0])));
-    const float Yc = fmaf(c.Ac[5], fk, fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1])));
-    const float Zc = fmaf(c.Ac[8], fk, fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2])));
-    if (!(Zc > 0.0f)) return 0.0f;
-    const float iz = recip(Zc);
-    const float u = rintf(fmaf(c.fx, Xc * iz, c.cx));
-    const float v = rintf(fmaf(c.fy, Yc * iz, c.cy));
-    if (!(u >= 0.0f && u <= c.wm1 && v >= 0.0f && v <= c.hm1)) return 0.0f;
-    const int pix = (int)v * c.dw + (int)u;
-    const float d = c.depth[pix];
-    if (!valid_depth(d)) return 0.0f;
-    const float Px = ((u - c.cx) * c.inv_fx) * d;
-    const float Py = ((v - c.cy) * c.inv_fy) * d;
-    const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
-    if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > c.sigma2) return 0.0f;
-    // W of the depth pixel (Eq. 8 normal and the viewing ray), from the frame's weight map
-    const float w = c.wmap[pix];
-    if (__builtin_bit_cast(uint32_t, w) == kNoNormal) return 0.0f;
-    if (!(w > c.gate * Wc)) return 0.0f;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
+// The forward decision of one colour voxel for one frame, split so that several frames'
+// image reads can be in flight together: weight_fetch projects the voxel centre into the
+// depth camera (Eq. 5-6) and reads its depth and weight-map entries; weight_test applies
+// every test of Sec. IV.B except the gate (which needs the running weight) and returns the
+// weight-map W if they all pass, else 0.  Same single-precision operations as the forward.
+struct WeightFetch {
+    float Xc, Yc, Zc, u, v, d, w;
+    bool in;
+};
+
+template <class C>
+__device__ __forceinline__ WeightFetch weight_fetch(const C& c, float fi, float fj, float fk)
+{
+    WeightFetch r;
+    r.Xc = fmaf(c.Ac[2], fk, fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0])));
+    r.Yc = fmaf(c.Ac[5], fk, fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1])));
+    r.Zc = fmaf(c.Ac[8], fk, fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2])));
+    const float iz = recip(r.Zc);
+    r.u = rintf(fmaf(c.fx, r.Xc * iz, c.cx));
+    r.v = rintf(fmaf(c.fy, r.Yc * iz, c.cy));
+    r.in = (r.Zc > 0.0f) & (r.u >= 0.0f) & (r.u <= c.wm1) & (r.v >= 0.0f) & (r.v <= c.hm1);
+    const uint32_t off = r.in ? ((uint32_t)(int)r.v * (uint32_t)c.dw + (uint32_t)(int)r.u) * 4u : kOffImage;
+    const uint32_t bytes = (uint32_t)(c.dw * c.dh) * 4u;
+    r.d = image_load(c.depth, bytes, off);
+    r.w = image_load(c.wmap, bytes, off);
+    return r;
+}
+
+template <class C>
+__device__ __forceinline__ float weight_test(const C& c, const WeightFetch& r, float fi, float fj,
+                                             float fk)
+{
+    const float Px = ((r.u - c.cx) * c.inv_fx) * r.d;
+    const float Py = ((r.v - c.cy) * c.inv_fy) * r.d;
+    const float dx = r.Xc - Px, dy = r.Yc - Py, dz = r.Zc - r.d;
+    const bool valid = valid_depth(r.d);
+    const bool band = r.in & valid & !(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > c.sigma2) &
+                      (__builtin_bit_cast(uint32_t, r.w) != kNoNormal);
     const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
     const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-    if (!(qz > 0.0f)) return 0.0f;
     const float iqz = recip(qz);
     const float x0 = floorf(fmaf(c.fxr, qx * iqz, c.cxr));
     const float y0 = floorf(fmaf(c.fyr, qy * iqz, c.cyr));
-    if (!(x0 >= 0.0f && x0 <= c.hd_xmax && y0 >= 0.0f && y0 <= c.hd_ymax)) return 0.0f;
-    return w;
+    const bool hd = (qz > 0.0f) & (x0 >= 0.0f) & (x0 <= c.hd_xmax) & (y0 >= 0.0f) & (y0 <= c.hd_ymax);
+    return (band & hd) ? r.w : 0.0f;
 }
 
 __device__ __forceinline__ double wave_sum_d(double x)
@@ -151,6 +174,7 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
     double* facc = s_pose + (POSE ? wave * HIST * 6 : 0);
     const size_t nvox = (size_t)a.cdim[0] * (size_t)a.cdim[1] * (size_t)a.cdim[2];
     const uint32_t n_live = *a.n_live;
+    const const_ptr<FrameConsts> frames = as_const(a.frames);
     for (;;) {
         const uint32_t e = wave_ticket(a.queue);
         if (e >= n_live) break;
@@ -178,13 +202,35 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
                 const size_t idx = ((size_t)k * (size_t)a.cdim[1] + (size_t)j) * (size_t)a.cdim[0] + (size_t)i;
                 const float g0 = a.grad[idx], g1 = a.grad[nvox + idx], g2 = a.grad[2 * nvox + idx];
                 if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
-                // forward replay over the live frames: alpha_n, by rank among them
+                // forward replay over the live frames, by rank among them: first the
+                // weight-independent tests, four frames at a time with their image reads
+                // in flight together (W or 0 into the history) ...
+                int r = 0;
+                for (unsigned long long m = mask; m;) {
+                    int fr[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ok[q] = m != 0ull;
+                        fr[q] = ok[q] ? __builtin_ctzll(m) : fr[0];
+                        m &= m - 1;
+                    }
+                    WeightFetch wf[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) wf[q] = weight_fetch(frames[fr[q]], fi, fj, fk);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (ok[q]) hist[(r + q) * WAVE] = weight_test(frames[fr[q]], wf[q], fi, fj, fk);
+                    r += 4;
+                }
+                // ... then the gate against the running weight and alpha_n
                 float Wc = a.wc0 ? a.wc0[idx] : 0.0f;
-                int any = 0, r = 0;
+                int any = 0;
+                r = 0;
                 for (unsigned long long m = mask; m; m &= m - 1, ++r) {
-                    const float w = colour_weight(a.frames[__builtin_ctzll(m)], fi, fj, fk, Wc);
+                    const float w = hist[r * WAVE];
                     float alpha = 0.0f;
-                    if (w > 0.0f) {
+                    if (w > 0.0f && w > frames[__builtin_ctzll(m)].gate * Wc) {
                         alpha = w / (Wc + w);
                         Wc = fmaf(w, 1.0f - Wc, Wc);
                         any = 1;
@@ -201,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
                     if (alpha == 0.0f) continue;
                     const float beta = alpha * tail;
                     tail *= 1.0f - alpha;
-                    const FrameConsts& c = a.frames[f];
+                    const auto& c = frames[f];
                     const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
                     const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
                     const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));

@@ -152,6 +152,19 @@ __device__ __forceinline__ uint32_t first_lane_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Per-launch tables are read-only for the whole launch: reading them through the
+// constant address space lets the compiler use scalar loads and keep them in SGPRs (a
+// kernel that also writes global memory otherwise gets vector loads, since the compiler
+// cannot prove that its writes leave the table alone).
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ const_ptr<T> as_const(const T* p)
+{
+    return (const_ptr<T>)p;
+}
+
 // Next entry of a work queue for the whole wave (one ticket per wave).  Every active lane
 // takes part in the atomic (the first active lane adds 1, the others 0) and the first
 // lane's result is broadcast, so the ticket is never defined under lane-dependent

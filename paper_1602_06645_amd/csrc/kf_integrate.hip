@@ -62,17 +62,6 @@ __device__ __forceinline__ float hd_sample(const void* rgb, int fmt, bool neares
     return lerp(lerp(p00, p10, ax), lerp(p01, p11, ax), ay);
 }
 
-// Per-launch tables are read-only for the whole launch: reading them through the
-// constant address space lets the compiler use scalar loads and keep them in SGPRs.
-template <class T>
-using const_ptr = const __attribute__((address_space(4))) T*;
-
-template <class T>
-__device__ __forceinline__ const_ptr<T> as_const(const T* p)
-{
-    return (const_ptr<T>)p;
-}
-
 struct Counts {
     unsigned long long g_upd = 0, g_touch = 0, c_eval = 0, c_read = 0, c_upd = 0, c_touch = 0;
     unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (same in every lane)
