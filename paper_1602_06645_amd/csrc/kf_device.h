@@ -136,13 +136,33 @@ struct BackwardArgs {
 // IEEE quotient for every normal z with |z| <= 2^126; zero, subnormal, larger, infinite
 // and NaN z take the IEEE division (a branch no lane takes for the camera depths of a
 // scene).  The equality is checked over all 2^32 inputs by the test suite on gfx950.
-__device__ __forceinline__ float recip(float z)
+__device__ __forceinline__ bool recip_exact(float z)
+{
+    const uint32_t mag = __builtin_bit_cast(uint32_t, z) & 0x7FFFFFFFu;
+    return mag - 0x00800000u <= 0x7E000000u - 0x00800000u;
+}
+
+// The Newton-refined reciprocal alone: equal to 1.0f / z where recip_exact(z).
+__device__ __forceinline__ float recip_newton(float z)
 {
     const float r = __builtin_amdgcn_rcpf(z);
-    float q = fmaf(fmaf(-z, r, 1.0f), r, r);
-    const uint32_t mag = __builtin_bit_cast(uint32_t, z) & 0x7FFFFFFFu;
-    if (__builtin_expect(mag - 0x00800000u > 0x7E000000u - 0x00800000u, 0)) q = 1.0f / z;
+    return fmaf(fmaf(-z, r, 1.0f), r, r);
+}
+
+__device__ __forceinline__ float recip(float z)
+{
+    float q = recip_newton(z);
+    if (__builtin_expect(!recip_exact(z), 0)) q = 1.0f / z;
     return q;
+}
+
+// A column's camera depths Z(k) = fma(a, k, c) are monotone in k (the fma of an exact
+// product and sum is rounded monotonically), so if its first and last voxels' depths have
+// one sign and lie where recip_newton is exact, so do all of them.
+__device__ __forceinline__ bool column_recip_exact(float z_first, float z_last)
+{
+    const bool a = recip_exact(z_first), b = recip_exact(z_last);
+    return a & b & ((z_first > 0.0f) == (z_last > 0.0f));
 }
 
 // The first active lane's value of a 32-bit unsigned quantity.  The builtin takes and

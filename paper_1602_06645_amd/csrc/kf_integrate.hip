@@ -126,11 +126,12 @@ struct Pixel {
     uint32_t off;
 };
 
-template <class C>
+template <bool EXACT = false, class C>
 __device__ __forceinline__ Pixel project(const C& c, float X, float Y, float Z)
 {
     Pixel p;
-    const float iz = recip(Z);
+    // EXACT: the caller has established recip_exact(Z)
+    const float iz = EXACT ? recip_newton(Z) : recip(Z);
     p.u = rintf(fmaf(c.fx, X * iz, c.cx));
     p.v = rintf(fmaf(c.fy, Y * iz, c.cy));
     p.inside = (Z > 0.0f) & (p.u >= 0.0f) & (p.u <= c.wm1) & (p.v >= 0.0f) & (p.v <= c.hm1);
@@ -172,22 +173,31 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
         float sdf[ZS];
         uint32_t upd = 0;
+        auto sweep = [&](auto exact) {
 #pragma unroll
-        for (int kk = 0; kk < ZS; ++kk) {
-            const float fk = (float)(col.k0 + kk);
-            const float Zc = fmaf(c.Ag[8], fk, cZ);
-            const Pixel px = project(c, fmaf(c.Ag[2], fk, cX), fmaf(c.Ag[5], fk, cY), Zc);
-            const bool in = px.inside & (kk < col.kn);
-            const float d = load_f32(depth, in ? px.off : kOutside);
-            const bool valid = in & valid_depth(d);
-            sdf[kk] = d - Zc;
-            const bool u = valid & !(sdf[kk] < -c.trunc);
-            upd |= (uint32_t)u << kk;
-            if constexpr (MODE == MODE_STATUS) {
-                if (kk < col.kn)
-                    status[col.base + (size_t)kk * col.slice] = (uint8_t)(!px.inside ? 0 : !valid ? 1 : u ? 6 : 2);
+            for (int kk = 0; kk < ZS; ++kk) {
+                const float fk = (float)(col.k0 + kk);
+                const float Zc = fmaf(c.Ag[8], fk, cZ);
+                const Pixel px = project<decltype(exact)::value>(c, fmaf(c.Ag[2], fk, cX),
+                                                                 fmaf(c.Ag[5], fk, cY), Zc);
+                const bool in = px.inside & (kk < col.kn);
+                const float d = load_f32(depth, in ? px.off : kOutside);
+                const bool valid = in & valid_depth(d);
+                sdf[kk] = d - Zc;
+                const bool u = valid & !(sdf[kk] < -c.trunc);
+                upd |= (uint32_t)u << kk;
+                if constexpr (MODE == MODE_STATUS) {
+                    if (kk < col.kn)
+                        status[col.base + (size_t)kk * col.slice] = (uint8_t)(!px.inside ? 0 : !valid ? 1 : u ? 6 : 2);
+                }
             }
-        }
+        };
+        // the per-voxel range test of the reciprocal, once per column and frame (a branch
+        // every lane takes the same way unless a column reaches the camera plane)
+        if (column_recip_exact(fmaf(c.Ag[8], (float)col.k0, cZ), fmaf(c.Ag[8], (float)(col.k0 + ZS - 1), cZ)))
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
         if constexpr (MODE != MODE_STATUS) {
             const uint32_t need = upd & ~loaded;
             if (need) {
@@ -292,25 +302,33 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         // (1) Eq. 5-7 and the distance test against sigma.
         uint32_t poff[ZS];   // byte offset of the depth pixel of voxels in the band
         uint32_t band = 0;
+        auto sweep = [&](auto exact) {
 #pragma unroll
-        for (int kk = 0; kk < ZS; ++kk) {
-            const float fk = (float)(col.k0 + kk);
-            const float Xc = fmaf(c.Ac[2], fk, cX);
-            const float Yc = fmaf(c.Ac[5], fk, cY);
-            const float Zc = fmaf(c.Ac[8], fk, cZ);
-            const Pixel px = project(c, Xc, Yc, Zc);
-            const bool in = px.inside & (kk < col.kn);
-            const float d = load_f32(depth, in ? px.off : kOutside);
-            const bool valid = in & valid_depth(d);
-            const float Px = ((px.u - c.cx) * c.inv_fx) * d;
-            const float Py = ((px.v - c.cy) * c.inv_fy) * d;
-            const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
-            const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const bool bd = valid & !(dist2 > c.sigma2);
-            band |= (uint32_t)bd << kk;
-            poff[kk] = bd ? px.off : kOutside;
-            if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
-        }
+            for (int kk = 0; kk < ZS; ++kk) {
+                const float fk = (float)(col.k0 + kk);
+                const float Xc = fmaf(c.Ac[2], fk, cX);
+                const float Yc = fmaf(c.Ac[5], fk, cY);
+                const float Zc = fmaf(c.Ac[8], fk, cZ);
+                const Pixel px = project<decltype(exact)::value>(c, Xc, Yc, Zc);
+                const bool in = px.inside & (kk < col.kn);
+                const float d = load_f32(depth, in ? px.off : kOutside);
+                const bool valid = in & valid_depth(d);
+                const float Px = ((px.u - c.cx) * c.inv_fx) * d;
+                const float Py = ((px.v - c.cy) * c.inv_fy) * d;
+                const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
+                const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const bool bd = valid & !(dist2 > c.sigma2);
+                band |= (uint32_t)bd << kk;
+                poff[kk] = bd ? px.off : kOutside;
+                if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
+            }
+        };
+        // the per-voxel range test of the reciprocal, once per column and frame (a branch
+        // every lane takes the same way unless a column reaches the camera plane)
+        if (column_recip_exact(fmaf(c.Ac[8], (float)col.k0, cZ), fmaf(c.Ac[8], (float)(col.k0 + ZS - 1), cZ)))
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
         if (band) {
             // (2)-(3) W of the voxel's depth pixel (Eq. 8 normal from the neighbours
             // (u+1, v) and (u, v+1); unit normal . unit viewing direction), computed once
