@@ -10,7 +10,7 @@ import torch
 
 import paper_1602_06645_amd as kf
 from gpu_helpers import (assert_bitwise, assert_matches_oracle, integrate_plain, say, to_host)
-from helpers import camera_volume, frames, intrinsics, plane_depth
+from helpers import camera_volume, frames, intrinsics, plane_depth, posed, ramp_image
 from kf_synth import configs
 from kf_synth.scenes import VolumeSpec, default_rgb_extrinsic
 
@@ -101,6 +101,27 @@ def test_passes_wider_than_32_frames(oracle, K):
     vol2 = kf.Volume(spec)
     kf.integrate_batch([(vol2, kf.Scan.from_frames(fr.to(DEV)))], frames_per_pass=K, use_graph=True)
     assert_bitwise(to_host(vol2), want_state, f"K={K} graph: ")
+
+
+def test_camera_inside_the_volume(oracle):
+    """The camera sits inside the volume, so voxel columns cross its plane (Z <= 0 at one end,
+    > 0 at the other): those columns take the per-voxel reciprocal with its range test, the
+    others the column-checked Newton reciprocal; both bit-exact with the oracle, plain and
+    fused."""
+    Kd = intrinsics(131.25, 79.5, 59.5)
+    spec = camera_volume(g=32, ratio=2, z0=-0.25, size=1.0)
+    poses = np.stack([posed((4.0 * f, -3.0 * f), (0.01 * f, -0.005 * f, 0.02 * f)) for f in range(5)])
+    fr = frames(np.full((5, 120, 160), 0.6), ramp_image(320, 240), Kd,
+                intrinsics(262.5, 159.5, 119.5), default_rgb_extrinsic(), poses, 0.03)
+    say("camera inside the volume: columns crossing the camera plane")
+    want, cnt = _oracle_state(oracle, spec, fr)
+    assert cnt[0] > 1000 and cnt[4] > 1000
+    vol = kf.Volume(spec)
+    integrate_plain(vol, fr.to(DEV))
+    assert_bitwise(to_host(vol), want, "plain: ")
+    vol2 = kf.Volume(spec)
+    kf.integrate_batch([(vol2, kf.Scan.from_frames(fr.to(DEV)))], frames_per_pass=5)
+    assert_bitwise(to_host(vol2), want, "fused: ")
 
 
 def test_ragged_volume_and_anisotropic_cameras(oracle):
