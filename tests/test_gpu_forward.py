@@ -86,16 +86,16 @@ def test_counters_match_oracle(oracle, tiny, K):
     assert_bitwise(to_host(vol), want_state, "counted: ")
 
 
-@pytest.mark.parametrize("K", [40, 64])
+@pytest.mark.parametrize("K", [40, 64, 1000])
 def test_passes_wider_than_32_frames(oracle, K):
-    """70 frames in passes of 40 (40 + 30) or 64 (64 + 6) frames: 64-bit frame masks with
-    live frames above bit 31, one wave per brick in the culling; state and counters equal
-    the oracle's."""
+    """70 frames in passes of 40 (40 + 30) or 64 (64 + 6) frames, and K = 1000, which acts
+    as 64: 64-bit frame masks with live frames above bit 31; state and counters (whose
+    per-pass figures depend on the pass length) equal the oracle's."""
     spec, fr = configs.tiny(n_frames=70)
     say(f"tiny: 70 frames, counted batch K={K}")
     vol = kf.Volume(spec)
     cnt = kf.integrate_batch_counted([(vol, kf.Scan.from_frames(fr.to(DEV)))], frames_per_pass=K)
-    want_state, want = _oracle_state(oracle, spec, fr, K)
+    want_state, want = _oracle_state(oracle, spec, fr, min(K, 64))
     assert list(cnt[:6]) == list(want)
     assert_bitwise(to_host(vol), want_state, f"K={K}: ")
     vol2 = kf.Volume(spec)
