@@ -375,6 +375,9 @@ struct BatchPlan {
 
 // Frames a pass can hold: one bit per frame in a brick's 64-bit live mask.
 constexpr int32_t kMaxFramesPerPass = 64;
+// Counters of a pass: live entries of the heavy and light lists of each kind, then the
+// queue head of each kind.
+constexpr size_t kPassCounters = 6;
 
 kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchPlan* plan)
 {
@@ -439,8 +442,8 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
 }
 
 // Device image of a plan:
-//   [frame table][scene table of each pass][4 counters per pass: live entries and queue
-//   heads of each kind][live list][pyramids][weight maps]
+//   [frame table][scene table of each pass][kPassCounters counters per pass][live lists:
+//   heavy and light][pyramids][weight maps]
 struct DeviceTables {
     std::vector<unsigned char> host;
     size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
@@ -459,11 +462,11 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
         off = align(off + pass.size() * sizeof(kf::SceneDev));
     }
     t->counters_off = off;
-    off = align(off + 4 * (p.passes.size() + 1) * sizeof(uint32_t));
+    off = align(off + kPassCounters * (p.passes.size() + 1) * sizeof(uint32_t));
     uint32_t max_items = 0;
     for (uint32_t n : p.pass_items) max_items = n > max_items ? n : max_items;
     t->live_off = off;
-    off = align(off + (size_t)max_items * sizeof(uint4));
+    off = align(off + 2 * (size_t)max_items * sizeof(uint4));
     t->pyr_off = off;
     for (const auto& fc : p.frames) {
         t->frame_pyr_off.push_back(off);
@@ -525,7 +528,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
     KF_HIP(kf::launch_weight_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
            "weight map launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
-    KF_HIP(kf::launch_fill_u32(cnt, 4 * (p.passes.size() + 1), 0u, stream), "counter reset");
+    KF_HIP(kf::launch_fill_u32(cnt, kPassCounters * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint4* live = (uint4*)(dev + t.live_off);
     const int disable = cull_disabled() ? 1 : 0;
     for (size_t q = 0; q < p.passes.size(); ++q) {
@@ -542,7 +545,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         c.max_frames = 0;
         for (const kf::SceneDev& d : p.passes[q]) c.max_frames = d.n_frames > c.max_frames ? d.n_frames : c.max_frames;
         c.live = live;
-        c.n_live = cnt + 4 * q;
+        c.n_live = cnt + kPassCounters * q;
         KF_HIP(kf::launch_cull(c, stream), "cull launch");
         kf::IntegrateArgs a;
         memset(&a, 0, sizeof a);
@@ -551,8 +554,8 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         a.n_scenes = c.n_scenes;
         a.live = live;
         a.cap = c.n_items;
-        a.n_live = cnt + 4 * q;
-        a.queue = cnt + 4 * q + 2;
+        a.n_live = cnt + kPassCounters * q;
+        a.queue = cnt + kPassCounters * q + 4;
         a.counters = counters;
         const bool timed = (int32_t)q < ev.n;
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.start[q], stream), "hipEventRecord");

@@ -77,11 +77,12 @@ struct IntegrateArgs {
     const SceneDev* scenes;           // table of n_scenes
     const FrameConsts* frames;        // frame table
     int32_t n_scenes;
-    const uint4* live;                // (brick, frame mask low, frame mask high, 0):
-                                      // geometry entries from the front, colour entries
-                                      // from the back
+    const uint4* live;                // (brick, frame mask low, frame mask high, 0): a
+                                      // heavy list [cap] and a light list [cap], each
+                                      // with geometry entries from the front and colour
+                                      // entries from the back
     uint32_t cap;                     // entries `live` can hold (bricks of the pass)
-    const uint32_t* n_live;           // [KIND]: entries of each kind
+    const uint32_t* n_live;           // [list][KIND]: entries of each list and kind
     uint32_t* queue;                  // [KIND]: next entry to take
     unsigned long long* counters;     // MODE_COUNT: uint64[8]
 };
@@ -102,8 +103,8 @@ struct CullArgs {
     uint32_t n_chunks;                // culling chunks of all scenes of the pass
     int32_t disable;                  // 1: every brick is live in every frame
     int32_t max_frames;               // frames of the pass's longest scene (<= 64)
-    uint4* live;                      // n_items entries (see IntegrateArgs)
-    uint32_t* n_live;                 // [KIND]
+    uint4* live;                      // 2 x n_items entries (see IntegrateArgs)
+    uint32_t* n_live;                 // [list][KIND]
 };
 
 // The adjoint over up to 64 frames: colour bricks culled like the forward's, then

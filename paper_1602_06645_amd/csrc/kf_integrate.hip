@@ -516,17 +516,29 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
         const unsigned long long mask = q < nbr ? s_mask[q] : 0ull;
         const unsigned long long has = __ballot(mask != 0ull);
         if (has == 0ull) return;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.n_live + (colour ? KIND_COLOUR : KIND_GEOM),
-                                        (uint32_t)__builtin_popcountll(has));
-        base = __shfl(base, 0, WAVE);
+        // bricks live in at least half of the pass's frames go to the heavy list, which the
+        // integration drains first (longest first shortens the launch's tail)
+        const bool heavy = 2u * (uint32_t)__builtin_popcountll(mask) >= (uint32_t)a.max_frames;
+        const unsigned long long hv = __ballot(mask != 0ull && heavy), lt = has & ~hv;
+        const int kind = colour ? KIND_COLOUR : KIND_GEOM;
+        uint32_t base_h = 0, base_l = 0;
+        if (lane == 0) {
+            if (hv) base_h = atomicAdd(a.n_live + kind, (uint32_t)__builtin_popcountll(hv));
+            if (lt) base_l = atomicAdd(a.n_live + 2 + kind, (uint32_t)__builtin_popcountll(lt));
+        }
+        base_h = __shfl(base_h, 0, WAVE);
+        base_l = __shfl(base_l, 0, WAVE);
         if (mask != 0ull) {
             const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
             const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
             const uint32_t li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
             const uint32_t item = sc.item_begin + (colour ? sc.geom_items : 0u) + li;
-            const uint32_t pos = base + (uint32_t)__builtin_popcountll(has & ((1ull << lane) - 1ull));
-            a.live[colour ? a.n_items - 1u - pos : pos] = make_uint4(item, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const bool h = (hv >> lane) & 1ull;
+            const uint32_t pos = h ? base_h + (uint32_t)__builtin_popcountll(hv & below)
+                                   : base_l + (uint32_t)__builtin_popcountll(lt & below);
+            uint4* list = a.live + (h ? 0u : a.n_items);
+            list[colour ? a.n_items - 1u - pos : pos] = make_uint4(item, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
         }
     }
 }
@@ -626,12 +638,16 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     Counts cnt;
-    const uint32_t n_live = *as_const(a.n_live + KIND);
+    // the heavy list first, then the light one
+    const uint32_t n_heavy = *as_const(a.n_live + KIND);
+    const uint32_t n_live = n_heavy + *as_const(a.n_live + 2 + KIND);
     const const_ptr<SceneDev> scenes = as_const(a.scenes);
     for (;;) {
         const uint32_t e = wave_ticket(a.queue + KIND);
         if (e >= n_live) break;
-        const uint32_t pos = KIND == KIND_COLOUR ? a.cap - 1u - e : e;
+        const bool light = e >= n_heavy;
+        const uint32_t el = light ? e - n_heavy : e;
+        const uint32_t pos = (KIND == KIND_COLOUR ? a.cap - 1u - el : el) + (light ? a.cap : 0u);
         const const_ptr<uint32_t> ent = as_const((const uint32_t*)a.live) + 4 * (size_t)pos;
         const uint32_t item = ent[0];
         const unsigned long long fmask = ent[1] | (unsigned long long)ent[2] << 32;
