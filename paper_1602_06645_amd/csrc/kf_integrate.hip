@@ -6,11 +6,13 @@
 //      their 2x2 reductions (built once per batch call for all frames);
 //   2. cull kernel: one thread per (brick, frame) decides whether any voxel of the
 //      brick can pass the depth tests (conservatively, from the brick's corners and the
-//      pyramid) and appends (brick, frame mask) of the live bricks to a list;
+//      pyramid) and appends (brick, frame mask) of the live bricks to a heavy or a light
+//      list by the number of frames in the mask;
 //   3. integrate kernels (one launch for geometry bricks, one for colour bricks):
-//      persistent waves take live bricks from the list; each lane keeps its column's ZS
-//      voxels in registers for all frames of the pass, reads a voxel's state only when a
-//      frame first needs it and writes it back only if it was read.
+//      persistent waves take live bricks from the lists, heavy ones first; each lane
+//      keeps its column's ZS voxels in registers for all frames of the pass, reads a
+//      voxel's state only when a frame first needs it and writes it back only if it was
+//      read.
 // Culling never changes a result: a brick is dropped for a frame only if every voxel in
 // it would have been rejected before touching its state.
 //
@@ -449,11 +451,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 // One block per culling chunk (CHUNK^3 bricks of one kind).  The first wave tests the
 // chunk's voxel box against the frames of the pass (one lane per frame) and lists the
 // frames it passed; the block then tests the (brick, listed frame) pairs, one per thread
-// (frame-major), and ORs each live pair's frame bit into its brick's mask in LDS.  Skipping the other
-// frames is exact: the chunk test is conservative for every voxel of the chunk, as the
-// brick test is for every voxel of the brick.  The first wave appends the bricks with a
-// non-empty mask to the list in brick order, with one atomic per block (geometry from
-// the front, colour from the back).
+// (frame-major), and ORs each live pair's frame bit into its brick's mask in LDS.
+// Skipping the other frames is exact: the chunk test is conservative for every voxel of
+// the chunk, as the brick test is for every voxel of the brick.  The first wave appends
+// the bricks with a non-empty mask to the heavy or the light list in brick order, with
+// one atomic per list and block (geometry from the front, colour from the back).
 constexpr int CHUNK_BRICKS = CHUNK * CHUNK * CHUNK;
 static_assert(CHUNK_BRICKS <= WAVE, "one lane per brick of a chunk in the append");
 
