@@ -391,12 +391,16 @@ def main() -> int:
 
     if not args.no_cpu:
         from oracle import oracle as O
-        n_cpu = min(6, fr.n)
-        sub = fr.select(slice(0, n_cpu)).numpy()
+        # a bounded sample: consecutive frames of the same scan, one call each, until about
+        # 10 s of oracle time
         st = O.State(spec, np.float32)
-        tc = time.perf_counter()
-        O.integrate(spec, sub, st)
-        t_cpu = time.perf_counter() - tc
+        n_cpu, t_cpu = 0, 0.0
+        while n_cpu < fr.n and t_cpu < 10.0:
+            one = fr.select(slice(n_cpu, n_cpu + 1)).numpy()
+            tc = time.perf_counter()
+            O.integrate(spec, one, st)
+            t_cpu += time.perf_counter() - tc
+            n_cpu += 1
         out["cpu_baseline"] = {"value": n_vox * n_cpu / t_cpu, "unit": "voxel updates/s",
                                "cores": O.num_threads(), "kind": "oracle",
                                "sample": f"frames 0-{n_cpu - 1} of the same scan, whole volume "
