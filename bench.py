@@ -2,22 +2,29 @@
 """Benchmark of the per-frame volumetric integration (TSDF geometry volume + asymmetric
 colour volume, arXiv 1602.06645 Sec. III and IV.B) on one MI355X.
 
-Workload (synthetic, seeded): geometry 256^3 + colour 512^3 over a 0.75 m cube, a
-300-frame orbit of 640x480 float depth (noisy, 1 % holes) and 1920x1080 RGB8 images of
-3 spheres and 2 boxes on a plane; trunc = 4 geometry voxels, w_max = 128.
+Headline workload (synthetic, seeded): the fused multi-frame scan, geometry 512^3 +
+colour 1024^3 over a 1 m cube (18.3 GB of state), a 256-frame orbit of 640x480 float
+depth (noisy, 1 % holes) and 1920x1080 RGB8 images of 4 spheres and 4 boxes on a plane;
+trunc = 4 geometry voxels, w_max = 128.
 
-One step = one whole scan: reset the volume, then integrate all 300 frames in passes of
-K frames (one call: depth pyramids for all frames, then per pass a culling launch and two
-persistent integration launches, geometry bricks then colour bricks).  The metric counts
-every voxel of both volumes once per frame (the swept voxel updates of KinectFusion-style
-integration).  Besides the headline line the JSON carries: the plain frame-by-frame path
-and the fused/plain speedup, forward + backward time of the differentiable form on the
-first 32 frames, the roofline of the dominant kernels (VALU-bound: algorithmic operations
-per pass over the pass's measured duration, with the HBM fraction of the algorithmic bytes
-beside it; both from units of work counted by the kernels' counting instantiation), and the
-CPU oracle timed on a sample.
+One step = one whole scan: reset the volume, then integrate all 256 frames in passes of
+K frames (K from the autotuner; one call: depth pyramids and weight maps for all frames,
+then per pass a culling launch and two persistent integration launches, geometry bricks
+then colour bricks).  The metric counts every voxel of both volumes once per frame (the
+swept voxel updates of KinectFusion-style integration).
 
-Usage: python bench.py [--steps K] [--warmup W] [--frames N] [--frames-per-pass K]
+Besides the headline the JSON line carries: the plain frame-by-frame path on the same
+scan and the fused/plain speedup; the roofline of the dominant kernel (the colour
+integration launch, VALU-bound: algorithmic operations per launch over its duration
+measured with HIP events on the launch stream, with the HBM fraction of its algorithmic
+bytes beside it); the many-uneven-scenes batch (16 scans, 86 GB of state) against the
+same scans integrated one by one; a device copy giving the achievable HBM bandwidth;
+the Kinect-like scan (256^3 / 512^3, 300 frames) with ray casting, marching cubes and
+texture maps of its volume; forward + backward of the differentiable form on its first
+32 frames; and the CPU oracle timed on a sample of the headline scan's z-slabs on all
+host threads and on one.
+
+Usage: python bench.py [--steps K] [--warmup W] [--frames-per-pass K] [--legs a,b,...]
 """
 from __future__ import annotations
 
@@ -60,21 +67,13 @@ OPS = {
     # product, norms, dot product, square root and division): its own launch
     "weight_map_pixel": 59,
 }
-WORKLOAD = ("kinect-like scan: geometry 256^3 + colour 512^3 (2x per axis) over 0.75 m, "
-            "300 frames of 640x480 float32 depth + 1920x1080 RGB8")
+WORKLOAD = ("fused multi-frame scan: geometry 512^3 + colour 1024^3 (2x per axis) over 1.0 m, "
+            "256 frames of 640x480 float32 depth + 1920x1080 RGB8, 4 spheres + 4 boxes")
+ALL_LEGS = ("plain", "copy", "many", "kinect", "backward", "cpu")
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def default_frames_per_pass() -> int:
-    path = os.path.join(ROOT, "paper_1602_06645_amd", "tuning.json")
-    try:
-        with open(path) as f:
-            return int(json.load(f)["kinect"]["frames_per_pass"])
-    except (OSError, KeyError, ValueError):
-        return 8
 
 
 def kernel_source_hash() -> str:
@@ -87,10 +86,11 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(K: int):
-    """HBM bytes per pass of the integrate kernels from the rocprofv3 FETCH_SIZE and
-    WRITE_SIZE runs recorded under profiles/ (scaled by the same counters on a plain copy
-    of known size); None when the kernel source or the pass length changed since."""
-    path = os.path.join(ROOT, "profiles", "integrate_kernel_kinect_traffic.txt")
+    """HBM bytes per launch of the integration kernels on the headline scan from the
+    rocprofv3 FETCH_SIZE and WRITE_SIZE runs recorded under profiles/ (scaled by the same
+    counters on a plain copy of known size): {"colour": B, "geometry": B}; None when the
+    kernel source or the pass length changed since."""
+    path = os.path.join(ROOT, "profiles", "integrate_kernels_fused_traffic.txt")
     try:
         with open(path) as f:
             rec = json.loads(f.read().split("JSON:", 1)[1])
@@ -101,13 +101,37 @@ def measured_traffic(K: int):
     return rec.get("bytes_per_launch")
 
 
-def pass_scans(kf, fr, K):
-    out = []
-    for p in range(0, fr.n, K):
-        q = min(fr.n, p + K)
-        out.append(kf.Scan(fr.depth[p:q], fr.rgb[p:q], fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
-                           fr.T_world_from_cam[p:q], fr.trunc, fr.w_max))
-    return out
+def alg_counts(cnt, n_frames, frame_bytes):
+    """Algorithmic bytes and operations of a whole scan from the counting instantiation's
+    counters, split by launch kind (the frame inputs are charged to the colour launch,
+    which reads the HD images, and the geometry launch, which reads the depth maps)."""
+    g_bytes = 16 * int(cnt[1])
+    c_bytes = 4 * int(cnt[3]) + 28 * int(cnt[5])
+    g_ops = OPS["geom_voxel_frame"] * 512 * int(cnt[6]) + OPS["geom_update"] * int(cnt[0])
+    c_ops = (OPS["colour_voxel_frame"] * 512 * int(cnt[7]) + OPS["colour_gate"] * int(cnt[2])
+             + OPS["colour_update"] * int(cnt[4]))
+    return {"geometry": {"bytes": g_bytes + n_frames * frame_bytes[0], "ops": g_ops},
+            "colour": {"bytes": c_bytes + n_frames * (frame_bytes[0] + frame_bytes[1]),
+                       "ops": c_ops}}
+
+
+def counters_dict(cnt, spec, n):
+    return {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
+            "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),
+            "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5]),
+            "geom_brick_frames": int(cnt[6]), "colour_brick_frames": int(cnt[7]),
+            "geom_live_fraction": int(cnt[6]) * 512 / (spec.n_geom * n),
+            "colour_live_fraction": int(cnt[7]) * 512 / (spec.n_colour * n)}
+
+
+def timed_reps(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
 
 
 def main() -> int:
@@ -115,11 +139,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--frames-per-pass", type=int, default=0, help="0: tuned default")
+    ap.add_argument("--legs", default=",".join(ALL_LEGS),
+                    help="extra legs after the headline, comma-separated, from "
+                         + ",".join(ALL_LEGS) + " ('' for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="time only the fused scan (for profiling runs)")
+    ap.add_argument("--no-extras", action="store_true", help="time only the headline scan")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only run the plain frame-by-frame path twice (for profiling it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -129,12 +156,20 @@ def main() -> int:
               "(the integration runs on one GPU per process)",
               file=sys.stderr, flush=True)
         return 2
+    legs = set() if args.no_extras else {x for x in args.legs.split(",") if x}
+    if args.no_cpu:
+        legs.discard("cpu")
+    unknown = legs - set(ALL_LEGS)
+    if unknown:
+        print(f"unknown legs {sorted(unknown)}", file=sys.stderr)
+        return 2
 
     import numpy as np
     import torch
 
     import paper_1602_06645_amd as kf
     from kf_synth import configs
+    from paper_1602_06645_amd import autotune
 
     if not torch.cuda.is_available():
         log("no GPU visible")
@@ -148,62 +183,78 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_per_dispatch": 4 << 28}), flush=True)
         return 0
-    K = args.frames_per_pass or default_frames_per_pass()
+    K = args.frames_per_pass or autotune.frames_per_pass("fused", default=64)
 
     t = time.perf_counter()
-    spec, fr = configs.kinect(device="cuda", n_frames=args.frames)
+    spec, fr = configs.fused(device="cuda")
     torch.cuda.synchronize()
-    log(f"generated {fr.n} frames on the GPU in {time.perf_counter() - t:.1f} s")
+    log(f"generated the fused scan ({fr.n} frames) on the GPU in {time.perf_counter() - t:.1f} s")
     n_vox = spec.n_geom + spec.n_colour
     vol = kf.Volume(spec)
-    passes = pass_scans(kf, fr, K)
-    frame_bytes = fr.depth[0].numel() * 4 + fr.rgb[0].numel()
-
-    # ---- algorithmic bytes of the fused scan (counting instantiation, not timed)
-    vol.reset()
-    cnt = kf.integrate_batch_counted([(vol, kf.Scan.from_frames(fr))], frames_per_pass=K)
-    alg_bytes = 16 * int(cnt[1]) + 4 * int(cnt[3]) + 28 * int(cnt[5]) + fr.n * frame_bytes
-    log(f"counters {list(map(int, cnt))}; algorithmic bytes per scan {alg_bytes / 1e9:.3f} GB")
-
-    # ---- fused scan: warmup, then the timed steps.  A step integrates the whole scan in
-    # one call (passes of K frames); HIP events recorded by the library around each
-    # integration launch give the dominant kernel's duration.
     scan = kf.Scan.from_frames(fr)
-    n_pass = len(passes)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(n_pass * args.steps)]
 
-    def scan_step(events=None):
+    def plain_scan():
         vol.reset()
-        if events is None:
-            kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
-        else:
-            kf.integrate_batch_timed([(vol, scan)], K, events)
+        for f in range(fr.n):
+            vol.integrate(fr.depth[f], fr.rgb[f], fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
+                          fr.T_world_from_cam[f], fr.trunc, fr.w_max)
+
+    if args.plain_only:
+        for _ in range(2):
+            log(f"plain scan: {1e3 * timed_reps(plain_scan, 1):.1f} ms")
+        return 0
+
+    frame_bytes = (fr.depth[0].numel() * 4, fr.rgb[0].numel())
+    n_pass = (fr.n + K - 1) // K
+
+    # ---- algorithmic bytes and operations (counting instantiation, not timed)
+    vol.reset()
+    cnt = kf.integrate_batch_counted([(vol, scan)], frames_per_pass=K)
+    alg = alg_counts(cnt, fr.n, frame_bytes)
+    log(f"counters {list(map(int, cnt))}; algorithmic bytes per scan "
+        f"{(alg['geometry']['bytes'] + alg['colour']['bytes']) / 1e9:.3f} GB")
+
+    # ---- headline: warmup through the recorded graph, then the timed steps; HIP events
+    # recorded by the library around each launch give the kernels' durations
+    def graph_scan():
+        vol.reset()
+        kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
 
     for _ in range(args.warmup):
-        scan_step()
+        graph_scan()
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} scans, K={K}, {n_pass} passes per scan)")
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
+          for _ in range(n_pass * args.steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        scan_step(ev[s * n_pass:(s + 1) * n_pass])
+        vol.reset()
+        kf.integrate_batch_timed([(vol, scan)], K, ev[s * n_pass:(s + 1) * n_pass])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+    wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
     value = n_vox * fr.n * args.steps / wall
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s, "
-        f"integrate kernels {launch_ms:.3f} ms per pass")
-    per_launch_bytes = alg_bytes / len(passes)
-    achieved_gbs = per_launch_bytes / (launch_ms * 1e-3) / 1e9
-    # algorithmic operations of the two integration launches of one pass (the weight maps
-    # are computed by their own launch and are not part of it)
-    alg_ops = (OPS["geom_voxel_frame"] * 512 * int(cnt[6]) + OPS["geom_update"] * int(cnt[0])
-               + OPS["colour_voxel_frame"] * 512 * int(cnt[7]) + OPS["colour_gate"] * int(cnt[2])
-               + OPS["colour_update"] * int(cnt[4]))
-    per_launch_ops = alg_ops / len(passes)
-    achieved_tops = per_launch_ops / (launch_ms * 1e-3) / 1e12
+    geom_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    col_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    log(f"fused: {ms_step:.2f} ms per scan, {value:.4g} voxel updates/s; per pass geometry "
+        f"launch {geom_ms:.3f} ms, colour launch {col_ms:.3f} ms")
+
+    def launch_roof(kind, ms):
+        ops = alg[kind]["ops"] / n_pass
+        byts = alg[kind]["bytes"] / n_pass
+        tops = ops / (ms * 1e-3) / 1e12
+        gbs = byts / (ms * 1e-3) / 1e9
+        return {"launch_ms": ms, "algorithmic_ops_per_launch": ops, "achieved_tops": tops,
+                "frac": tops / ALU_PEAK_TOPS, "algorithmic_bytes_per_launch": byts,
+                "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS}}
+
+    colour = launch_roof("colour", col_ms)
+    geom = launch_roof("geometry", geom_ms)
+    both_ms = geom_ms + col_ms
+    both_tops = (alg["geometry"]["ops"] + alg["colour"]["ops"]) / n_pass / (both_ms * 1e-3) / 1e12
+    traffic = measured_traffic(K)
     out = {
         "metric": METRIC,
         "value": value,
@@ -222,62 +273,135 @@ def main() -> int:
                    "depth": [fr.depth.shape[2], fr.depth.shape[1]],
                    "rgb": [fr.rgb.shape[2], fr.rgb.shape[1]], "rgb_format": "u8",
                    "trunc_m": fr.trunc, "w_max": fr.w_max, "sigma_m": spec.sigma,
-                   "gate": spec.gate},
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
-                     "unit": "Top/s (FP32 vector operations)",
-                     "frac": achieved_tops / ALU_PEAK_TOPS, "traffic": measured_traffic(K),
-                     "algorithmic_ops_per_launch": per_launch_ops,
-                     "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved_gbs / HBM_PEAK_GBS},
-                     "kernel": "integrate_kernel<0,0> + integrate_kernel<0,1> (geometry and "
-                               "colour persistent launches of one fused pass)",
-                     "launch_ms": launch_ms, "algorithmic_bytes_per_launch": per_launch_bytes},
-        "counters": {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
-                     "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),
-                     "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5]),
-                     "geom_brick_frames": int(cnt[6]), "colour_brick_frames": int(cnt[7]),
-                     "geom_live_fraction": int(cnt[6]) * 512 / (spec.n_geom * fr.n),
-                     "colour_live_fraction": int(cnt[7]) * 512 / (spec.n_colour * fr.n)},
+                   "gate": spec.gate, "graph": "warmup only (timed steps record events)"},
+        "roofline": {"bound": "alu", "achieved": colour["achieved_tops"], "peak": ALU_PEAK_TOPS,
+                     "unit": "Top/s (FP32 vector operations)", "frac": colour["frac"],
+                     "traffic": None if traffic is None else traffic.get("colour"),
+                     "kernel": "integrate_kernel<0,1> (colour bricks, persistent launch of one "
+                               "fused pass)",
+                     "launch_ms": col_ms,
+                     "algorithmic_ops_per_launch": colour["algorithmic_ops_per_launch"],
+                     "algorithmic_bytes_per_launch": colour["algorithmic_bytes_per_launch"],
+                     "hbm": colour["hbm"],
+                     "geometry_launch": dict(geom, traffic=None if traffic is None
+                                             else traffic.get("geometry")),
+                     "both_launches": {"launch_ms": both_ms, "achieved_tops": both_tops,
+                                       "frac": both_tops / ALU_PEAK_TOPS}},
+        "counters": counters_dict(cnt, spec, fr.n),
         "effective_voxel_updates_per_s": (int(cnt[0]) + int(cnt[4])) * args.steps / wall,
     }
 
-    if not args.no_extras:
-        # ---- plain frame-by-frame path over the same scan
-        def plain_step():
-            vol.reset()
-            for f in range(fr.n):
-                vol.integrate(fr.depth[f], fr.rgb[f], fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
-                              fr.T_world_from_cam[f], fr.trunc, fr.w_max)
-        plain_step()
-        torch.cuda.synchronize()
-        tp = time.perf_counter()
-        n_plain = max(1, min(args.steps, 3))
-        for _ in range(n_plain):
-            plain_step()
-        torch.cuda.synchronize()
-        plain_wall = (time.perf_counter() - tp) / n_plain
+    if "plain" in legs:
+        # ---- the plain frame-by-frame path on the same scan (one call per frame)
+        plain_scan()
+        plain_wall = timed_reps(plain_scan, 1)
         out["plain_ms_per_step"] = 1e3 * plain_wall
         out["plain_voxel_updates_per_s"] = n_vox * fr.n / plain_wall
         out["fused_vs_plain"] = plain_wall / (wall / args.steps)
-        log(f"plain: {1e3 * plain_wall:.2f} ms per scan; fused speedup {out['fused_vs_plain']:.2f}x")
+        log(f"plain: {1e3 * plain_wall:.1f} ms per scan; fused speedup {out['fused_vs_plain']:.2f}x")
 
-        # ---- the nearest-pixel HD sampling variant: the same scan and launch configuration
-        import dataclasses
-        spec_n = dataclasses.replace(spec, hd_sampling="nearest")
-        vol_n = kf.Volume(spec_n)
+    cpu_frames = fr.numpy() if "cpu" in legs else None
+    del scan, fr, vol
+    torch.cuda.empty_cache()
 
-        def nearest_step():
-            vol_n.reset()
-            kf.integrate_batch([(vol_n, scan)], frames_per_pass=K, use_graph=True)
-        nearest_step()
+    if "copy" in legs:
+        # ---- achievable HBM bandwidth: a 4 GiB device-to-device copy (read + write)
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        tn = time.perf_counter()
-        for _ in range(3):
-            nearest_step()
+        ms = e0.elapsed_time(e1) / 5
+        out["hbm_copy"] = {"GBps": 2 * 4 * n / (ms * 1e-3) / 1e9, "bytes": 2 * 4 * n,
+                           "ms": ms, "note": "torch copy_ of 4 GiB float32, read + write"}
+        log(f"HBM copy: {out['hbm_copy']['GBps']:.0f} GB/s")
+        del src, dst
+        torch.cuda.empty_cache()
+
+    if "many" in legs:
+        # ---- 16 uneven scans in one batch call against the same scans one by one
+        t = time.perf_counter()
+        scans = configs.multi_scene(device="cuda")
         torch.cuda.synchronize()
-        out["nearest_ms_per_step"] = 1e3 * (time.perf_counter() - tn) / 3
-        log(f"nearest-pixel HD sampling: {out['nearest_ms_per_step']:.2f} ms per scan")
-        del vol_n
+        log(f"generated the many-scenes batch ({len(scans)} scans) in {time.perf_counter() - t:.1f} s")
+        vols = [kf.Volume(s) for s, _ in scans]
+        pairs = [(v, kf.Scan.from_frames(f)) for v, (_, f) in zip(vols, scans)]
+        Km = autotune.frames_per_pass("many_scenes", default=32)
+
+        def batched():
+            for v in vols:
+                v.reset()
+            kf.integrate_batch(pairs, frames_per_pass=Km, use_graph=True)
+
+        def one_by_one_fused():
+            for p in pairs:
+                p[0].reset()
+                kf.integrate_batch([p], frames_per_pass=Km, use_graph=True)
+
+        def one_by_one_plain():
+            for v, (s, f) in zip(vols, scans):
+                v.reset()
+                for q in range(f.n):
+                    v.integrate(f.depth[q], f.rgb[q], f.K_d, f.K_rgb, f.T_rgb_from_d,
+                                f.T_world_from_cam[q], f.trunc, f.w_max)
+        batched()
+        one_by_one_fused()
+        b_s = timed_reps(batched, 3)
+        f_s = timed_reps(one_by_one_fused, 3)
+        one_by_one_plain()
+        p_s = timed_reps(one_by_one_plain, 1)
+        nv = sum((s.n_geom + s.n_colour) * f.n for s, f in scans)
+        out["many_scenes"] = {
+            "scenes": len(scans), "state_GB": sum(4 * 2 * s.n_geom + 4 * 4 * s.n_colour
+                                                  for s, _ in scans) / 1e9,
+            "frames_per_scene": scans[0][1].n, "frames_per_pass": Km,
+            "batched_ms": 1e3 * b_s, "batched_voxel_updates_per_s": nv / b_s,
+            "sequential_fused_ms": 1e3 * f_s, "sequential_plain_ms": 1e3 * p_s,
+            "batched_vs_sequential_plain": p_s / b_s, "batched_vs_sequential_fused": f_s / b_s,
+            "note": "resets of all volumes included in every figure"}
+        log(f"many scenes: batched {1e3 * b_s:.1f} ms, one by one fused {1e3 * f_s:.1f} ms, "
+            f"one by one plain {1e3 * p_s:.1f} ms")
+        del vols, pairs, scans
+        torch.cuda.empty_cache()
+
+    if legs & {"kinect", "backward"}:
+        kinect_legs(out, legs, kf, configs, np, torch)
+
+    if "cpu" in legs:
+        out["cpu_baseline"], out["cpu_baseline_1core"] = cpu_legs(spec, cpu_frames, np)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def kinect_legs(out, legs, kf, configs, np, torch):
+    """The Kinect-like scan (256^3 / 512^3, 300 frames): fused scan time, ray casting,
+    marching cubes and texture maps of its volume; forward + backward on its first 32
+    frames."""
+    from paper_1602_06645_amd import autotune
+    t = time.perf_counter()
+    spec, fr = configs.kinect(device="cuda")
+    torch.cuda.synchronize()
+    log(f"generated the Kinect-like scan ({fr.n} frames) in {time.perf_counter() - t:.1f} s")
+    vol = kf.Volume(spec)
+    scan = kf.Scan.from_frames(fr)
+    res = {"workload": "geometry 256^3 + colour 512^3 over 0.75 m, 300 frames of 640x480 "
+                       "depth + 1920x1080 RGB8"}
+    if "kinect" in legs:
+        K = autotune.frames_per_pass("kinect", default=64)
+
+        def scan_step():
+            vol.reset()
+            kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
+        scan_step()
+        s = timed_reps(scan_step, 5)
+        res.update({"frames_per_pass": K, "ms_per_scan": 1e3 * s,
+                    "voxel_updates_per_s": (spec.n_geom + spec.n_colour) * fr.n / s})
+        log(f"kinect scan: {1e3 * s:.2f} ms")
 
         # ---- ray casting of the integrated volumes (the scan's poses, depth resolution)
         step = 0.8 * fr.trunc
@@ -296,7 +420,7 @@ def main() -> int:
         torch.cuda.synchronize()
         rc_ms = float(np.mean([a.elapsed_time(b) for a, b in rc_ev]))
         hit_frac = float(np.mean([float((d > 0).float().mean()) for d in hits]))
-        out["raycast"] = {"ms_per_image": rc_ms, "rays_per_s": W * H / (rc_ms * 1e-3),
+        res["raycast"] = {"ms_per_image": rc_ms, "rays_per_s": W * H / (rc_ms * 1e-3),
                           "image": [W, H], "step_m": step, "poses": len(rc_poses),
                           "hit_fraction": hit_frac,
                           "outputs": "depth, vertex, normal, rgb (float32)"}
@@ -317,7 +441,7 @@ def main() -> int:
         torch.cuda.synchronize()
         mc_wall = (time.perf_counter() - tm) / len(mc_ev)
         mc_ms = float(np.mean([a.elapsed_time(b) for a, b in mc_ev]))
-        out["mesh"] = {"ms_per_mesh": mc_ms, "wall_ms_per_call": 1e3 * mc_wall,
+        res["mesh"] = {"ms_per_mesh": mc_ms, "wall_ms_per_call": 1e3 * mc_wall,
                        "vertices": cap[0], "triangles": cap[1],
                        "voxels_per_s": spec.n_geom / (mc_ms * 1e-3),
                        "note": "one kf_mesh_extract call: classify, count, scan, read the "
@@ -326,7 +450,7 @@ def main() -> int:
             f"{cap[0]} vertices, {cap[1]} triangles")
         del verts, tris
 
-        # ---- per-polygon texture maps from the integrated colour volume (Sec. IV.C)
+        # ---- per-polygon texture maps from the integrated colour volume (Sec. IV.D)
         tri, size_pixel = configs.kinect_triangles(n_frames=fr.n)
         AH = 4096
         rects, AW = kf.texture_layout(tri, size_pixel, AH)
@@ -344,7 +468,7 @@ def main() -> int:
         tx_ms = float(np.mean([a.elapsed_time(b) for a, b in tx_ev]))
         n_texels = int((rects[:, 2].astype(np.int64) * rects[:, 3]).sum())
         nonzero = float(atlas["rgb8"].reshape(-1, 3).amax(1).gt(0).sum()) / n_texels
-        out["texture"] = {"ms_per_atlas": tx_ms, "texels_per_s": n_texels / (tx_ms * 1e-3),
+        res["texture"] = {"ms_per_atlas": tx_ms, "texels_per_s": n_texels / (tx_ms * 1e-3),
                           "triangles": len(tri), "texels": n_texels, "atlas": [AW, AH],
                           "size_pixel_m": size_pixel, "nonzero_fraction": nonzero,
                           "outputs": "float32 RGB + 8-bit RGB atlases",
@@ -353,6 +477,7 @@ def main() -> int:
             f"({nonzero:.3f} non-zero)")
         del atlas, tri_d, rects_d
 
+    if "backward" in legs:
         # ---- differentiable form: first 32 frames as float images, forward + backward
         nb = min(32, fr.n)
         rgbf = fr.rgb[:nb].to(torch.float32) * torch.tensor(np.float32(1.0 / 255.0), device="cuda")
@@ -364,50 +489,66 @@ def main() -> int:
             vol.reset()
             kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
             return kf.integrate_backward(spec, scan32, g)
-        fwd_bwd()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
-            fwd_bwd()
-        torch.cuda.synchronize()
-        out["fwd_bwd_ms"] = 1e3 * (time.perf_counter() - tb) / reps
-        out["fwd_bwd_config"] = f"first {nb} frames, float32 RGB, full volume, g ~ N(0,1) on every colour voxel"
-        log(f"forward+backward ({nb} frames): {out['fwd_bwd_ms']:.2f} ms")
 
         def fwd_bwd_pose():
             vol.reset()
             kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
             return kf.integrate_backward(spec, scan32, g, pose=True)
+        fwd_bwd()
+        res["fwd_bwd_ms"] = 1e3 * timed_reps(fwd_bwd, 3)
+        res["fwd_bwd_config"] = (f"first {nb} frames, float32 RGB, full volume, g ~ N(0,1) on "
+                                 "every colour voxel")
+        log(f"forward+backward ({nb} frames): {res['fwd_bwd_ms']:.2f} ms")
         fwd_bwd_pose()
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        for _ in range(reps):
-            fwd_bwd_pose()
-        torch.cuda.synchronize()
-        out["fwd_bwd_pose_ms"] = 1e3 * (time.perf_counter() - tb) / reps
-        log(f"forward+backward with the {nb} depth-pose gradients: {out['fwd_bwd_pose_ms']:.2f} ms")
+        res["fwd_bwd_pose_ms"] = 1e3 * timed_reps(fwd_bwd_pose, 3)
+        log(f"forward+backward with the {nb} depth-pose gradients: {res['fwd_bwd_pose_ms']:.2f} ms")
+        out["fwd_bwd_ms"] = res["fwd_bwd_ms"]
         del rgbf, scan32, g
+    out["kinect"] = res
+    del vol, scan, fr
+    torch.cuda.empty_cache()
 
-    if not args.no_cpu:
-        from oracle import oracle as O
-        # a bounded sample: consecutive frames of the same scan, one call each, until about
-        # 10 s of oracle time
-        st = O.State(spec, np.float32)
-        n_cpu, t_cpu = 0, 0.0
-        while n_cpu < fr.n and t_cpu < 10.0:
-            one = fr.select(slice(n_cpu, n_cpu + 1)).numpy()
-            tc = time.perf_counter()
-            O.integrate(spec, one, st)
-            t_cpu += time.perf_counter() - tc
-            n_cpu += 1
-        out["cpu_baseline"] = {"value": n_vox * n_cpu / t_cpu, "unit": "voxel updates/s",
-                               "cores": O.num_threads(), "kind": "oracle",
-                               "sample": f"frames 0-{n_cpu - 1} of the same scan, whole volume "
-                                         f"(plain C oracle, OpenMP over z), {t_cpu:.1f} s"}
-        log(f"cpu oracle: {out['cpu_baseline']['value']:.4g} voxel updates/s on {O.num_threads()} threads")
-    print(json.dumps(out), flush=True)
-    return 0
+
+def cpu_legs(spec, frames, np):
+    """The oracle (plain C, OpenMP over z) on a seeded sample of the headline scan's
+    z-slabs, all 256 frames: on every host thread, and on one.  Voxels are independent,
+    so the rate on a sample of slabs is the rate of the whole volume's work per slab."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(1003)
+    ratio = spec.cdim[2] // spec.gdim[2]
+
+    def run(n_slabs, thick):
+        # slabs of `thick` geometry slices and the colour slices over the same z range
+        starts = sorted(rng.choice(spec.gdim[2] // thick, n_slabs, replace=False) * thick)
+        vox, secs = 0, 0.0
+        for g0 in starts:
+            gz, cz = (int(g0), int(g0) + thick), (int(g0) * ratio, (int(g0) + thick) * ratio)
+            st = O.State(spec, np.float32, gz=gz, cz=cz)
+            t = time.perf_counter()
+            O.integrate(spec, frames, st)
+            secs += time.perf_counter() - t
+            vox += st.tsdf.size + st.r.size
+        return vox * frames.n / secs, secs, starts
+
+    threads = O.num_threads()
+    v_all, s_all, sl = run(3, 4)          # 12 of 512 geometry slices: 3/128 of the volume
+    res_all = {"value": v_all, "unit": "voxel updates/s", "cores": threads, "kind": "oracle",
+               "sample": f"3 seeded z-slabs of 4 geometry / {4 * ratio} colour slices at "
+                         f"geometry z {[int(s) for s in sl]} (3/128 of the volume), all "
+                         f"{frames.n} frames, {s_all:.1f} s on {threads} threads; plain C "
+                         "oracle, OpenMP over z"}
+    log(f"cpu oracle: {v_all:.4g} voxel updates/s on {threads} threads ({s_all:.1f} s)")
+    O.set_num_threads(1)
+    try:
+        v_one, s_one, sl = run(1, 1)      # 1 of 512 geometry slices: 1/512 of the volume
+    finally:
+        O.set_num_threads(threads)
+    res_one = {"value": v_one, "unit": "voxel updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"1 seeded z-slab of 1 geometry / {ratio} colour slices at geometry "
+                         f"z {int(sl[0])} (1/512 of the volume), all {frames.n} frames, "
+                         f"{s_one:.1f} s on one thread"}
+    log(f"cpu oracle: {v_one:.4g} voxel updates/s on 1 thread ({s_one:.1f} s)")
+    return res_all, res_one
 
 
 if __name__ == "__main__":

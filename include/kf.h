@@ -150,13 +150,14 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
 /*
  * kf_integrate_batch (without a graph) that also records start_events[q] and
  * end_events[q] (hipEvent_t handles created by the caller) on `stream` immediately before
- * the geometry and after the colour integration launch of pass q, for q < n_events;
- * n_events must be at least the number of passes.  For measuring the integration kernels
- * alone.
+ * the geometry and after the colour integration launch of pass q, for q < n_events, and,
+ * when mid_events is not NULL, mid_events[q] between the two launches; n_events must be
+ * at least the number of passes.  For measuring the integration kernels alone.
  */
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
                                    int32_t frames_per_pass, void* const* start_events,
-                                   void* const* end_events, int32_t n_events, void* stream);
+                                   void* const* mid_events, void* const* end_events,
+                                   int32_t n_events, void* stream);
 
 /*
  * Byte accounting for kf_integrate_batch with the same arguments: performs the same
@@ -261,7 +262,7 @@ kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capaci
                           void* stream);
 
 /*
- * Texture-map sizes and their place in an atlas image (Sec. IV.C: Eq. 11-12 and the
+ * Texture-map sizes and their place in an atlas image (Sec. IV.D: Eq. 11-12 and the
  * merging of the maps into one image).  Host-only, no device work.
  *   tri:   host float32 [n_tri][3][3], the world vertices (V1, V2, V3) of each triangle;
  *          V1 maps to the map's top-left texel, V2 to its top-right, V3 to its bottom-left.
@@ -279,7 +280,7 @@ kf_status kf_texture_layout(int32_t n_tri, const float* tri, double size_pixel,
                             int32_t atlas_height, int32_t* rects, int32_t* atlas_width);
 
 /*
- * Texel colours of every triangle's texture map from the colour volume (Sec. IV.C,
+ * Texel colours of every triangle's texture map from the colour volume (Sec. IV.D,
  * Eq. 13-14).  Texel (i, j) of the w x h map of triangle n (i < w, j < h) is the world
  * point V1 + i (V2 - V1) / (w - 1) + j (V3 - V1) / (h - 1), coloured by trilinear
  * interpolation of the colour volume (zero unless the point lies between the first and

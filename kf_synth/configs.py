@@ -67,7 +67,7 @@ def kinect_triangles(n_tri: int = 8192, edge_px: int = 16, n_frames: int = 300,
     ground), seen from the first n_frames scan poses, inside the volume's box: a
     simplified model of a few thousand polygons.  At the default sizes the maps hold
     about 20 M texels (a 4096-row atlas about 7400 texels wide).  The texel size is the footprint of one HD pixel at the scan distance
-    (0.8 m / f_hd, Sec. IV.C: set by the HD camera's resolution and the scanning distance).
+    (0.8 m / f_hd, Sec. IV.D: set by the HD camera's resolution and the scanning distance).
     Returns (float32 [n_tri, 3, 3] triangles, size_pixel in metres)."""
     rng = np.random.default_rng(scene_seed)      # the scene and poses of kinect(seed=1002)
     sc = random_scene(rng, size, 3, 2)

@@ -1,6 +1,6 @@
 /*
  * Oracle for the volumetric integration of arXiv 1602.06645 (Sec. III, Sec. IV.A-B), the
- * ray casting of its volumes and the per-polygon texture maps of Sec. IV.C (Eq. 11-14).
+ * ray casting of its volumes and the per-polygon texture maps of Sec. IV.D (Eq. 11-14).
  *
  * TEST INFRASTRUCTURE ONLY: a plain CPU implementation used by the tests, the smoke
  * check and the benchmark's CPU-baseline leg.  The product library never links or calls
@@ -18,6 +18,9 @@
 #include <string.h>
 
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* Threads of the OpenMP loops from now on (timing on a given number of cores). */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* ---- per-frame constants, double precision (Eq. 3 and Eq. 5 folded into affine maps) */
 

@@ -3,7 +3,7 @@
  * with High Quality Textures" (arXiv 1602.06645): the TSDF geometry volume of Sec. III
  * and the asymmetric colour volume of Sec. IV.B (Eq. 5-10) with the depth-to-HD-RGB
  * mapping of Sec. IV.A (Eq. 1-4), plus the adjoint of the colour update; ray casting of
- * the two volumes (Sec. III rendering); the per-polygon texture maps of Sec. IV.C
+ * the two volumes (Sec. III rendering); the per-polygon texture maps of Sec. IV.D
  * (Eq. 11-14) and their column-wise atlas.
  *
  * TEST INFRASTRUCTURE ONLY.  This is a plain, slow CPU implementation that the test
@@ -73,6 +73,7 @@ void or_frame_consts(const or_volume* vol, const or_frames* fr, int frame, or_fc
 
 /* Threads the OpenMP loops of this library use. */
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 /*
  * Forward integration in FP32 (or_integrate_f32) or FP64 (or_integrate_f64).
@@ -152,7 +153,7 @@ void or_raycast_f64(const or_volume* vol, const float* tsdf, const float* wg, co
                     float* normal, float* colour);
 
 /*
- * Per-polygon texture maps and their atlas (Sec. IV.C, Eq. 11-14 and the merging scheme).
+ * Per-polygon texture maps and their atlas (Sec. IV.D, Eq. 11-14 and the merging scheme).
  * tri: [n][3][3] world vertices (V1, V2, V3) of each triangle.  Layout (double, host):
  * w = max(2, ceil(|V1V2| / size_pixel)), h = max(2, ceil(|V1V3| / size_pixel)); the maps
  * are placed down a column of an atlas of atlas_height texels, top to bottom, and a new

@@ -1,5 +1,5 @@
 /*
- * Per-polygon texture maps (Sec. IV.C, Eq. 13-14 and the colour-volume lookup), written
+ * Per-polygon texture maps (Sec. IV.D, Eq. 13-14 and the colour-volume lookup), written
  * once and included twice by kf_oracle.c (REAL = float, the parity precision; REAL =
  * double).  TEST INFRASTRUCTURE ONLY.
  *

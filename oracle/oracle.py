@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU-bas
 leg use this module to compute the reference results of the volumetric integration of
 arXiv 1602.06645 (Sec. III TSDF volume; Sec. IV.B colour volume, Eq. 5-10; Sec. IV.A
 depth-to-HD mapping, Eq. 1-4), the ray casting of the two volumes and the per-polygon
-texture maps of Sec. IV.C (Eq. 11-14).  The product library never imports it.
+texture maps of Sec. IV.D (Eq. 11-14).  The product library never imports it.
 """
 from __future__ import annotations
 
@@ -154,6 +154,14 @@ def num_threads() -> int:
     return int(L.or_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops for the following calls."""
+    L = lib()
+    L.or_set_num_threads.argtypes = [C.c_int]
+    L.or_set_num_threads.restype = None
+    L.or_set_num_threads(int(n))
+
+
 def frame_consts(vol, fr, frame: int) -> dict:
     keep: list = []
     out = _FC64()
@@ -283,7 +291,7 @@ def raycast(vol, state: State, K, T_world_from_cam, width: int, height: int, del
 
 def texture_layout(tri, size_pixel: float, atlas_height: int):
     """Texture-map sizes (Eq. 11-12, rounded up, at least 2 x 2) and their column-wise
-    placement in an atlas of atlas_height texels (Sec. IV.C merging).  tri: [n, 3, 3]
+    placement in an atlas of atlas_height texels (Sec. IV.D merging).  tri: [n, 3, 3]
     world vertices (V1, V2, V3).  Returns (rects int32 [n, 4] = x, y, w, h; atlas width),
     or raises ValueError when a map does not fit."""
     t = _c(tri, np.float32).reshape(-1, 9)

@@ -50,7 +50,8 @@ SIGNATURES = {
     "kf_integrate_batch": (C.c_int, [C.POINTER(Scene), _I, _I, _I, _P]),
     "kf_integrate_batch_counted": (C.c_int, [C.POINTER(Scene), _I, _I, _P, _P]),
     "kf_integrate_batch_timed": (C.c_int, [C.POINTER(Scene), _I, _I, C.POINTER(C.c_void_p),
-                                           C.POINTER(C.c_void_p), _I, _P]),
+                                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _I,
+                                           _P]),
     "kf_debug_status": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P, _P, _P]),
     "kf_integrate_backward": (C.c_int, [C.POINTER(VolumeDesc), _P, _I, _P, _P, _I, _I, _I, _I,
                                         _P, _P, _P, _P, _P, _P, _P, _P, _P]),

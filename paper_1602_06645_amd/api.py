@@ -41,6 +41,20 @@ def _dev(t: torch.Tensor, dtype, name: str, ndim: int | None = None) -> torch.Te
     return t
 
 
+def _rgb(rgb, ndim: int, name: str = "rgb") -> torch.Tensor:
+    """An HD image (ndim 3: [CH,CW,3]) or a stack of them (ndim 4: [n,CH,CW,3]): three
+    interleaved channels per pixel, checked before the device so that no other layout
+    (one or four channels, channel-first) ever reaches a kernel."""
+    if not isinstance(rgb, torch.Tensor):
+        raise ValueError(f"{name} must be a tensor")
+    if rgb.dim() != ndim or rgb.shape[-1] != 3:
+        want = "[CH,CW,3]" if ndim == 3 else "[n,CH,CW,3]"
+        raise ValueError(f"{name} must be {want} with 3 interleaved channels, got shape "
+                         f"{tuple(rgb.shape)}")
+    _rgb_fmt(rgb)
+    return _dev(rgb, rgb.dtype, name, ndim)
+
+
 def _rgb_fmt(rgb: torch.Tensor) -> int:
     if rgb.dtype == torch.uint8:
         return L.KF_RGB8
@@ -104,8 +118,8 @@ class Volume:
     def integrate(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam,
                   trunc: float, w_max: float) -> None:
         """One frame: depth [H,W] float32 metres, rgb [CH,CW,3] uint8 or float32."""
+        rgb = _rgb(rgb, 3)
         depth = _dev(depth, torch.float32, "depth", 2)
-        rgb = _dev(rgb, rgb.dtype, "rgb", 3)
         Kd, Kr = _mat(K_d, (3, 3)), _mat(K_rgb, (3, 3))
         Trd, Twc = _mat(T_rgb_from_d, (4, 4)), _mat(T_world_from_cam, (4, 4))
         L.check(L.load().kf_integrate(
@@ -174,8 +188,8 @@ class Volume:
 
     def status(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
         """Per-voxel outcome codes of one frame (no update): (geometry, colour) uint8."""
+        rgb = _rgb(rgb, 3)
         depth = _dev(depth, torch.float32, "depth", 2)
-        rgb = _dev(rgb, rgb.dtype, "rgb", 3)
         gs = torch.empty(self.tsdf.numel(), dtype=torch.uint8, device=self.tsdf.device)
         cs = torch.empty(self.r.numel(), dtype=torch.uint8, device=self.r.device)
         Kd, Kr = _mat(K_d, (3, 3)), _mat(K_rgb, (3, 3))
@@ -206,8 +220,8 @@ class Scan:
     frame (T_world_from_cam [n,4,4]); K_d, K_rgb 3x3; T_rgb_from_d 4x4."""
 
     def __init__(self, depth, rgb, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc, w_max):
+        self.rgb = _rgb(rgb, 4)
         self.depth = _dev(depth, torch.float32, "depth", 3)
-        self.rgb = _dev(rgb, rgb.dtype, "rgb", 4)
         self.fmt = _rgb_fmt(self.rgb)
         n = self.depth.shape[0]
         if self.rgb.shape[0] != n:
@@ -254,16 +268,21 @@ def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) ->
 
 
 def integrate_batch_timed(pairs, frames_per_pass: int, events) -> None:
-    """integrate_batch that records each (start, end) pair of `events` (torch.cuda.Event,
-    enable_timing=True) around the integration launch of one pass, in order."""
-    for s, e in events:          # torch creates the HIP event on first record
-        s.record()
-        e.record()
-    starts = (C.c_void_p * len(events))(*[s.cuda_event for s, _ in events])
-    ends = (C.c_void_p * len(events))(*[e.cuda_event for _, e in events])
+    """integrate_batch that records each pair (start, end) or triple (start, mid, end) of
+    `events` (torch.cuda.Event, enable_timing=True) around the integration launches of
+    one pass, in order; mid is recorded between the geometry and the colour launch."""
+    for ev in events:             # torch creates the HIP event on first record
+        for e in ev:
+            e.record()
+    n = len(events)
+    starts = (C.c_void_p * n)(*[ev[0].cuda_event for ev in events])
+    ends = (C.c_void_p * n)(*[ev[-1].cuda_event for ev in events])
+    mids = None
+    if n and len(events[0]) == 3:
+        mids = (C.c_void_p * n)(*[ev[1].cuda_event for ev in events])
     arr = _scenes(pairs)
     L.check(L.load().kf_integrate_batch_timed(arr, len(pairs), int(frames_per_pass), starts,
-                                              ends, len(events), _stream()))
+                                              mids, ends, n, _stream()))
 
 
 def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:

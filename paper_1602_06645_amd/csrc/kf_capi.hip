@@ -487,7 +487,9 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
 // Fill the host image for device base address `dev` (the frames point at their pyramids).
 void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
 {
-    t->host.assign(t->pyr_off, 0);   // the pyramids and weight maps are written on the device
+    // the tables and counters; the live lists, pyramids and weight maps are written on
+    // the device (the counters are cleared there too)
+    t->host.assign(t->live_off, 0);
     std::vector<kf::FrameConsts> frames = p.frames;
     for (size_t f = 0; f < frames.size(); ++f) {
         frames[f].pyr = (float2*)(dev + t->frame_pyr_off[f]);
@@ -513,6 +515,7 @@ kf_status resident_grid(int mode, uint32_t grid[2])
 // Caller events recorded around the integration launch of each pass (may be empty).
 struct PassEvents {
     void* const* start = nullptr;
+    void* const* mid = nullptr;       // may be NULL
     void* const* end = nullptr;
     int32_t n = 0;
 };
@@ -560,6 +563,7 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         const bool timed = (int32_t)q < ev.n;
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.start[q], stream), "hipEventRecord");
         KF_HIP(kf::launch_integrate(mode, kf::KIND_GEOM, a, grid[0], stream), "integrate launch");
+        if (timed && ev.mid) KF_HIP(hipEventRecord((hipEvent_t)ev.mid[q], stream), "hipEventRecord");
         KF_HIP(kf::launch_integrate(mode, kf::KIND_COLOUR, a, grid[1], stream), "integrate launch");
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.end[q], stream), "hipEventRecord");
     }
@@ -864,13 +868,16 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t f
 
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
                                    int32_t frames_per_pass, void* const* start_events,
-                                   void* const* end_events, int32_t n_events, void* stream)
+                                   void* const* mid_events, void* const* end_events,
+                                   int32_t n_events, void* stream)
 {
     if (n_events < 1 || !start_events || !end_events) return fail(KF_E_ARG, "events missing");
     for (int32_t q = 0; q < n_events; ++q)
-        if (!start_events[q] || !end_events[q]) return fail(KF_E_ARG, "an event is NULL");
+        if (!start_events[q] || !end_events[q] || (mid_events && !mid_events[q]))
+            return fail(KF_E_ARG, "an event is NULL");
     PassEvents ev;
     ev.start = start_events;
+    ev.mid = mid_events;
     ev.end = end_events;
     ev.n = n_events;
     return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,

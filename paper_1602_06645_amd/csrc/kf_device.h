@@ -134,7 +134,7 @@ struct BackwardArgs {
 
 // 1.0f / z, correctly rounded, in fewer instructions than the IEEE division: the hardware
 // reciprocal refined by one Newton step with an FMA residual, r + r (1 - z r), equals the
-// IEEE quotient for every normal z with |z| <= 2^126; zero, subnormal, larger, infinite
+// IEEE quotient for every normal z with |z| <= 2^125; zero, subnormal, larger, infinite
 // and NaN z take the IEEE division (a branch no lane takes for the camera depths of a
 // scene).  The equality is checked over all 2^32 inputs by the test suite on gfx950.
 __device__ __forceinline__ bool recip_exact(float z)

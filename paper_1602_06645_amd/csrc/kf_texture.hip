@@ -1,4 +1,4 @@
-// Per-polygon texture maps from the colour volume for gfx950 (Sec. IV.C, Eq. 13-14 and
+// Per-polygon texture maps from the colour volume for gfx950 (Sec. IV.D, Eq. 13-14 and
 // the colour-volume lookup).  Texel (i, j) of the w x h map of triangle (V1, V2, V3), placed
 // at (x, y) in the atlas, is the world point V1 + i (V2 - V1)/(w - 1) + j (V3 - V1)/(h - 1)
 // (i then j, each an fma) coloured by trilinear interpolation of the colour volume, in

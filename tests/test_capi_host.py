@@ -172,12 +172,13 @@ def test_timed_batch_rejects_bad_arguments():
         sc[0].T_rgb_from_d, sc[0].T_world_from_cam = T.ctypes.data, poses.ctypes.data
         sc[0].trunc_m, sc[0].w_max = 0.01, 128.0
         ev = (C.c_void_p * 3)(0x10, 0x20, 0x30)
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, 3, None) == L.KF_E_ARG
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, 0, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, None, ev, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, None, ev, 0, None) == L.KF_E_ARG
         holey = (C.c_void_p * 3)(0x10, None, 0x30)
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, holey, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, None, holey, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, holey, ev, 3, None) == L.KF_E_ARG
         # K = 1 makes three passes; two events are too few
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, 2, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, ev, 2, None) == L.KF_E_ARG
         assert b"below the number of passes" in lib.kf_last_error()
     finally:
         lib.kf_volume_destroy(h)
@@ -338,3 +339,23 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         L.load()
+
+
+@pytest.mark.parametrize("shape", [(2, 24, 32, 1), (2, 24, 32, 4), (2, 3, 24, 32), (2, 24, 32)])
+def test_binding_rejects_rgb_without_three_interleaved_channels(shape):
+    """The kernels read 3 interleaved channels per HD pixel: any other layout (1 or 4
+    channels, channel-first, a missing channel axis) is refused by the binding before a
+    pointer reaches the library."""
+    import torch
+    from paper_1602_06645_amd import api
+    depth = torch.zeros((2, 12, 16), dtype=torch.float32)
+    rgb = torch.zeros(shape, dtype=torch.uint8)
+    eye = np.eye(3)
+    with pytest.raises(ValueError, match="3 interleaved channels"):
+        api.Scan(depth, rgb, eye, eye, np.eye(4), np.stack([np.eye(4)] * 2), 0.01, 64)
+    with pytest.raises(ValueError, match="3 interleaved channels"):
+        api._rgb(rgb[0], 3)
+    # the right layout gets past the shape check (and then needs a device tensor)
+    with pytest.raises(ValueError, match="CUDA/HIP tensor"):
+        api.Scan(depth, torch.zeros((2, 24, 32, 3), dtype=torch.uint8), eye, eye, np.eye(4),
+                 np.stack([np.eye(4)] * 2), 0.01, 64)

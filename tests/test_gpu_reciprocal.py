@@ -1,5 +1,5 @@
 """The library's reciprocal (hardware reciprocal plus one Newton step, the IEEE division
-outside the normal range up to 2^126) equals 1.0f / z bit for bit for every one of the
+outside the normal range up to 2^125) equals 1.0f / z bit for bit for every one of the
 2^32 single-precision inputs (needs gfx950).  The projections of the integration, the
 colour update and the adjoint rely on it for bit-exactness with the oracle."""
 import ctypes as C

@@ -1,6 +1,6 @@
 """Pins of the oracle's per-polygon texture maps and atlas layout (CPU only).
 
-Texture generation (Sec. IV.C, Eq. 11-14) is checked against results fixed by geometry and
+Texture generation (Sec. IV.D, Eq. 11-14) is checked against results fixed by geometry and
 by an independent interpolation routine rather than by its own formulas:
 * map sizes of triangles with exactly representable edge lengths (Eq. 11-12, rounded up,
   at least 2);
@@ -225,7 +225,7 @@ def test_untouched_texels_and_f32_vs_f64(oracle):
     np.testing.assert_allclose(a32[mask], a64[mask], rtol=0, atol=1e-5)
 
 
-# ---- atlas layout (Sec. IV.C merging)
+# ---- atlas layout (Sec. IV.D merging)
 
 def check_layout(rects, width, H):
     x, y, w, h = rects.T.astype(np.int64)
