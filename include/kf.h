@@ -148,6 +148,25 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
                              int32_t frames_per_pass, int32_t use_graph, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): kf_integrate_batch without a graph, with the
+ * same arguments and the same result, whose workspace (frame constants, per-pass tables,
+ * queue counters, live lists, depth pyramids and colour weight maps) lives in a fixed
+ * 64 MiB device array inside the library instead of the stream-ordered allocator.  Calls
+ * nothing that allocates device or pinned host memory: the tables reach the device in
+ * kernel arguments, the counters are cleared by a kernel.  The array exists once per GPU
+ * (held until the process ends) and every call on that GPU uses it, so calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by the caller; a
+ * call's workspace is re-initialised by the call itself.  KF_E_RANGE if the batch needs
+ * more than 64 MiB of workspace: about 32 bytes per brick of the largest pass's volumes
+ * (a brick is 16 x 4 x 8 geometry or 8 x 8 x 8 colour voxels) plus about 1.3 MB per
+ * 640 x 480 depth frame of the batch (a 256^3 / 512^3 pair of volumes takes 9.4 MB plus
+ * its frames; a 512^3 / 1024^3 pair does not fit).  Other errors as kf_integrate_batch.
+ */
+kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
+                                     int32_t frames_per_pass, void* stream);
+
+/*
  * kf_integrate_batch (without a graph) that also records start_events[q] and
  * end_events[q] (hipEvent_t handles created by the caller) on `stream` immediately before
  * the geometry and after the colour integration launch of pass q, for q < n_events, and,

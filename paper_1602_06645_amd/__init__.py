@@ -4,6 +4,7 @@ with High Quality Textures" (arXiv 1602.06645), with batched/fused and different
 forms, ray casting of the volumes and per-polygon texture maps (Sec. IV.D).  The work runs
 in libkfvol.so (HIP for gfx950, C ABI in include/kf.h)."""
 from .api import (Scan, Volume, integrate_backward, integrate_batch,  # noqa: F401
-                  integrate_batch_counted, integrate_batch_timed, texture_layout,
+                  integrate_batch_counted, integrate_batch_noalloc, integrate_batch_timed,
+                  texture_layout,
                   volume_desc)
 from .autograd import KFColourFn, se3_exp, se3_left_jacobian  # noqa: F401

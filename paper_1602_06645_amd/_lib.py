@@ -48,6 +48,7 @@ SIGNATURES = {
     "kf_volume_destroy": (None, [_P]),
     "kf_integrate": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P]),
     "kf_integrate_batch": (C.c_int, [C.POINTER(Scene), _I, _I, _I, _P]),
+    "kf_integrate_batch_noalloc": (C.c_int, [C.POINTER(Scene), _I, _I, _P]),
     "kf_integrate_batch_counted": (C.c_int, [C.POINTER(Scene), _I, _I, _P, _P]),
     "kf_integrate_batch_timed": (C.c_int, [C.POINTER(Scene), _I, _I, C.POINTER(C.c_void_p),
                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _I,

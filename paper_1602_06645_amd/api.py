@@ -267,6 +267,14 @@ def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) ->
                                         _stream()))
 
 
+def integrate_batch_noalloc(pairs, frames_per_pass: int = 1) -> None:
+    """integrate_batch through kf_integrate_batch_noalloc: the library allocates nothing
+    (its workspace is a fixed 64 MiB device array per GPU, shared by all such calls)."""
+    arr = _scenes(pairs)
+    L.check(L.load().kf_integrate_batch_noalloc(arr, len(pairs), int(frames_per_pass),
+                                                _stream()))
+
+
 def integrate_batch_timed(pairs, frames_per_pass: int, events) -> None:
     """integrate_batch that records each pair (start, end) or triple (start, mid, end) of
     `events` (torch.cuda.Event, enable_timing=True) around the integration launches of

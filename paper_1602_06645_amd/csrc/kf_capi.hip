@@ -702,6 +702,90 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     return KF_OK;
 }
 
+// ------------------------------------------------------------ allocation-free workspace
+
+// Workspace of kf_integrate_batch_noalloc: a file-scope device array, one copy per GPU that
+// loads the library, held until the process ends.  On the host the array's name is only a
+// stand-in for the device symbol, never a device address: each GPU's copy is looked up
+// once per device with hipGetSymbolAddress (scratch_base) and that address is what the
+// launches receive.  Calls that overlap on one GPU share the array and race.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchBases {
+    std::mutex mu;
+    unsigned char* ptr[64] = {};
+};
+ScratchBases g_scratch;
+
+// Device address of the current device's scratch array (looked up on its first use).
+kf_status scratch_base(unsigned char** out)
+{
+    int device = 0;
+    KF_HIP(hipGetDevice(&device), "hipGetDevice");
+    if (device < 0 || device >= 64) return fail(KF_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch.mu);
+    if (!g_scratch.ptr[device]) {
+        void* p = nullptr;
+        KF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(KF_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch.ptr[device] = (unsigned char*)p;
+    }
+    *out = g_scratch.ptr[device];
+    return KF_OK;
+}
+
+// Host bytes carried to device memory by value in a kernel's arguments: no staging buffer,
+// no copy from host memory that must outlive the call (a captured launch keeps its
+// arguments).
+constexpr uint32_t kUploadWords = 960;
+struct UploadChunk {
+    uint32_t* dst;
+    uint32_t words;
+    uint32_t data[kUploadWords];
+};
+
+__global__ __launch_bounds__(256) void upload_kernel(UploadChunk c)
+{
+    for (uint32_t t = threadIdx.x; t < c.words; t += 256) c.dst[t] = c.data[t];
+}
+
+// Copy `bytes` (a multiple of 4) from host `src` to device `dst` in kernel arguments.
+kf_status upload(unsigned char* dst, const unsigned char* src, size_t bytes, hipStream_t stream)
+{
+    UploadChunk c;
+    for (size_t off = 0; off < bytes; off += 4 * (size_t)kUploadWords) {
+        const size_t n = bytes - off < 4 * (size_t)kUploadWords ? bytes - off : 4 * (size_t)kUploadWords;
+        c.dst = (uint32_t*)(dst + off);
+        c.words = (uint32_t)(n / 4);
+        memcpy(c.data, src + off, n);
+        hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, stream, c);
+        KF_HIP(hipGetLastError(), "upload launch");
+    }
+    return KF_OK;
+}
+
+kf_status run_batch_noalloc(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStream_t stream)
+{
+    BatchPlan plan;
+    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    if (st != KF_OK) return st;
+    if (plan.passes.empty()) return KF_OK;
+    DeviceTables t;
+    layout_tables(plan, &t);
+    if (t.bytes > kScratchBytes)
+        return fail(KF_E_RANGE, "the batch needs %zu bytes of workspace; the allocation-free "
+                                "entry point holds %zu (fewer frames per call or smaller volumes)",
+                    t.bytes, kScratchBytes);
+    uint32_t grid[2] = {0, 0};
+    if ((st = resident_grid(kf::MODE_INTEGRATE, grid)) != KF_OK) return st;
+    unsigned char* dev = nullptr;
+    if ((st = scratch_base(&dev)) != KF_OK) return st;
+    fill_tables(plan, dev, &t);
+    if ((st = upload(dev, t.host.data(), t.host.size(), stream)) != KF_OK) return st;
+    return enqueue_passes(plan, t, dev, kf::MODE_INTEGRATE, nullptr, grid, stream);
+}
+
 }  // namespace
 
 // =========================================================================== C ABI
@@ -864,6 +948,12 @@ kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t f
     }
     return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
                      (hipStream_t)stream);
+}
+
+kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
+                                     int32_t frames_per_pass, void* stream)
+{
+    return run_batch_noalloc(scenes, n_scenes, frames_per_pass, (hipStream_t)stream);
 }
 
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,

@@ -24,6 +24,8 @@ using std::min;
 #define __shared__ static thread_local
 #define __constant__
 #define address_space(n)
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) ((const void*)&(x))
 
 struct dim3 {
     unsigned x, y, z;
@@ -231,6 +233,8 @@ hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
 hipError_t hipGraphExecDestroy(hipGraphExec_t e);
 hipError_t hipGetLastError();
+// the emulated device is the host: a device symbol's address is its host address
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) { *p = const_cast<void*>(sym); return hipSuccess; }
 const char* hipGetErrorString(hipError_t e);
 
 // kernel launch: run the grid now (stream order = program order)

@@ -55,10 +55,13 @@ def scene(vol, fr, keep):
     return s
 
 
-def forward_case(pairs, K, specs=None):
+def forward_case(pairs, K, specs=None, noalloc=False):
     keep = []
     arr = (L.Scene * len(pairs))(*[scene(v, f, keep) for v, f in pairs])
-    check(lib.kf_integrate_batch(arr, len(pairs), K, 0, None))
+    if noalloc:
+        check(lib.kf_integrate_batch_noalloc(arr, len(pairs), K, None))
+    else:
+        check(lib.kf_integrate_batch(arr, len(pairs), K, 0, None))
     worst = 0
     for (v, fr), spec in zip(pairs, specs or SPECS):
         st = O.State(spec, np.float32)
@@ -258,6 +261,13 @@ fr40 = fr40.numpy()
 out["wide_pass_mismatches"] = forward_case([(Vol(spec6), fr6), (Vol(spec40), fr40)], 36,
                                            [spec6, spec40])
 tick("wide passes")
+# the allocation-free entry point (workspace in the library's fixed array): the three-scan
+# batch, then a smaller one reusing the array
+out["noalloc_mismatches"] = (
+    forward_case([(Vol(spec6), fr6), (Vol(spec32), fr32.as_float_rgb()), (Vol(spec_odd), fr32)], 8,
+                 noalloc=True)
+    + forward_case([(Vol(spec6), fr6)], 4, [spec6], noalloc=True))
+tick("no-alloc")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
 # nearest-pixel HD sampling: an 8-bit scan and a float one on the odd volume

@@ -5,7 +5,7 @@ without a GPU that the kernels' logic equals the oracle (bit for bit in the forw
 the adjoint tolerance in the backward) and touches no memory outside its buffers: two
 scans and an odd-sized volume (partial bricks and culling chunks) in one batch (RGB8 and
 float images, 6 and 32 frames, 8 frames per pass), passes of more than 32 frames (40
-frames at 36 per pass), the
+frames at 36 per pass), the allocation-free entry point on two batches in a row, the
 per-voxel outcome codes of every frame of a scan, the ray cast of an integrated volume, and
 the adjoint over 6 and 32 frames (a
 live frame in bit 31 of a brick's frame mask)."""
@@ -47,6 +47,7 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     res = json.loads(r.stdout.split("JSON:", 1)[1])
     assert res["forward_mismatches"] == 0
     assert res["wide_pass_mismatches"] == 0
+    assert res["noalloc_mismatches"] == 0
     assert res["status_mismatches"] == 0
     assert res["raycast_mismatches"] == 0
     assert res["texture_mismatches"] == 0
