@@ -10,14 +10,21 @@
 // chains the sample's spatial derivative through the pinhole projection and the se(3)
 // left perturbation dq/d(rho, phi) = [I | -[q]x].
 //
-// The colour bricks of the forward (8 x 8 x 8, one wave each) are culled frame by frame
-// exactly like the forward's (a culled frame cannot update any voxel of the brick, so
-// its alpha is 0).  Persistent waves take the live bricks; each voxel replays the forward
-// decisions of its live frames (the same single-precision sequence as the forward, so the
-// same frames update it), keeps alpha_n in an LDS history private to the lane, and a
-// reverse sweep scatters the image gradient with float atomics and accumulates the
-// extrinsic gradient in double.  Each brick writes its own extrinsic partial; a last
-// kernel sums them in a fixed order, so d_xi is deterministic.
+// The colour bricks of the forward (8 x 8 x 8) are culled frame by frame exactly like the
+// forward's (a culled frame cannot update any voxel of the brick, so its alpha is 0).  A
+// persistent workgroup of 512 threads takes one live brick at a time, one voxel per
+// thread: each voxel replays the forward decisions of its live frames (the same
+// single-precision sequence as the forward, so the same frames update it) and keeps
+// alpha_n in LDS; the brick then sweeps the frames backwards together.  Each update's
+// image gradient is written as a record (pixel, bilinear fractions, g beta) into the
+// brick's segment for that frame; a segment lists the HD tiles its cells can touch
+// (from the brick's projected corners).  Three small launches sort the segments by
+// (frame, tile), and one workgroup per (frame, tile) adds its records in LDS and adds
+// the tile into the image gradient: no global atomics per update.  A brick whose records
+// do not fit the record buffer, or whose footprint in a frame is larger than 2 x 2 tiles
+// (or crosses the HD camera plane), scatters that frame's updates with float atomics
+// instead (same values, another order of addition).  The extrinsic gradient is summed
+// per brick in double and the bricks' partials in a fixed order (deterministic d_xi).
 #include <hip/hip_runtime.h>
 
 #include "kf_cull.h"
@@ -27,6 +34,9 @@
 namespace kf {
 
 constexpr int BWD_MAX_FRAMES = 64;
+constexpr int BWD_BLOCK = CBX * CBY * ZS;      // one colour brick, one voxel per thread
+constexpr int BWD_WAVES = BWD_BLOCK / WAVE;    // one wave per z slice of the brick
+static_assert(BWD_WAVES == ZS && CBX * CBY == WAVE, "a wave is one z slice of a brick");
 
 namespace {
 
@@ -96,6 +106,60 @@ __device__ __forceinline__ double wave_sum_d(double x)
     return x;
 }
 
+// Rank of this lane among the set lanes of `ballot` below it.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long ballot)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+}
+
+// HD tiles that the bilinear cells of a brick's voxels can touch in one frame: the
+// brick's box lies in front of the HD camera and its image lies inside the hull of its
+// 8 projected corners (projected in double, widened by a pixel for the single-precision
+// rounding of the per-voxel projection, and by the cell's second pixel), clamped to the
+// image.  Returns the first tile on each axis (t[0] = x, t[1] = y) and whether the range
+// spans a second tile (t[2] = x, t[3] = y); false when a corner is not in front of the
+// camera, the range spans more than 2 tiles on an axis, or no pixel of the image (the
+// frame's updates are then scattered directly).
+__device__ inline bool brick_tiles(const FrameConsts& c, int i0, int i1, int j0, int j1, int k0,
+                                   int k1, int* t)
+{
+    double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    for (int q = 0; q < 8; ++q) {
+        const double fi = (q & 1) ? i1 : i0, fj = (q & 2) ? j1 : j0, fk = (q & 4) ? k1 : k0;
+        const double qx = (double)c.Ah[0] * fi + (double)c.Ah[1] * fj + (double)c.Ah[2] * fk + c.bh[0];
+        const double qy = (double)c.Ah[3] * fi + (double)c.Ah[4] * fj + (double)c.Ah[5] * fk + c.bh[1];
+        const double qz = (double)c.Ah[6] * fi + (double)c.Ah[7] * fj + (double)c.Ah[8] * fk + c.bh[2];
+        if (!(qz > 1e-6)) return false;
+        const double x = (double)c.fxr * qx / qz + c.cxr, y = (double)c.fyr * qy / qz + c.cyr;
+        xmin = fmin(xmin, x);
+        xmax = fmax(xmax, x);
+        ymin = fmin(ymin, y);
+        ymax = fmax(ymax, y);
+    }
+    const double lo_x = fmax(floor(xmin) - 1.0, 0.0), hi_x = fmin(floor(xmax) + 2.0, (double)(c.cw - 1));
+    const double lo_y = fmax(floor(ymin) - 1.0, 0.0), hi_y = fmin(floor(ymax) + 2.0, (double)(c.ch - 1));
+    if (!(lo_x <= hi_x) || !(lo_y <= hi_y)) return false;
+    const int tx0 = (int)lo_x / BWD_TILE_W, tx1 = (int)hi_x / BWD_TILE_W;
+    const int ty0 = (int)lo_y / BWD_TILE_H, ty1 = (int)hi_y / BWD_TILE_H;
+    t[0] = tx0;
+    t[1] = ty0;
+    t[2] = tx1 - tx0;
+    t[3] = ty1 - ty0;
+    return tx1 - tx0 <= 1 && ty1 - ty0 <= 1;
+}
+
+// A segment (uint4): first record, record count, frame | x span << 8 | y span << 9, and
+// first tile x | first tile y << 16.
+__device__ __forceinline__ void segment_tiles(uint4 sg, int* f, int* tx0, int* tx1, int* ty0, int* ty1)
+{
+    *f = (int)(sg.z & 0xFFu);
+    *tx0 = (int)(sg.w & 0xFFFFu);
+    *ty0 = (int)(sg.w >> 16);
+    *tx1 = *tx0 + (int)((sg.z >> 8) & 1u);
+    *ty1 = *ty0 + (int)((sg.z >> 9) & 1u);
+}
+
 }  // namespace
 
 // One block per culling chunk of CHUNK^3 colour bricks: the first wave tests the chunk's
@@ -161,159 +225,394 @@ __global__ __launch_bounds__(BLOCK) void backward_cull_kernel(BackwardArgs a)
     for (uint32_t e = threadIdx.x; e < s_n; e += BLOCK) a.live[s_base + e] = s_ent[e];
 }
 
-// HIST: LDS floats per lane for the alpha history (at least the frames of the call).
+// HIST: frames of the alpha history (at least the frames of the call).
 // POSE: also the per-frame extrinsic partials of each brick (for the depth-pose adjoint),
-// summed per frame in the wave's LDS and written as one row per brick.
+// summed per frame in LDS and written as one row per brick.
 template <int HIST, bool POSE>
-__global__ __launch_bounds__(BLOCK) void backward_kernel(BackwardArgs a)
+__global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
 {
-    __shared__ float s_alpha[BLOCK * HIST];   // lane t of wave w: [w][f][t]
-    __shared__ double s_pose[POSE ? (BLOCK / WAVE) * HIST * 6 : 1];
-    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-    float* hist = s_alpha + wave * WAVE * HIST + lane;
-    double* facc = s_pose + (POSE ? wave * HIST * 6 : 0);
+    __shared__ float s_alpha[HIST * BWD_BLOCK];         // [rank][thread]
+    __shared__ uint32_t s_wcnt[BWD_WAVES][HIST];        // records per wave and rank, then
+                                                        // the wave's offset in the segment
+    __shared__ uint32_t s_seg[HIST];                    // first record of each rank's segment
+    __shared__ uint32_t s_cnt[HIST];                    // records of each rank's segment
+    __shared__ int32_t s_tiles[HIST][4];                // tiles of each rank's segment (brick_tiles)
+    __shared__ double s_xi[BWD_WAVES][6];
+    __shared__ double s_pose[POSE ? HIST * 6 : 1];      // [frame][6]
+    __shared__ double s_pw[POSE ? 2 : 1][BWD_WAVES][6]; // per-wave sums of one frame (two
+                                                        // frames alternate)
+    __shared__ uint32_t s_ticket;
+    __shared__ unsigned long long s_direct;             // ranks scattered with atomics
+
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wave = t / WAVE;
+    float* hist = s_alpha + t;
     const size_t nvox = (size_t)a.cdim[0] * (size_t)a.cdim[1] * (size_t)a.cdim[2];
     const uint32_t n_live = *a.n_live;
     const const_ptr<FrameConsts> frames = as_const(a.frames);
     for (;;) {
-        const uint32_t e = wave_ticket(a.queue);
+        if (t == 0) s_ticket = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t e = first_lane_u32(s_ticket);
         if (e >= n_live) break;
         const uint4 ent = a.live[e];
         const uint32_t li = first_lane_u32(ent.x);
         const unsigned long long mask = ((unsigned long long)first_lane_u32(ent.z) << 32) |
                                         (unsigned long long)first_lane_u32(ent.y);
+        const int n_r = __builtin_popcountll(mask);
         const int bx = (int)(li % (uint32_t)a.cbricks[0]);
         const int by = (int)((li / (uint32_t)a.cbricks[0]) % (uint32_t)a.cbricks[1]);
         const int bz = (int)(li / ((uint32_t)a.cbricks[0] * (uint32_t)a.cbricks[1]));
-        const int i = bx * CBX + lane % CBX, j = by * CBY + lane / CBX, k0 = bz * ZS;
-        double xi[6] = {0, 0, 0, 0, 0, 0};
-        if constexpr (POSE) {
-            for (int q = lane; q < a.n_frames * 6; q += WAVE) facc[q] = 0.0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int i = bx * CBX + lane % CBX, j = by * CBY + lane / CBX, k = bz * ZS + wave;
+        const bool inside = i < a.cdim[0] && j < a.cdim[1] && k < a.cdim[2];
+        const float fi = (float)i, fj = (float)j, fk = (float)k;
+        const size_t idx = ((size_t)k * (size_t)a.cdim[1] + (size_t)j) * (size_t)a.cdim[0] + (size_t)i;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        if (inside) {
+            g0 = a.grad[idx];
+            g1 = a.grad[nvox + idx];
+            g2 = a.grad[2 * nvox + idx];
         }
-        if (i < a.cdim[0] && j < a.cdim[1]) {
-            const float fi = (float)i, fj = (float)j;
-            const int kn = min(ZS, a.cdim[2] - k0);
-            for (int kk = 0; kk < kn; ++kk) {
-                const int k = k0 + kk;
-                const float fk = (float)k;
-                const size_t idx = ((size_t)k * (size_t)a.cdim[1] + (size_t)j) * (size_t)a.cdim[0] + (size_t)i;
-                const float g0 = a.grad[idx], g1 = a.grad[nvox + idx], g2 = a.grad[2 * nvox + idx];
-                if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;
-                // forward replay over the live frames, by rank among them: first the
-                // weight-independent tests, four frames at a time with their image reads
-                // in flight together (W or 0 into the history) ...
-                int r = 0;
-                for (unsigned long long m = mask; m;) {
-                    int fr[4];
-                    bool ok[4];
+        // the frames' tile ranges (one thread per rank), and a clear per-frame pose table
+        if (t < n_r) {
+            unsigned long long m = mask;
+            for (int q = 0; q < t; ++q) m &= m - 1;
+            const int f = __builtin_ctzll(m);
+            const int i0 = bx * CBX, i1 = min(a.cdim[0], i0 + CBX) - 1;
+            const int j0 = by * CBY, j1 = min(a.cdim[1], j0 + CBY) - 1;
+            const int k0 = bz * ZS, k1 = min(a.cdim[2], k0 + ZS) - 1;
+            int tr[4] = {0, 0, 0, 0};
+            const bool binned = a.rec_cap > 0 && brick_tiles(a.frames[f], i0, i1, j0, j1, k0, k1, tr);
+            for (int q = 0; q < 4; ++q) s_tiles[t][q] = tr[q];
+            s_cnt[t] = binned ? 0u : 0xFFFFFFFFu;   // marks a direct rank until the counts
+        }
+        if constexpr (POSE)
+            for (int q = t; q < a.n_frames * 6; q += BWD_BLOCK) s_pose[q] = 0.0;
+        // forward replay over the live frames, by rank among them: first the
+        // weight-independent tests, four frames at a time with their image reads in flight
+        // together (W or 0 into the history) ...
+        const bool active = inside && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f);
+        unsigned long long upd = 0;   // bit r: rank r updates this voxel
+        if (active) {
+            int r = 0;
+            for (unsigned long long m = mask; m;) {
+                int fr[4];
+                bool ok[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ok[q] = m != 0ull;
-                        fr[q] = ok[q] ? __builtin_ctzll(m) : fr[0];
-                        m &= m - 1;
-                    }
-                    WeightFetch wf[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) wf[q] = weight_fetch(frames[fr[q]], fi, fj, fk);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (ok[q]) hist[(r + q) * WAVE] = weight_test(frames[fr[q]], wf[q], fi, fj, fk);
-                    r += 4;
+                for (int q = 0; q < 4; ++q) {
+                    ok[q] = m != 0ull;
+                    fr[q] = ok[q] ? __builtin_ctzll(m) : fr[0];
+                    m &= m - 1;
                 }
-                // ... then the gate against the running weight and alpha_n
-                float Wc = a.wc0 ? a.wc0[idx] : 0.0f;
-                int any = 0;
-                r = 0;
-                for (unsigned long long m = mask; m; m &= m - 1, ++r) {
-                    const float w = hist[r * WAVE];
-                    float alpha = 0.0f;
-                    if (w > 0.0f && w > frames[__builtin_ctzll(m)].gate * Wc) {
-                        alpha = w / (Wc + w);
-                        Wc = fmaf(w, 1.0f - Wc, Wc);
-                        any = 1;
-                    }
-                    hist[r * WAVE] = alpha;
+                WeightFetch wf[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wf[q] = weight_fetch(frames[fr[q]], fi, fj, fk);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (ok[q]) hist[(r + q) * BWD_BLOCK] = weight_test(frames[fr[q]], wf[q], fi, fj, fk);
+                r += 4;
+            }
+            // ... then the gate against the running weight and alpha_n
+            float Wc = a.wc0 ? a.wc0[idx] : 0.0f;
+            r = 0;
+            for (unsigned long long m = mask; m; m &= m - 1, ++r) {
+                const float w = hist[r * BWD_BLOCK];
+                float alpha = 0.0f;
+                if (w > 0.0f && w > frames[__builtin_ctzll(m)].gate * Wc) {
+                    alpha = w / (Wc + w);
+                    Wc = fmaf(w, 1.0f - Wc, Wc);
+                    upd |= 1ull << r;
                 }
-                if (!any) continue;
-                // reverse sweep
-                float tail = 1.0f;
-                for (unsigned long long m = mask; m; m &= ~(1ull << (63 - __builtin_clzll(m)))) {
-                    const int f = 63 - __builtin_clzll(m);
-                    --r;
-                    const float alpha = hist[r * WAVE];
-                    if (alpha == 0.0f) continue;
-                    const float beta = alpha * tail;
-                    tail *= 1.0f - alpha;
-                    const auto& c = frames[f];
-                    const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
-                    const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
-                    const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
-                    const float iqz = recip(qz);
-                    const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
-                    const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
-                    const float x0 = floorf(xh), y0 = floorf(yh);
-                    const float ax = xh - x0, ay = yh - y0;
-                    const int cell = ((int)y0 * c.cw + (int)x0) * 3;
-                    const int row = c.cw * 3;
-                    const float* img = (const float*)c.rgb;
+                hist[r * BWD_BLOCK] = alpha;
+            }
+        }
+        __syncthreads();   // s_tiles, s_cnt (direct marks) and s_pose are set
+        // records per wave and rank (direct ranks have none)
+        for (int r = 0; r < n_r; ++r) {
+            const unsigned long long b = __ballot((upd >> r) & 1ull);
+            if (lane == 0) s_wcnt[wave][r] = s_cnt[r] == 0xFFFFFFFFu ? 0u : (uint32_t)__builtin_popcountll(b);
+        }
+        __syncthreads();
+        // segments: per rank the waves' offsets and the count (wave 0, one lane per rank),
+        // then one reservation for the brick's records
+        if (wave == 0) {
+            uint32_t cnt = 0;
+            const bool direct = lane < n_r && s_cnt[lane] == 0xFFFFFFFFu;
+            if (lane < n_r) {
+                for (int w = 0; w < BWD_WAVES; ++w) {
+                    const uint32_t c = s_wcnt[w][lane];
+                    s_wcnt[w][lane] = cnt;
+                    cnt += c;
+                }
+            }
+            uint32_t incl = cnt;
+#pragma unroll
+            for (int off = 1; off < WAVE; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, WAVE);
+                if (lane >= off) incl += y;
+            }
+            const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+            unsigned long long base = 0;
+            if (lane == 0 && total > 0) base = atomicAdd(a.rec_next, (unsigned long long)total);
+            base = __shfl(base, 0, WAVE);
+            const bool fits = base + total <= (unsigned long long)a.rec_cap;
+            if (lane < n_r) {
+                s_seg[lane] = (uint32_t)base + incl - cnt;
+                s_cnt[lane] = cnt;
+            }
+            const unsigned long long dm = __ballot(lane < n_r && (direct || !fits));
+            if (lane == 0) s_direct = dm;
+        }
+        __syncthreads();
+        const unsigned long long direct = s_direct;
+        // reverse sweep over the ranks, all voxels of the brick together
+        double xi[6] = {0, 0, 0, 0, 0, 0};
+        float tail = 1.0f;
+        unsigned long long m = mask;
+        for (int r = n_r - 1; r >= 0; --r) {
+            const int f = 63 - __builtin_clzll(m);
+            m &= ~(1ull << f);
+            const bool u = (upd >> r) & 1ull;
+            const unsigned long long bal = __ballot(u);
+            double pf[6] = {0, 0, 0, 0, 0, 0};   // this update's extrinsic terms (POSE)
+            if (u) {
+                const float alpha = hist[r * BWD_BLOCK];
+                const float beta = alpha * tail;
+                tail *= 1.0f - alpha;
+                const auto& c = frames[f];
+                const float qx = fmaf(c.Ah[2], fk, fmaf(c.Ah[1], fj, fmaf(c.Ah[0], fi, c.bh[0])));
+                const float qy = fmaf(c.Ah[5], fk, fmaf(c.Ah[4], fj, fmaf(c.Ah[3], fi, c.bh[1])));
+                const float qz = fmaf(c.Ah[8], fk, fmaf(c.Ah[7], fj, fmaf(c.Ah[6], fi, c.bh[2])));
+                const float iqz = recip(qz);
+                const float xh = fmaf(c.fxr, qx * iqz, c.cxr);
+                const float yh = fmaf(c.fyr, qy * iqz, c.cyr);
+                const float x0 = floorf(xh), y0 = floorf(yh);
+                const float ax = xh - x0, ay = yh - y0;
+                const int pix = (int)y0 * c.cw + (int)x0;
+                const int cell = pix * 3;
+                const int row = c.cw * 3;
+                const float* img = (const float*)c.rgb;
+                const float gb0 = g0 * beta, gb1 = g1 * beta, gb2 = g2 * beta;
+                if ((direct >> r) & 1ull) {
                     float* dimg = a.d_rgb + (size_t)f * (size_t)c.cw * (size_t)c.ch * 3;
                     const float w00 = (1.0f - ax) * (1.0f - ay), w10 = ax * (1.0f - ay);
                     const float w01 = (1.0f - ax) * ay, w11 = ax * ay;
-                    const float gv[3] = {g0, g1, g2};
-                    float gx = 0.0f, gy = 0.0f;   // sum_ch g beta ds/dx, ds/dy
+                    const float gv[3] = {gb0, gb1, gb2};
                     for (int ch = 0; ch < 3; ++ch) {
-                        const float gb = gv[ch] * beta;
-                        if (gb == 0.0f) continue;
-                        unsafeAtomicAdd(dimg + cell + ch, gb * w00);
-                        unsafeAtomicAdd(dimg + cell + 3 + ch, gb * w10);
-                        unsafeAtomicAdd(dimg + cell + row + ch, gb * w01);
-                        unsafeAtomicAdd(dimg + cell + row + 3 + ch, gb * w11);
-                        const float p00 = img[cell + ch], p10 = img[cell + 3 + ch];
-                        const float p01 = img[cell + row + ch], p11 = img[cell + row + 3 + ch];
-                        gx = fmaf(gb, (1.0f - ay) * (p10 - p00) + ay * (p11 - p01), gx);
-                        gy = fmaf(gb, (1.0f - ax) * (p01 - p00) + ax * (p11 - p10), gy);
+                        if (gv[ch] == 0.0f) continue;
+                        unsafeAtomicAdd(dimg + cell + ch, gv[ch] * w00);
+                        unsafeAtomicAdd(dimg + cell + 3 + ch, gv[ch] * w10);
+                        unsafeAtomicAdd(dimg + cell + row + ch, gv[ch] * w01);
+                        unsafeAtomicAdd(dimg + cell + row + 3 + ch, gv[ch] * w11);
                     }
-                    // pinhole Jacobian of Eq. 4 after the division by z
-                    const double dqx = (double)gx * c.fxr * iqz;
-                    const double dqy = (double)gy * c.fyr * iqz;
-                    const double dqz = -((double)gx * c.fxr * qx + (double)gy * c.fyr * qy) * iqz * iqz;
-                    xi[0] += dqx;
-                    xi[1] += dqy;
-                    xi[2] += dqz;
-                    xi[3] += (double)qy * dqz - (double)qz * dqy;
-                    xi[4] += (double)qz * dqx - (double)qx * dqz;
-                    xi[5] += (double)qx * dqy - (double)qy * dqx;
-                    if constexpr (POSE) {
-                        double* fa = facc + f * 6;
-                        atomicAdd(fa + 0, dqx);
-                        atomicAdd(fa + 1, dqy);
-                        atomicAdd(fa + 2, dqz);
-                        atomicAdd(fa + 3, (double)qy * dqz - (double)qz * dqy);
-                        atomicAdd(fa + 4, (double)qz * dqx - (double)qx * dqz);
-                        atomicAdd(fa + 5, (double)qx * dqy - (double)qy * dqx);
-                    }
+                } else {
+                    const size_t pos = (size_t)s_seg[r] + s_wcnt[wave][r] + lane_rank(bal);
+                    float2* rec = (float2*)(a.records + pos * 6);
+                    rec[0] = make_float2(__builtin_bit_cast(float, (uint32_t)pix), ax);
+                    rec[1] = make_float2(ay, gb0);
+                    rec[2] = make_float2(gb1, gb2);
+                }
+                const float gvals[3] = {gb0, gb1, gb2};
+                float gx = 0.0f, gy = 0.0f;   // sum_ch g beta ds/dx, ds/dy
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float gb = gvals[ch];
+                    if (gb == 0.0f) continue;
+                    const float p00 = img[cell + ch], p10 = img[cell + 3 + ch];
+                    const float p01 = img[cell + row + ch], p11 = img[cell + row + 3 + ch];
+                    gx = fmaf(gb, (1.0f - ay) * (p10 - p00) + ay * (p11 - p01), gx);
+                    gy = fmaf(gb, (1.0f - ax) * (p01 - p00) + ax * (p11 - p10), gy);
+                }
+                // pinhole Jacobian of Eq. 4 after the division by z
+                const double dqx = (double)gx * c.fxr * iqz;
+                const double dqy = (double)gy * c.fyr * iqz;
+                const double dqz = -((double)gx * c.fxr * qx + (double)gy * c.fyr * qy) * iqz * iqz;
+                const double p3 = (double)qy * dqz - (double)qz * dqy;
+                const double p4 = (double)qz * dqx - (double)qx * dqz;
+                const double p5 = (double)qx * dqy - (double)qy * dqx;
+                xi[0] += dqx;
+                xi[1] += dqy;
+                xi[2] += dqz;
+                xi[3] += p3;
+                xi[4] += p4;
+                xi[5] += p5;
+                pf[0] = dqx;
+                pf[1] = dqy;
+                pf[2] = dqz;
+                pf[3] = p3;
+                pf[4] = p4;
+                pf[5] = p5;
+            }
+            if constexpr (POSE) {
+                // the frame's terms summed over the brick in a fixed order: a butterfly per
+                // wave, then the waves in order (deterministic); the per-wave sums of
+                // consecutive frames alternate between two tables, one barrier per frame
+                double (*pw)[6] = s_pw[r & 1];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    const double sum = bal ? wave_sum_d(pf[q]) : 0.0;
+                    if (lane == q) pw[wave][q] = sum;
+                }
+                __syncthreads();
+                if (t < 6) {
+                    double acc = 0.0;
+                    for (int w = 0; w < BWD_WAVES; ++w) acc += pw[w][t];
+                    s_pose[f * 6 + t] = acc;
                 }
             }
         }
-        // the brick's extrinsic partial (a fixed butterfly order: deterministic)
-        const double s0 = wave_sum_d(xi[0]), s1 = wave_sum_d(xi[1]), s2 = wave_sum_d(xi[2]);
-        const double s3 = wave_sum_d(xi[3]), s4 = wave_sum_d(xi[4]), s5 = wave_sum_d(xi[5]);
-        // every lane stores component lane % 6 (the values are the same in every lane), so
-        // nothing in the loop depends on the lane index
-        const int q = lane % 6;
-        const double sq = q == 0 ? s0 : q == 1 ? s1 : q == 2 ? s2 : q == 3 ? s3 : q == 4 ? s4 : s5;
-        a.partials[(size_t)li * 6 + q] = sq;
+        // the brick's extrinsic partial: per wave a fixed butterfly, then the waves in order
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double s = wave_sum_d(xi[q]);
+            if (lane == q) s_xi[wave][q] = s;
+        }
+        __syncthreads();   // s_xi, s_pose complete; the history is free again
+        if (t < 6) {
+            double acc = 0.0;
+            for (int w = 0; w < BWD_WAVES; ++w) acc += s_xi[w][t];
+            a.partials[(size_t)li * 6 + t] = acc;
+        }
         if constexpr (POSE) {
             // the brick's per-frame partials, one row per brick (indexed by the brick, so the
             // reduction order does not depend on scheduling)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double* row = a.pose_partials + (size_t)li * (size_t)a.n_frames * 6;
-            for (int c = lane; c < a.n_frames * 6; c += WAVE) row[c] = facc[c];
+            double* prow = a.pose_partials + (size_t)li * (size_t)a.n_frames * 6;
+            for (int q = t; q < a.n_frames * 6; q += BWD_BLOCK) prow[q] = s_pose[q];
+        }
+        // the segments of the binned ranks, and their (frame, tile) counts
+        if (t < n_r && !((direct >> t) & 1ull) && s_cnt[t] > 0) {
+            unsigned long long mm = mask;
+            for (int q = 0; q < t; ++q) mm &= mm - 1;
+            const int f = __builtin_ctzll(mm);
+            const uint4 sg = make_uint4(s_seg[t], s_cnt[t],
+                                        (uint32_t)f | (uint32_t)s_tiles[t][2] << 8 | (uint32_t)s_tiles[t][3] << 9,
+                                        (uint32_t)s_tiles[t][0] | (uint32_t)s_tiles[t][1] << 16);
+            const uint32_t slot = atomicAdd(a.seg_next, 1u);
+            a.segs[slot] = sg;
+            const uint32_t n_tiles = (uint32_t)(a.tiles_x * a.tiles_y);
+            for (int ty = s_tiles[t][1]; ty <= s_tiles[t][1] + s_tiles[t][3]; ++ty)
+                for (int tx = s_tiles[t][0]; tx <= s_tiles[t][0] + s_tiles[t][2]; ++tx)
+                    atomicAdd(a.bin_count + (size_t)f * n_tiles + (uint32_t)(ty * a.tiles_x + tx), 1u);
+        }
+        __syncthreads();   // LDS tables are reused by the next brick
+    }
+}
+
+// Exclusive prefix sum of n counts in place (one block of 1024 threads; n + 1 entries, the
+// last receiving the total).
+__global__ __launch_bounds__(1024) void bin_scan_kernel(uint32_t* counts, uint32_t n)
+{
+    __shared__ uint32_t s[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t b0 = min(n, t * per), b1 = min(n, b0 + per);
+    uint32_t sum = 0;
+    for (uint32_t q = b0; q < b1; ++q) sum += counts[q];
+    s[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t y = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+    for (uint32_t q = b0; q < b1; ++q) {
+        const uint32_t c = counts[q];
+        counts[q] = run;
+        run += c;
+    }
+    if (t == 1023) counts[n] = s[1023];
+}
+
+// Each segment's index into every (frame, tile) bin its range covers.
+__global__ __launch_bounds__(256) void bin_fill_kernel(BackwardArgs a)
+{
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= *a.seg_next) return;
+    int f, tx0, tx1, ty0, ty1;
+    segment_tiles(a.segs[s], &f, &tx0, &tx1, &ty0, &ty1);
+    const uint32_t n_tiles = (uint32_t)(a.tiles_x * a.tiles_y);
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            const size_t bin = (size_t)f * n_tiles + (uint32_t)(ty * a.tiles_x + tx);
+            const uint32_t p = atomicAdd(a.bin_fill + bin, 1u);
+            a.bin_segs[a.bin_count[bin] + p] = s;
+        }
+}
+
+// One block per (tile, frame): the records of the segments binned there, added in LDS
+// over the tile's pixels (a record adds g beta times its four bilinear weights to the
+// pixels of its cell that lie in the tile), then added to the image gradient.
+constexpr int IMG_BLOCK = 256;
+constexpr int IMG_SEGS = 256;   // segments staged per round
+
+__global__ __launch_bounds__(IMG_BLOCK) void backward_image_kernel(BackwardArgs a)
+{
+    __shared__ float s_acc[BWD_TILE_W * BWD_TILE_H * 3];
+    __shared__ uint32_t s_first[IMG_SEGS], s_off[IMG_SEGS + 1];
+    const uint32_t n_tiles = (uint32_t)(a.tiles_x * a.tiles_y);
+    const uint32_t tile = blockIdx.x, f = blockIdx.y;
+    const size_t bin = (size_t)f * n_tiles + tile;
+    const uint32_t b0 = a.bin_count[bin], b1 = a.bin_count[bin + 1];
+    if (b0 == b1) return;   // the whole block
+    const int t = threadIdx.x;
+    const FrameConsts& c = a.frames[f];
+    const int tx0 = (int)(tile % (uint32_t)a.tiles_x) * BWD_TILE_W;
+    const int ty0 = (int)(tile / (uint32_t)a.tiles_x) * BWD_TILE_H;
+    for (int q = t; q < BWD_TILE_W * BWD_TILE_H * 3; q += IMG_BLOCK) s_acc[q] = 0.0f;
+    for (uint32_t s0 = b0; s0 < b1; s0 += IMG_SEGS) {
+        const uint32_t ns = min((uint32_t)IMG_SEGS, b1 - s0);
+        __syncthreads();   // the previous round's tables are no longer read
+        uint32_t cnt = 0;
+        if ((uint32_t)t < ns) {
+            const uint4 sg = a.segs[a.bin_segs[s0 + t]];
+            s_first[t] = sg.x;
+            cnt = sg.y;
+        }
+        // exclusive scan of the counts over the block (IMG_SEGS == IMG_BLOCK)
+        s_off[t + 1] = cnt;
+        if (t == 0) s_off[0] = 0;
+        __syncthreads();
+        for (int off = 1; off < IMG_SEGS; off <<= 1) {
+            const uint32_t y = t + 1 > off ? s_off[t + 1 - off] : 0u;
+            __syncthreads();
+            s_off[t + 1] += y;
+            __syncthreads();
+        }
+        const uint32_t total = s_off[ns];
+        for (uint32_t q = t; q < total; q += IMG_BLOCK) {
+            // the segment holding record q of the round
+            uint32_t lo = 0, hi = ns - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (s_off[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const float* rec = a.records + ((size_t)s_first[lo] + (q - s_off[lo])) * 6;
+            const uint32_t pix = __builtin_bit_cast(uint32_t, rec[0]);
+            const float ax = rec[1], ay = rec[2];
+            const float gv[3] = {rec[3], rec[4], rec[5]};
+            const int x0 = (int)(pix % (uint32_t)c.cw), y0 = (int)(pix / (uint32_t)c.cw);
+            const float w[4] = {(1.0f - ax) * (1.0f - ay), ax * (1.0f - ay), (1.0f - ax) * ay, ax * ay};
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int lx = x0 + (p & 1) - tx0, ly = y0 + (p >> 1) - ty0;
+                if (lx < 0 || lx >= BWD_TILE_W || ly < 0 || ly >= BWD_TILE_H) continue;
+                float* acc = s_acc + (ly * BWD_TILE_W + lx) * 3;
+                for (int ch = 0; ch < 3; ++ch)
+                    if (gv[ch] != 0.0f) atomicAdd(acc + ch, gv[ch] * w[p]);
+            }
+        }
+    }
+    __syncthreads();
+    float* dimg = a.d_rgb + (size_t)f * (size_t)c.cw * (size_t)c.ch * 3;
+    for (int q = t; q < BWD_TILE_W * BWD_TILE_H * 3; q += IMG_BLOCK) {
+        const float v = s_acc[q];
+        if (v == 0.0f) continue;
+        const int p = q / 3, ch = q - 3 * p;
+        const int x = tx0 + p % BWD_TILE_W, y = ty0 + p / BWD_TILE_W;
+        if (x < c.cw && y < c.ch) {
+            float* d = dimg + ((size_t)y * (size_t)c.cw + (size_t)x) * 3 + ch;
+            *d += v;
         }
     }
 }
@@ -380,10 +679,10 @@ static hipError_t launch_backward_hist(const BackwardArgs& a, int device, hipStr
     int n_cu = 0, per_cu = 0;
     hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_kernel<HIST, POSE>, BLOCK, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, backward_kernel<HIST, POSE>, BWD_BLOCK, 0);
     if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)(n_cu * (per_cu > 0 ? per_cu : 1));
-    hipLaunchKernelGGL((backward_kernel<HIST, POSE>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    hipLaunchKernelGGL((backward_kernel<HIST, POSE>), dim3(grid), dim3(BWD_BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -406,6 +705,17 @@ hipError_t launch_backward(const BackwardArgs& a, double* d_xi, double* d_pose, 
             e = a.n_frames <= 32 ? launch_backward_hist<32, false>(a, device, stream)
                                  : launch_backward_hist<64, false>(a, device, stream);
         if (e != hipSuccess) return e;
+        if (a.seg_cap > 0) {
+            // sort the segments by (frame, tile) and add each tile's records
+            const uint32_t n_bins = (uint32_t)a.n_frames * (uint32_t)(a.tiles_x * a.tiles_y);
+            hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, stream, a.bin_count, n_bins);
+            hipLaunchKernelGGL(bin_fill_kernel, dim3((a.seg_cap + 255) / 256), dim3(256), 0, stream, a);
+            hipLaunchKernelGGL(backward_image_kernel,
+                               dim3((unsigned)(a.tiles_x * a.tiles_y), (unsigned)a.n_frames),
+                               dim3(IMG_BLOCK), 0, stream, a);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     if (pose && a.n_frames > 0) {
         // per-frame column sums over the bricks (two fixed-order stages), then the adjoint map

@@ -1040,7 +1040,27 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     const bool pose = d_pose != nullptr && n_frames > 0;
     const size_t width = (size_t)n_frames * 6;
     const size_t pose_p_off = align(pose_t_off + (pose ? (size_t)n_frames * 12 * sizeof(double) : 0));
-    const size_t pyr_off = align(pose_p_off + (pose ? ((size_t)a.n_items + kf::XI_BLOCKS + 1) * width * sizeof(double) : 0));
+    // image-gradient records, their segments and (frame, tile) bins: records for half an
+    // update per HD pixel and frame (a brick that finds the buffer full scatters with
+    // atomics instead), one segment per live brick and frame, four bins per segment
+    a.tiles_x = (int32_t)ceil_div(cw, kf::BWD_TILE_W);
+    a.tiles_y = (int32_t)ceil_div(ch, kf::BWD_TILE_H);
+    const bool binned = n_frames > 0 && a.tiles_x <= 65535 && a.tiles_y <= 65535;
+    uint64_t rec_cap = binned ? (uint64_t)n_frames * (uint64_t)cw * (uint64_t)ch / 2 : 0;
+    if (binned && rec_cap < (1u << 20)) rec_cap = 1u << 20;
+    if (rec_cap > 0x7FFFFFFFull) rec_cap = 0x7FFFFFFFull;
+    if (const char* ev = getenv("KF_BWD_RECORDS")) rec_cap = binned ? strtoull(ev, nullptr, 10) : 0;
+    if (rec_cap > 0x7FFFFFFFull) rec_cap = 0x7FFFFFFFull;
+    a.rec_cap = (uint32_t)rec_cap;
+    a.seg_cap = binned ? (uint32_t)n_frames * a.n_items : 0u;
+    const size_t n_bins = binned ? (size_t)n_frames * (size_t)a.tiles_x * (size_t)a.tiles_y : 0;
+    const size_t rec_off = align(pose_p_off + (pose ? ((size_t)a.n_items + kf::XI_BLOCKS + 1) * width * sizeof(double) : 0));
+    const size_t recn_off = align(rec_off + (size_t)a.rec_cap * 6 * sizeof(float));
+    const size_t seg_off = align(recn_off + 2 * sizeof(unsigned long long));
+    const size_t bins_off = align(seg_off + (size_t)a.seg_cap * sizeof(uint4));
+    const size_t fill_off = align(bins_off + (n_bins + 1) * sizeof(uint32_t));
+    const size_t bsegs_off = align(fill_off + n_bins * sizeof(uint32_t));
+    const size_t pyr_off = align(bsegs_off + 4 * (size_t)a.seg_cap * sizeof(uint32_t));
     size_t off = pyr_off;
     int32_t max_tiles0 = 0;
     std::vector<size_t> pyr(fc.size(), 0);
@@ -1068,6 +1088,13 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     a.queue = a.n_live + 1;
     a.live = (uint4*)(ws + live_off);
     a.partials = (double*)(ws + partials_off);
+    a.records = (float*)(ws + rec_off);
+    a.rec_next = (unsigned long long*)(ws + recn_off);
+    a.segs = (uint4*)(ws + seg_off);
+    a.seg_next = (uint32_t*)(ws + recn_off + sizeof(unsigned long long));
+    a.bin_count = (uint32_t*)(ws + bins_off);
+    a.bin_fill = (uint32_t*)(ws + fill_off);
+    a.bin_segs = (uint32_t*)(ws + bsegs_off);
     std::vector<double> pose_t;
     if (pose) {
         // T_hd_from_world = T_rgb_from_d T_world_from_cam^-1 of each frame, in double
@@ -1098,6 +1125,11 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     if (s == KF_OK && n_frames > 0) {
         if ((e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st)) != hipSuccess) what = "gradient reset";
         else if ((e = kf::launch_fill_u32((uint32_t*)(ws + counters_off), 2, 0u, st)) != hipSuccess) what = "counter reset";
+        else if ((e = kf::launch_fill_u32((uint32_t*)(ws + recn_off), 4, 0u, st)) != hipSuccess) what = "record counter reset";
+        else if (n_bins > 0 && (e = kf::launch_fill_u32((uint32_t*)(ws + bins_off), n_bins + 1, 0u, st)) != hipSuccess)
+            what = "bin reset";
+        else if (n_bins > 0 && (e = kf::launch_fill_u32((uint32_t*)(ws + fill_off), n_bins, 0u, st)) != hipSuccess)
+            what = "bin reset";
         else if ((e = kf::launch_fill_u32((uint32_t*)a.partials, (size_t)a.n_items * 12, 0u, st)) != hipSuccess)
             what = "partial reset";
         else if (pose && (e = kf::launch_fill_u32((uint32_t*)a.pose_partials, (size_t)a.n_items * width * 2, 0u,

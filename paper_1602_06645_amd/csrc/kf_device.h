@@ -130,7 +130,22 @@ struct BackwardArgs {
                                       // [n_frames][6] sums
     const double* pose_adjoint;       // [n_frames][12]: R (row-major) and t of each frame's
                                       // T_hd_from_world, for d_pose = -Ad^T (frame partial)
+    // image-gradient records and their (frame, HD tile) bins (see kf_backward.hip)
+    float* records;                   // [rec_cap][6]: pixel index (bits), ax, ay, g beta (3)
+    unsigned long long* rec_next;     // records reserved so far (may pass rec_cap)
+    uint32_t rec_cap;                 // 0: every update is scattered with atomics
+    uint4* segs;                      // [seg_cap] (first record, count, frame | spans, tiles)
+    uint32_t* seg_next;
+    uint32_t seg_cap;                 // n_frames * n_items: a brick has one segment per frame
+    int32_t tiles_x, tiles_y;         // BWD_TILE_W x BWD_TILE_H tiles of the HD image
+    uint32_t* bin_count;              // [n_frames * tiles + 1] segments per (frame, tile), then
+                                      // their exclusive prefix sum
+    uint32_t* bin_fill;               // [n_frames * tiles]
+    uint32_t* bin_segs;               // [4 * seg_cap] segment of each bin entry
 };
+
+// Tiles of the HD image over which the adjoint adds its image-gradient records.
+constexpr int BWD_TILE_W = 64, BWD_TILE_H = 32;
 
 // 1.0f / z, correctly rounded, in fewer instructions than the IEEE division: the hardware
 // reciprocal refined by one Newton step with an FMA residual, r + r (1 - z r), equals the

@@ -218,6 +218,8 @@ static bool needs_fibers(const void* k)
         (const void*)kf::backward_kernel<64, false>,
         (const void*)kf::backward_kernel<32, true>,
         (const void*)kf::backward_kernel<64, true>,
+        (const void*)kf::bin_scan_kernel,
+        (const void*)kf::backward_image_kernel,
     };
     for (const void* p : list)
         if (p == k) return true;

@@ -163,6 +163,7 @@ inline unsigned long long atomicOr(unsigned long long* p, unsigned long long v)
     return std::atomic_ref<unsigned long long>(*p).fetch_or(v);
 }
 inline float unsafeAtomicAdd(float* p, float v) { return std::atomic_ref<float>(*p).fetch_add(v); }
+inline float atomicAdd(float* p, float v) { return std::atomic_ref<float>(*p).fetch_add(v); }
 inline double atomicAdd(double* p, double v) { return std::atomic_ref<double>(*p).fetch_add(v); }
 
 // ---------------------------------------------------------------- buffer resources

@@ -288,4 +288,13 @@ tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)
 out["backward_odd"] = backward_case(spec_odd, fr6, pose=True)
 tick("backward 32")
+# the image gradient scattered with atomics for every update (no record buffer), and with a
+# record buffer too small for the 32-frame scan (bricks past its end scatter directly)
+for case, cap in (("backward_direct", "0"), ("backward_overflow", "3000")):
+    os.environ["KF_BWD_RECORDS"] = cap
+    try:
+        out[case] = backward_case(spec32, fr32, pose=True)
+    finally:
+        del os.environ["KF_BWD_RECORDS"]
+tick("backward direct / overflow")
 print("JSON:" + json.dumps(out), flush=True)

@@ -8,7 +8,8 @@ float images, 6 and 32 frames, 8 frames per pass), passes of more than 32 frames
 frames at 36 per pass), the allocation-free entry point on two batches in a row, the
 per-voxel outcome codes of every frame of a scan, the ray cast of an integrated volume, and
 the adjoint over 6 and 32 frames (a
-live frame in bit 31 of a brick's frame mask)."""
+live frame in bit 31 of a brick's frame mask), with its image gradient added per HD tile
+from records, scattered with atomics, and both (a record buffer that runs out)."""
 import json
 import os
 import subprocess
@@ -53,7 +54,8 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert res["texture_mismatches"] == 0
     assert res["nearest_mismatches"] == 0 and res["nearest_status_mismatches"] == 0
     assert res["mesh_mismatches"] == 0
-    for case in ("backward_6", "backward_32", "backward_odd"):
+    for case in ("backward_6", "backward_32", "backward_odd", "backward_direct", "backward_overflow"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
-    for case in ("backward_6", "backward_odd"):      # with the depth-pose adjoint
+    for case in ("backward_6", "backward_odd", "backward_direct", "backward_overflow"):
+        # with the depth-pose adjoint
         assert res[case]["pose"] <= 1.0, res

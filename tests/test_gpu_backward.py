@@ -202,3 +202,33 @@ def test_depth_pose_adjoint_full_size(oracle, n_frames):
     torch.cuda.synchronize()
     assert np.abs(want).max() > 0
     _close(d_pose.cpu().numpy(), want)
+
+
+def test_backward_image_gradient_paths_agree(monkeypatch):
+    """The image gradient through the per-tile record sums, through float atomics alone
+    (no record buffer) and through both (a record buffer that fills up after a few
+    bricks), on the kinect volume's first 32 frames with dense g: the same numbers up to
+    the order of the float additions; the extrinsic gradient does not depend on the path."""
+    say("backward: full size, 32 frames, record / atomic / mixed image-gradient paths")
+    spec, fr = configs.kinect(device=DEV, n_frames=32)
+    fr = fr.as_float_rgb()
+    s = kf.Scan.from_frames(fr)
+    g = configs.gradient_weights(spec.n_colour, device=DEV)
+    out = {}
+    for name, cap in (("records", None), ("atomics", "0"), ("mixed", "200000")):
+        if cap is None:
+            monkeypatch.delenv("KF_BWD_RECORDS", raising=False)
+        else:
+            monkeypatch.setenv("KF_BWD_RECORDS", cap)
+        say(f"  image-gradient path: {name}")
+        out[name] = kf.integrate_backward(spec, s, g)
+        torch.cuda.synchronize()
+    monkeypatch.delenv("KF_BWD_RECORDS", raising=False)
+    ref_rgb, ref_xi = out["atomics"]
+    scale = float(ref_rgb.abs().max())
+    assert scale > 0
+    for name in ("records", "mixed"):
+        d_rgb, d_xi = out[name]
+        assert torch.equal(d_xi, ref_xi), f"{name}: extrinsic gradient differs"
+        err = float((d_rgb - ref_rgb).abs().max())
+        assert err <= 1e-5 * scale, f"{name}: image gradient differs by {err} (scale {scale})"
