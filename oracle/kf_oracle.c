@@ -528,3 +528,6 @@ int or_mc_cube_triangles(unsigned inside_mask, int32_t* tri_edges)
         for (int v = 0; v < 3; ++v) tri_edges[3 * i + v] = t[i][v];
     return n;
 }
+
+/* ---- quadric-error decimation of a triangle mesh (see kf_decimate_body.h) */
+#include "kf_decimate_body.h"

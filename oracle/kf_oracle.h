@@ -4,7 +4,8 @@
  * and the asymmetric colour volume of Sec. IV.B (Eq. 5-10) with the depth-to-HD-RGB
  * mapping of Sec. IV.A (Eq. 1-4), plus the adjoint of the colour update; ray casting of
  * the two volumes (Sec. III rendering); the per-polygon texture maps of Sec. IV.D
- * (Eq. 11-14) and their column-wise atlas.
+ * (Eq. 11-14) and their column-wise atlas; marching cubes and the quadric-error decimation
+ * of the mesh (Sec. IV.C).
  *
  * TEST INFRASTRUCTURE ONLY.  This is a plain, slow CPU implementation that the test
  * suite, the smoke check and the benchmark's CPU-baseline leg compare the GPU library
@@ -195,6 +196,16 @@ int or_marching_cubes(const or_volume* vol, const float* tsdf, const float* wg, 
 /* Triangles (as cube edge ids, [n][3]) of one cube whose inside corners are the set bits of
  * inside_mask (corner c = x + 2y + 4z); returns n. */
 int or_mc_cube_triangles(unsigned inside_mask, int32_t* tri_edges);
+
+/*
+ * Quadric-error decimation (Sec. IV.C, the reduction rate of Fig. 3; the definition is in
+ * kf_decimate_body.h): vin [nv][3], tin [nt][3] (CCW) in; writes the kept vertices (vout,
+ * at most nv) and triangles (tout, at most nt; either output may be NULL) and their counts.
+ * Returns the triangle count, or -1 for an index out of range or a triangle repeating a
+ * vertex.
+ */
+int64_t or_decimate(const float* vin, int64_t nv, const int32_t* tin, int64_t nt, double rate,
+                    float* vout, int64_t* nv_out, int32_t* tout, int64_t* nt_out);
 
 #ifdef __cplusplus
 }

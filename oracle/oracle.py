@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU-bas
 leg use this module to compute the reference results of the volumetric integration of
 arXiv 1602.06645 (Sec. III TSDF volume; Sec. IV.B colour volume, Eq. 5-10; Sec. IV.A
 depth-to-HD mapping, Eq. 1-4), the ray casting of the two volumes and the per-polygon
-texture maps of Sec. IV.D (Eq. 11-14).  The product library never imports it.
+texture maps of Sec. IV.D (Eq. 11-14), marching cubes and the quadric-error decimation of
+the mesh (Sec. IV.C).  The product library never imports it.
 """
 from __future__ import annotations
 
@@ -101,6 +102,8 @@ def lib():
         L.or_marching_cubes.restype = C.c_int
         L.or_mc_cube_triangles.argtypes = [C.c_uint, p]
         L.or_mc_cube_triangles.restype = C.c_int
+        L.or_decimate.argtypes = [p, C.c_int64, p, C.c_int64, C.c_double, p, p, p, p]
+        L.or_decimate.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -356,3 +359,18 @@ def mc_cube_triangles(inside_mask: int) -> np.ndarray:
     out = np.zeros((12, 3), np.int32)
     n = lib().or_mc_cube_triangles(int(inside_mask), out.ctypes.data)
     return out[:n].copy()
+
+
+def decimate(vertices, triangles, rate: float):
+    """Quadric-error decimation of a triangle mesh to round(rate * triangles) triangles
+    (Sec. IV.C; see kf_decimate_body.h): returns (float32 [n][3], int32 [m][3])."""
+    V = np.ascontiguousarray(vertices, np.float32).reshape(-1, 3)
+    T = np.ascontiguousarray(triangles, np.int32).reshape(-1, 3)
+    ov = np.zeros((max(len(V), 1), 3), np.float32)
+    ot = np.zeros((max(len(T), 1), 3), np.int32)
+    nv, nt = C.c_int64(), C.c_int64()
+    r = lib().or_decimate(V.ctypes.data, len(V), T.ctypes.data, len(T), float(rate), ov.ctypes.data,
+                          C.byref(nv), ot.ctypes.data, C.byref(nt))
+    if r < 0:
+        raise ValueError("bad mesh (index out of range or a triangle repeating a vertex)")
+    return ov[:nv.value].copy(), ot[:nt.value].copy()
