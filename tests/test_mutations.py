@@ -20,6 +20,7 @@ ROOT = os.path.dirname(HERE)
 ORACLE = os.path.join(ROOT, "oracle")
 BODY, MAIN, RC, TX = "kf_oracle_body.h", "kf_oracle.c", "kf_raycast_body.h", "kf_texture_body.h"
 MC = "kf_mesh_body.h"
+DEC = "kf_decimate_body.h"
 
 # (name, file, original text, mutated text)
 MUTANTS = [
@@ -91,6 +92,14 @@ MUTANTS = [
     ("mesh_edge_id_axes_swapped", MC, "if (d == 0) return 0 + y + 2 * z;", "if (d == 0) return 0 + z + 2 * y;"),
     ("mesh_fan_from_loop_start", MC, "for (; c < len; ++c) {", "for (; c < 0; ++c) {"),
     ("mesh_last_cube_column_dropped", MC, "for (int64_t x = 0; x + 1 < X; ++x) {", "for (int64_t x = 0; x + 2 < X; ++x) {"),
+    # quadric-error decimation
+    ("decimate_no_boundary_planes", DEC, "const double wt = DEC_BOUNDARY_WEIGHT;", "const double wt = 0.0;"),
+    ("decimate_no_link_condition", DEC, "    if (common != ns) return 0;\n", ""),
+    ("decimate_no_flip_test", DEC, "if (!(n0[0] * n1[0] + n0[1] * n1[1] + n0[2] * n1[2] > 0.0)) return 0;", ""),
+    ("decimate_midpoint_only", DEC, "if (tr > 0.0 && fabs(det) > DEC_DET_EPS * tr * tr * tr) {", "if (0) {"),
+    ("decimate_target_truncated", DEC, "floor(rate * (double)nt + 0.5)", "floor(rate * (double)nt)"),
+    ("decimate_quadrics_not_merged", DEC, "m.Q[a][k] = m.Q[a][k] + m.Q[b][k];", "m.Q[a][k] = m.Q[a][k];"),
+    ("decimate_cost_drops_cross_term", DEC, "+ 2.0 * q[1] * x * y", "+ 0.0 * q[1] * x * y"),
 ]
 
 PIN_FILES = [os.path.join(HERE, n) for n in (
@@ -100,14 +109,15 @@ PIN_FILES = [os.path.join(HERE, n) for n in (
 # mistake in the shared source or the integration body runs them all.
 PINS_FOR = {RC: [os.path.join(HERE, "test_raycast_pins.py")],
             TX: [os.path.join(HERE, "test_texture_pins.py")],
-            MC: [os.path.join(HERE, "test_mesh_pins.py")]}
+            MC: [os.path.join(HERE, "test_mesh_pins.py")],
+            DEC: [os.path.join(HERE, "test_decimate_pins.py")]}
 
 
 def _run_mutant(m, workdir):
     name, fname, old, new = m
     src = os.path.join(workdir, name)
     os.makedirs(src)
-    for f in (BODY, MAIN, RC, TX, MC, "kf_oracle.h"):
+    for f in (BODY, MAIN, RC, TX, MC, DEC, "kf_oracle.h"):
         shutil.copy(os.path.join(ORACLE, f), src)
     path = os.path.join(src, fname)
     text = open(path).read()
