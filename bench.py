@@ -19,8 +19,8 @@ integration launch, VALU-bound: algorithmic operations per launch over its durat
 measured with HIP events on the launch stream, with the HBM fraction of its algorithmic
 bytes beside it); the many-uneven-scenes batch (16 scans, 86 GB of state) against the
 same scans integrated one by one; a device copy giving the achievable HBM bandwidth;
-the Kinect-like scan (256^3 / 512^3, 300 frames) with ray casting, marching cubes and
-texture maps of its volume; forward + backward of the differentiable form on its first
+the Kinect-like scan (256^3 / 512^3, 300 frames) with ray casting, marching cubes, the
+quadric-error decimation of the mesh and texture maps of the decimated mesh; forward + backward of the differentiable form on its first
 32 frames; and the CPU oracle timed on a sample of the headline scan's z-slabs on all
 host threads and on one.
 
@@ -107,8 +107,8 @@ def alg_counts(cnt, n_frames, frame_bytes):
     which reads the HD images, and the geometry launch, which reads the depth maps)."""
     g_bytes = 16 * int(cnt[1])
     c_bytes = 4 * int(cnt[3]) + 28 * int(cnt[5])
-    g_ops = OPS["geom_voxel_frame"] * 512 * int(cnt[6]) + OPS["geom_update"] * int(cnt[0])
-    c_ops = (OPS["colour_voxel_frame"] * 512 * int(cnt[7]) + OPS["colour_gate"] * int(cnt[2])
+    g_ops = OPS["geom_voxel_frame"] * int(cnt[6]) + OPS["geom_update"] * int(cnt[0])
+    c_ops = (OPS["colour_voxel_frame"] * int(cnt[7]) + OPS["colour_gate"] * int(cnt[2])
              + OPS["colour_update"] * int(cnt[4]))
     return {"geometry": {"bytes": g_bytes + n_frames * frame_bytes[0], "ops": g_ops},
             "colour": {"bytes": c_bytes + n_frames * (frame_bytes[0] + frame_bytes[1]),
@@ -119,9 +119,10 @@ def counters_dict(cnt, spec, n):
     return {"geom_updates": int(cnt[0]), "geom_touched_per_pass": int(cnt[1]),
             "colour_gate_evals": int(cnt[2]), "colour_read_per_pass": int(cnt[3]),
             "colour_updates": int(cnt[4]), "colour_touched_per_pass": int(cnt[5]),
-            "geom_brick_frames": int(cnt[6]), "colour_brick_frames": int(cnt[7]),
-            "geom_live_fraction": int(cnt[6]) * 512 / (spec.n_geom * n),
-            "colour_live_fraction": int(cnt[7]) * 512 / (spec.n_colour * n)}
+            "geom_voxel_frames_in_live_bricks": int(cnt[6]),
+            "colour_voxel_frames_in_live_bricks": int(cnt[7]),
+            "geom_live_fraction": int(cnt[6]) / (spec.n_geom * n),
+            "colour_live_fraction": int(cnt[7]) / (spec.n_colour * n)}
 
 
 def timed_reps(fn, reps):
@@ -184,6 +185,8 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes_per_dispatch": 4 << 28}), flush=True)
         return 0
     K = args.frames_per_pass or autotune.frames_per_pass("fused", default=64)
+    bricks = autotune.bricks("fused")
+    bricks_cfg = bricks or {k: v[0] for k, v in kf.brick_shapes().items()}
 
     t = time.perf_counter()
     spec, fr = configs.fused(device="cuda")
@@ -209,7 +212,7 @@ def main() -> int:
 
     # ---- algorithmic bytes and operations (counting instantiation, not timed)
     vol.reset()
-    cnt = kf.integrate_batch_counted([(vol, scan)], frames_per_pass=K)
+    cnt = kf.integrate_batch_counted([(vol, scan)], frames_per_pass=K, bricks=bricks)
     alg = alg_counts(cnt, fr.n, frame_bytes)
     log(f"counters {list(map(int, cnt))}; algorithmic bytes per scan "
         f"{(alg['geometry']['bytes'] + alg['colour']['bytes']) / 1e9:.3f} GB")
@@ -218,7 +221,7 @@ def main() -> int:
     # recorded by the library around each launch give the kernels' durations
     def graph_scan():
         vol.reset()
-        kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
+        kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True, bricks=bricks)
 
     for _ in range(args.warmup):
         graph_scan()
@@ -230,7 +233,7 @@ def main() -> int:
     t0 = time.perf_counter()
     for s in range(args.steps):
         vol.reset()
-        kf.integrate_batch_timed([(vol, scan)], K, ev[s * n_pass:(s + 1) * n_pass])
+        kf.integrate_batch_timed([(vol, scan)], K, ev[s * n_pass:(s + 1) * n_pass], bricks=bricks)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
@@ -269,6 +272,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames": fr.n, "frames_per_pass": K,
+                   "bricks": {k: list(v) for k, v in bricks_cfg.items()},
                    "geometry_dim": list(spec.gdim), "colour_dim": list(spec.cdim),
                    "depth": [fr.depth.shape[2], fr.depth.shape[1]],
                    "rgb": [fr.rgb.shape[2], fr.rgb.shape[1]], "rgb_format": "u8",
@@ -332,16 +336,17 @@ def main() -> int:
         vols = [kf.Volume(s) for s, _ in scans]
         pairs = [(v, kf.Scan.from_frames(f)) for v, (_, f) in zip(vols, scans)]
         Km = autotune.frames_per_pass("many_scenes", default=32)
+        Bm = autotune.bricks("many_scenes")
 
         def batched():
             for v in vols:
                 v.reset()
-            kf.integrate_batch(pairs, frames_per_pass=Km, use_graph=True)
+            kf.integrate_batch(pairs, frames_per_pass=Km, use_graph=True, bricks=Bm)
 
         def one_by_one_fused():
             for p in pairs:
                 p[0].reset()
-                kf.integrate_batch([p], frames_per_pass=Km, use_graph=True)
+                kf.integrate_batch([p], frames_per_pass=Km, use_graph=True, bricks=Bm)
 
         def one_by_one_plain():
             for v, (s, f) in zip(vols, scans):
@@ -380,8 +385,8 @@ def main() -> int:
 
 def kinect_legs(out, legs, kf, configs, np, torch):
     """The Kinect-like scan (256^3 / 512^3, 300 frames): fused scan time, ray casting,
-    marching cubes and texture maps of its volume; forward + backward on its first 32
-    frames."""
+    marching cubes, decimation of the mesh and texture maps of the decimated mesh; forward +
+    backward on its first 32 frames."""
     from paper_1602_06645_amd import autotune
     t = time.perf_counter()
     spec, fr = configs.kinect(device="cuda")
@@ -393,10 +398,11 @@ def kinect_legs(out, legs, kf, configs, np, torch):
                        "depth + 1920x1080 RGB8"}
     if "kinect" in legs:
         K = autotune.frames_per_pass("kinect", default=64)
+        Bk = autotune.bricks("kinect")
 
         def scan_step():
             vol.reset()
-            kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True)
+            kf.integrate_batch([(vol, scan)], frames_per_pass=K, use_graph=True, bricks=Bk)
         scan_step()
         s = timed_reps(scan_step, 5)
         res.update({"frames_per_pass": K, "ms_per_scan": 1e3 * s,
@@ -450,8 +456,25 @@ def kinect_legs(out, legs, kf, configs, np, torch):
             f"{cap[0]} vertices, {cap[1]} triangles")
         del verts, tris
 
-        # ---- per-polygon texture maps from the integrated colour volume (Sec. IV.D)
-        tri, size_pixel = configs.kinect_triangles(n_frames=fr.n)
+        # ---- quadric-error decimation of the marching-cubes mesh (Sec. IV.C), host code
+        verts, tris = vol.mesh(capacity=cap)
+        vh, th = verts.cpu().numpy(), tris.cpu().numpy()
+        rate = 0.02
+        td = time.perf_counter()
+        dv, dt_ = kf.decimate(vh, th, rate)
+        dec_s = time.perf_counter() - td
+        res["decimation"] = {"rate": rate, "triangles_in": int(len(th)), "triangles_out": int(len(dt_)),
+                             "vertices_out": int(len(dv)), "ms": 1e3 * dec_s,
+                             "triangles_per_s": len(th) / dec_s,
+                             "note": "kf_mesh_decimate on the host (one thread), mesh copied from "
+                                     "the GPU first"}
+        log(f"decimation: {len(th)} -> {len(dt_)} triangles in {1e3 * dec_s:.0f} ms")
+        del verts, tris
+
+        # ---- per-polygon texture maps of the decimated mesh from the integrated colour
+        # volume (Sec. IV.D): V1, V2, V3 of each map are the triangle's vertices in order
+        tri = np.ascontiguousarray(dv[dt_], np.float32)
+        size_pixel = 0.8 / 1050.0   # one HD pixel at the scanning distance
         AH = 4096
         rects, AW = kf.texture_layout(tri, size_pixel, AH)
         tri_d = torch.as_tensor(tri, device="cuda")
@@ -469,6 +492,7 @@ def kinect_legs(out, legs, kf, configs, np, torch):
         n_texels = int((rects[:, 2].astype(np.int64) * rects[:, 3]).sum())
         nonzero = float(atlas["rgb8"].reshape(-1, 3).amax(1).gt(0).sum()) / n_texels
         res["texture"] = {"ms_per_atlas": tx_ms, "texels_per_s": n_texels / (tx_ms * 1e-3),
+                          "mesh": f"marching cubes of the scanned volume decimated to {rate:g}",
                           "triangles": len(tri), "texels": n_texels, "atlas": [AW, AH],
                           "size_pixel_m": size_pixel, "nonzero_fraction": nonzero,
                           "outputs": "float32 RGB + 8-bit RGB atlases",

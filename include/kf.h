@@ -132,6 +132,22 @@ typedef struct {
     double trunc_m, w_max;
 } kf_scene;
 
+/* Voxels per brick (x, y, z) of the forward integration's work items, per volume kind.
+ * A brick is the work of one wavefront: x * y == 64 voxel columns of z voxels.  The
+ * result never depends on the shapes (each voxel sees the same operations in the same
+ * frame order); the time does: longer columns share the per-column part of Eq. 5 among
+ * more voxels, smaller bricks are culled more finely.  Only the shapes listed by
+ * kf_brick_shapes are compiled. */
+typedef struct {
+    int32_t geom[3];     /* default 16 x 4 x 8 */
+    int32_t colour[3];   /* default 8 x 8 x 8  */
+} kf_bricks;
+
+/* The brick shapes compiled for kind 0 (geometry) or 1 (colour): writes up to `capacity`
+ * triples (x, y, z) to `shapes` (host int32 [capacity][3]), the first being the default,
+ * and their number to *n_shapes.  Host-only. */
+kf_status kf_brick_shapes(int32_t kind, int32_t* shapes, int32_t capacity, int32_t* n_shapes);
+
 /*
  * Integrate several independent scans (different volumes, sizes and frame counts).
  * Each voxel keeps its state on chip for frames_per_pass (K, 1 <= K; values above 64 act
@@ -146,6 +162,19 @@ typedef struct {
  */
 kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes,
                              int32_t frames_per_pass, int32_t use_graph, void* stream);
+
+/* Destroy every graph recorded by kf_integrate_batch(..., use_graph != 0, ...) and free the
+ * workspaces they own (waits for the device).  The cache keeps at most 64 graphs and 4 GiB
+ * of workspace on its own, dropping the least recently used; this empties it, e.g. before
+ * the volumes or images it refers to are freed for good.  *n_released and *bytes_released
+ * (either may be NULL) receive what was dropped. */
+kf_status kf_release_graphs(int32_t* n_released, size_t* bytes_released);
+
+/* kf_integrate_batch with the bricks of the given shapes (NULL: the defaults); a shape not
+ * listed by kf_brick_shapes is KF_E_UNSUPPORTED.  Same result for every shape. */
+kf_status kf_integrate_batch_bricks(const kf_scene* scenes, int32_t n_scenes,
+                                    int32_t frames_per_pass, int32_t use_graph,
+                                    const kf_bricks* bricks, void* stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph capture, serving
@@ -167,31 +196,32 @@ kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
                                      int32_t frames_per_pass, void* stream);
 
 /*
- * kf_integrate_batch (without a graph) that also records start_events[q] and
+ * kf_integrate_batch_bricks (without a graph) that also records start_events[q] and
  * end_events[q] (hipEvent_t handles created by the caller) on `stream` immediately before
  * the geometry and after the colour integration launch of pass q, for q < n_events, and,
  * when mid_events is not NULL, mid_events[q] between the two launches; n_events must be
  * at least the number of passes.  For measuring the integration kernels alone.
  */
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
-                                   int32_t frames_per_pass, void* const* start_events,
-                                   void* const* mid_events, void* const* end_events,
-                                   int32_t n_events, void* stream);
+                                   int32_t frames_per_pass, const kf_bricks* bricks,
+                                   void* const* start_events, void* const* mid_events,
+                                   void* const* end_events, int32_t n_events, void* stream);
 
 /*
- * Byte accounting for kf_integrate_batch with the same arguments: performs the same
- * integration and adds into counters (device, uint64[8], not cleared):
+ * Byte accounting for kf_integrate_batch_bricks with the same arguments: performs the
+ * same integration and adds into counters (device, uint64[8], not cleared):
  *   [0] geometry voxel updates        [1] geometry voxels updated at least once per pass
  *   [2] colour voxel-frames reaching the weight gate
  *   [3] colour voxels reaching the gate at least once per pass
  *   [4] colour voxel updates          [5] colour voxels updated at least once per pass
- *   [6] geometry brick-frames processed  [7] colour brick-frames processed
- *       (a brick is 512 voxels; the rest were culled as unable to pass the depth tests)
+ *   [6] geometry voxel-frames processed  [7] colour voxel-frames processed
+ *       (the voxels of the live bricks of each frame; the rest were culled as unable to
+ *       pass the depth tests; [0]-[5] do not depend on the brick shapes, [6]-[7] do)
  * Slower than kf_integrate_batch; for measurement only.
  */
 kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
-                                     int32_t frames_per_pass, unsigned long long* counters,
-                                     void* stream);
+                                     int32_t frames_per_pass, const kf_bricks* bricks,
+                                     unsigned long long* counters, void* stream);
 
 /*
  * Per-voxel outcome of one frame against the volume's current state, without updating
@@ -237,6 +267,18 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
                                 double* d_xi, double* d_pose, void* stream);
 
 /*
+ * se(3) helpers for the extrinsic of the adjoint (host-only, double precision):
+ *   kf_se3_compose:  T_out = exp(xi^) T_in, xi = (rho, phi) (translation, rotation), the
+ *                    left perturbation kf_integrate_backward differentiates (T_in rigid);
+ *   kf_se3_pullback: d_xi = J_l(xi)^T d_eps, the gradient with respect to xi of a function
+ *                    of exp(xi^) T when d_eps is its gradient for a left perturbation at
+ *                    exp(xi^) T (J_l the left Jacobian of SE(3)).
+ * Both sum the exponential series (40 terms); |phi| must not exceed 10 (KF_E_ARG).
+ */
+kf_status kf_se3_compose(const double xi[6], const double T_in[16], double T_out[16]);
+kf_status kf_se3_pullback(const double xi[6], const double d_eps[6], double d_xi[6]);
+
+/*
  * Ray cast the volumes from a camera (the rendering the method uses for live feedback and
  * the predicted surface of tracking: abstract and Sec. III).  For pixel (x, y) of a
  * width x height image with intrinsics K (zero skew, positive focal lengths) and pose
@@ -279,6 +321,31 @@ kf_status kf_raycast(kf_volume* vol, int32_t width, int32_t height, const double
 kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capacity,
                           int32_t* triangles, int64_t triangle_capacity, int64_t counts[2],
                           void* stream);
+
+/*
+ * Quadric-error decimation of a triangle mesh (Sec. IV.C: the dense marching-cubes model
+ * is simplified by quadric-based decimation to a reduction rate, the fraction of its
+ * polygons that remain; Fig. 3).  Host-only and synchronous: every pointer is HOST memory.
+ *   vertices:  float32 [n_vertices][3]; triangles: int32 [n_triangles][3] vertex indices,
+ *              counter-clockwise seen from outside (kf_mesh_extract's output, copied to
+ *              the host), each triangle with three distinct vertices;
+ *   rate:      in [0, 1]; edges are contracted until at most round(rate * n_triangles)
+ *              triangles remain (or no edge can be contracted without breaking the
+ *              surface);
+ *   out_vertices, out_triangles: room for n_vertices and n_triangles entries; receive the
+ *              kept vertices (in input order) and triangles (in input order, re-indexed,
+ *              orientation kept); *out_n_vertices, *out_n_triangles their counts.
+ * The squared distances to the planes of a vertex's triangles make its quadric error;
+ * open borders add planes perpendicular to their triangles (weight 1000) so they stay in
+ * place.  The cheapest edge (ties by its vertex indices) is
+ * contracted to the point minimising the summed quadric when the contraction keeps the
+ * surface manifold and turns no triangle over.  Deterministic (double precision).
+ * KF_E_ARG for bad indices, non-finite vertices or a rate outside [0, 1].
+ */
+kf_status kf_mesh_decimate(const float* vertices, int64_t n_vertices, const int32_t* triangles,
+                           int64_t n_triangles, double rate, float* out_vertices,
+                           int64_t* out_n_vertices, int32_t* out_triangles,
+                           int64_t* out_n_triangles);
 
 /*
  * Texture-map sizes and their place in an atlas image (Sec. IV.D: Eq. 11-12 and the

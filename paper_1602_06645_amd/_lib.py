@@ -38,6 +38,10 @@ class Scene(C.Structure):
                 ("w_max", C.c_double)]
 
 
+class Bricks(C.Structure):
+    _fields_ = [("geom", C.c_int32 * 3), ("colour", C.c_int32 * 3)]
+
+
 _P = C.c_void_p
 _I = C.c_int32
 _D = C.c_double
@@ -48,15 +52,22 @@ SIGNATURES = {
     "kf_volume_destroy": (None, [_P]),
     "kf_integrate": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P]),
     "kf_integrate_batch": (C.c_int, [C.POINTER(Scene), _I, _I, _I, _P]),
+    "kf_brick_shapes": (C.c_int, [_I, _P, _I, C.POINTER(_I)]),
+    "kf_integrate_batch_bricks": (C.c_int, [C.POINTER(Scene), _I, _I, _I, C.POINTER(Bricks), _P]),
     "kf_integrate_batch_noalloc": (C.c_int, [C.POINTER(Scene), _I, _I, _P]),
-    "kf_integrate_batch_counted": (C.c_int, [C.POINTER(Scene), _I, _I, _P, _P]),
-    "kf_integrate_batch_timed": (C.c_int, [C.POINTER(Scene), _I, _I, C.POINTER(C.c_void_p),
-                                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _I,
-                                           _P]),
+    "kf_release_graphs": (C.c_int, [C.POINTER(_I), C.POINTER(C.c_size_t)]),
+    "kf_integrate_batch_counted": (C.c_int, [C.POINTER(Scene), _I, _I, C.POINTER(Bricks), _P, _P]),
+    "kf_integrate_batch_timed": (C.c_int, [C.POINTER(Scene), _I, _I, C.POINTER(Bricks),
+                                           C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), _I, _P]),
     "kf_debug_status": (C.c_int, [_P, _P, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _D, _D, _P, _P, _P]),
     "kf_integrate_backward": (C.c_int, [C.POINTER(VolumeDesc), _P, _I, _P, _P, _I, _I, _I, _I,
                                         _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "kf_se3_compose": (C.c_int, [_P, _P, _P]),
+    "kf_se3_pullback": (C.c_int, [_P, _P, _P]),
     "kf_raycast": (C.c_int, [_P, _I, _I, _P, _P, _D, _P, _P, _P, _P, _P]),
+    "kf_mesh_decimate": (C.c_int, [_P, C.c_int64, _P, C.c_int64, _D, _P, C.POINTER(C.c_int64), _P,
+                                   C.POINTER(C.c_int64)]),
     "kf_texture_layout": (C.c_int, [_I, _P, _D, _I, _P, C.POINTER(_I)]),
     "kf_mesh_extract": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, _P, _P]),
     "kf_texture_generate": (C.c_int, [_P, _I, _P, _P, _I, _I, _P, _P, _P]),

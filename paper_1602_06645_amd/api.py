@@ -202,6 +202,25 @@ class Volume:
         return gs, cs
 
 
+def decimate(vertices, triangles, rate: float):
+    """Quadric-error decimation of a triangle mesh (kf_mesh_decimate, host-only): vertices
+    [n,3] float32 and triangles [m,3] int32 (numpy arrays or tensors, e.g. Volume.mesh());
+    returns numpy (vertices [n',3], triangles [m',3]) with at most round(rate * m)
+    triangles."""
+    V = np.ascontiguousarray(vertices.cpu().numpy() if isinstance(vertices, torch.Tensor)
+                             else vertices, dtype=np.float32).reshape(-1, 3)
+    T = np.ascontiguousarray(triangles.cpu().numpy() if isinstance(triangles, torch.Tensor)
+                             else triangles, dtype=np.int32).reshape(-1, 3)
+    ov = np.zeros((max(len(V), 1), 3), np.float32)
+    ot = np.zeros((max(len(T), 1), 3), np.int32)
+    nv, nt = C.c_int64(), C.c_int64()
+    L.check(L.load().kf_mesh_decimate(V.ctypes.data_as(C.c_void_p), len(V),
+                                      T.ctypes.data_as(C.c_void_p), len(T), float(rate),
+                                      ov.ctypes.data_as(C.c_void_p), C.byref(nv),
+                                      ot.ctypes.data_as(C.c_void_p), C.byref(nt)))
+    return ov[:nv.value].copy(), ot[:nt.value].copy()
+
+
 def texture_layout(tri, size_pixel: float, atlas_height: int):
     """Map sizes and atlas placement (kf_texture_layout, host-only): tri [n,3,3] world
     vertices.  Returns (rects int32 [n,4] = x, y, w, h; the atlas width)."""
@@ -260,11 +279,57 @@ def _scenes(pairs):
     return arr
 
 
-def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False) -> None:
-    """Integrate [(Volume, Scan), ...]: every scan into its own volume, all together."""
+def brick_shapes() -> dict:
+    """The brick shapes (x, y, z voxels) the library's integration kernels are compiled for:
+    {"geometry": [...], "colour": [...]}, the default first (kf_brick_shapes)."""
+    out = {}
+    for kind, name in ((0, "geometry"), (1, "colour")):
+        n = C.c_int32(0)
+        L.check(L.load().kf_brick_shapes(kind, None, 0, C.byref(n)))
+        buf = np.zeros((n.value, 3), np.int32)
+        L.check(L.load().kf_brick_shapes(kind, buf.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        out[name] = [tuple(int(x) for x in row) for row in buf]
+    return out
+
+
+def _bricks(bricks):
+    """kf_bricks from {"geometry": (x, y, z), "colour": (x, y, z)} (either may be left out:
+    the default shape), or None for the defaults."""
+    if bricks is None:
+        return None
+    unknown = set(bricks) - {"geometry", "colour"}
+    if unknown:
+        raise ValueError(f"unknown brick kinds {sorted(unknown)}")
+    defaults = brick_shapes()
+    b = L.Bricks()
+    for field, name in (("geom", "geometry"), ("colour", "colour")):
+        shape = tuple(int(x) for x in bricks.get(name, defaults[name][0]))
+        if len(shape) != 3:
+            raise ValueError(f"{name} brick must be (x, y, z)")
+        getattr(b, field)[:] = shape
+    return C.byref(b)
+
+
+def integrate_batch(pairs, frames_per_pass: int = 1, use_graph: bool = False,
+                    bricks: dict | None = None) -> None:
+    """Integrate [(Volume, Scan), ...]: every scan into its own volume, all together.
+    bricks: brick shapes of the work items (brick_shapes(); None: the defaults), which
+    change the time, never the result."""
     arr = _scenes(pairs)
-    L.check(L.load().kf_integrate_batch(arr, len(pairs), int(frames_per_pass), int(use_graph),
-                                        _stream()))
+    if bricks is None:
+        L.check(L.load().kf_integrate_batch(arr, len(pairs), int(frames_per_pass), int(use_graph),
+                                            _stream()))
+    else:
+        L.check(L.load().kf_integrate_batch_bricks(arr, len(pairs), int(frames_per_pass),
+                                                   int(use_graph), _bricks(bricks), _stream()))
+
+
+def release_graphs() -> tuple:
+    """Drop every recorded batch graph and its workspace (kf_release_graphs): returns
+    (graphs released, workspace bytes freed)."""
+    n, b = C.c_int32(0), C.c_size_t(0)
+    L.check(L.load().kf_release_graphs(C.byref(n), C.byref(b)))
+    return int(n.value), int(b.value)
 
 
 def integrate_batch_noalloc(pairs, frames_per_pass: int = 1) -> None:
@@ -275,7 +340,7 @@ def integrate_batch_noalloc(pairs, frames_per_pass: int = 1) -> None:
                                                 _stream()))
 
 
-def integrate_batch_timed(pairs, frames_per_pass: int, events) -> None:
+def integrate_batch_timed(pairs, frames_per_pass: int, events, bricks: dict | None = None) -> None:
     """integrate_batch that records each pair (start, end) or triple (start, mid, end) of
     `events` (torch.cuda.Event, enable_timing=True) around the integration launches of
     one pass, in order; mid is recorded between the geometry and the colour launch."""
@@ -289,17 +354,18 @@ def integrate_batch_timed(pairs, frames_per_pass: int, events) -> None:
     if n and len(events[0]) == 3:
         mids = (C.c_void_p * n)(*[ev[1].cuda_event for ev in events])
     arr = _scenes(pairs)
-    L.check(L.load().kf_integrate_batch_timed(arr, len(pairs), int(frames_per_pass), starts,
-                                              mids, ends, n, _stream()))
+    L.check(L.load().kf_integrate_batch_timed(arr, len(pairs), int(frames_per_pass),
+                                              _bricks(bricks), starts, mids, ends, n, _stream()))
 
 
-def integrate_batch_counted(pairs, frames_per_pass: int = 1) -> np.ndarray:
+def integrate_batch_counted(pairs, frames_per_pass: int = 1, bricks: dict | None = None) -> np.ndarray:
     """Same as integrate_batch, and return the eight accounting counters (include/kf.h)."""
     arr = _scenes(pairs)
     dev = pairs[0][0].tsdf.device if pairs else torch.device("cuda")
     cnt = torch.zeros(8, dtype=torch.int64, device=dev)
     L.check(L.load().kf_integrate_batch_counted(arr, len(pairs), int(frames_per_pass),
-                                                C.c_void_p(cnt.data_ptr()), _stream()))
+                                                _bricks(bricks), C.c_void_p(cnt.data_ptr()),
+                                                _stream()))
     return cnt.cpu().numpy()
 
 

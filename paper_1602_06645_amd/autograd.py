@@ -5,55 +5,51 @@ returns the colour volume (3 x N_colour, float32) obtained by integrating the fl
 images `rgb` [n,CH,CW,3] with the extrinsic exp(xi^) T_rgb_from_d (xi = (rho, phi) in
 se(3), float64, 6).  Gradients flow to `rgb` and `xi`; both come from the library's
 backward kernel, which returns the gradient for a left perturbation at the current
-extrinsic.  The chain rule to xi itself is the SE(3) left Jacobian (a 6x6 host product).
+extrinsic; kf_se3_pullback maps it to xi itself (the SE(3) left Jacobian) and
+kf_se3_compose forms the perturbed extrinsic.  The library's adjoint replays at most 64
+frames per call, so `rgb` may hold at most 64 frames (the forward alone takes any number).
 """
 from __future__ import annotations
+
+import ctypes as C
 
 import numpy as np
 import torch
 
+from . import _lib as L
 from .api import Scan, Volume, integrate_backward, integrate_batch
 
 
-def _hat3(w):
-    return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
+def _ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
 
 
-def se3_hat(xi) -> np.ndarray:
-    M = np.zeros((4, 4))
-    M[:3, :3] = _hat3(xi[3:])
-    M[:3, 3] = xi[:3]
-    return M
-
-
-def _series(A, coeff, terms=40):
-    out = np.zeros_like(A)
-    P = np.eye(A.shape[0])
-    for k in range(terms):
-        out = out + coeff(k) * P
-        P = P @ A
+def se3_exp_times(xi, T) -> np.ndarray:
+    """exp(xi^) T (kf_se3_compose); T rigid 4x4."""
+    x = np.ascontiguousarray(xi, np.float64).reshape(6)
+    Ti = np.ascontiguousarray(T, np.float64).reshape(4, 4)
+    out = np.zeros((4, 4), np.float64)
+    L.check(L.load().kf_se3_compose(_ptr(x), _ptr(Ti), _ptr(out)))
     return out
 
 
 def se3_exp(xi) -> np.ndarray:
-    """exp of the 4x4 twist (power series, converges for any xi)."""
-    fact = [1.0]
-    for k in range(1, 45):
-        fact.append(fact[-1] * k)
-    return _series(se3_hat(np.asarray(xi, float)), lambda k: 1.0 / fact[k])
+    """exp(xi^) as a 4x4 matrix."""
+    return se3_exp_times(xi, np.eye(4))
+
+
+def se3_pullback(xi, d_eps) -> np.ndarray:
+    """J_l(xi)^T d_eps (kf_se3_pullback)."""
+    x = np.ascontiguousarray(xi, np.float64).reshape(6)
+    d = np.ascontiguousarray(d_eps, np.float64).reshape(6)
+    out = np.zeros(6, np.float64)
+    L.check(L.load().kf_se3_pullback(_ptr(x), _ptr(d), _ptr(out)))
+    return out
 
 
 def se3_left_jacobian(xi) -> np.ndarray:
-    """J_l(xi) = sum_k ad_xi^k / (k+1)!, with ad_xi = [[phi^, rho^], [0, phi^]]."""
-    xi = np.asarray(xi, float)
-    ad = np.zeros((6, 6))
-    ad[:3, :3] = _hat3(xi[3:])
-    ad[:3, 3:] = _hat3(xi[:3])
-    ad[3:, 3:] = _hat3(xi[3:])
-    fact = [1.0]
-    for k in range(1, 45):
-        fact.append(fact[-1] * k)
-    return _series(ad, lambda k: 1.0 / fact[k + 1])
+    """J_l(xi) (6 x 6), column by column through kf_se3_pullback."""
+    return np.stack([se3_pullback(xi, e) for e in np.eye(6)], axis=0)
 
 
 class KFColourFn(torch.autograd.Function):
@@ -61,7 +57,7 @@ class KFColourFn(torch.autograd.Function):
     def forward(ctx, rgb, xi, depth, spec, K_d, K_rgb, T_rgb_from_d, T_world_from_cam,
                 trunc=0.01, w_max=128.0):
         xi_np = xi.detach().double().cpu().numpy()
-        T = se3_exp(xi_np) @ np.asarray(T_rgb_from_d, float)
+        T = se3_exp_times(xi_np, T_rgb_from_d)
         vol = Volume(spec, device=rgb.device)
         scan = Scan(depth, rgb.detach().contiguous(), K_d, K_rgb, T, T_world_from_cam, trunc, w_max)
         integrate_batch([(vol, scan)], frames_per_pass=max(1, scan.depth.shape[0]))
@@ -72,8 +68,7 @@ class KFColourFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad):
         d_rgb, d_eps = integrate_backward(ctx.spec, ctx.scan, grad.contiguous().float())
-        J = se3_left_jacobian(ctx.xi)
-        d_xi = J.T @ d_eps.double().cpu().numpy()
+        d_xi = se3_pullback(ctx.xi, d_eps.double().cpu().numpy())
         dtype, device = ctx.xi_meta
         return (d_rgb, torch.as_tensor(d_xi, dtype=dtype, device=device),
                 None, None, None, None, None, None, None, None)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libkfvol.so")
 SOURCES = ["kf_integrate.hip", "kf_backward.hip", "kf_raycast.hip", "kf_texture.hip",
-           "kf_mesh.hip", "kf_capi.hip"]
+           "kf_mesh.hip", "kf_capi.hip", "kf_decimate.cpp"]
 
 # IEEE single precision everywhere: no contraction into fma beyond the explicit fmaf
 # calls, correctly rounded division and square root, no packed-FP32 instructions.

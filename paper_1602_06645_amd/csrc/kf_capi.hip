@@ -267,7 +267,8 @@ size_t pyramid_entries(const kf::FrameConsts& c)
 
 uint32_t ceil_div(int32_t a, int32_t b) { return (uint32_t)((a + b - 1) / b); }
 
-void scene_dev(const kf_volume* v, int32_t fmt, kf::SceneDev* s)
+// Scene table entry of a volume for bricks of shapes BRICK_SHAPES[kind][shape[kind]].
+void scene_dev(const kf_volume* v, int32_t fmt, const int shape[2], kf::SceneDev* s)
 {
     memset(s, 0, sizeof *s);
     s->tsdf = v->bufs.tsdf;
@@ -280,12 +281,18 @@ void scene_dev(const kf_volume* v, int32_t fmt, kf::SceneDev* s)
         s->gdim[a] = v->desc.geom_dim[a];
         s->cdim[a] = v->desc.colour_dim[a];
     }
-    s->gbricks[0] = (int32_t)ceil_div(s->gdim[0], kf::GBX);
-    s->gbricks[1] = (int32_t)ceil_div(s->gdim[1], kf::GBY);
-    s->gbricks[2] = (int32_t)ceil_div(s->gdim[2], kf::ZS);
-    s->cbricks[0] = (int32_t)ceil_div(s->cdim[0], kf::CBX);
-    s->cbricks[1] = (int32_t)ceil_div(s->cdim[1], kf::CBY);
-    s->cbricks[2] = (int32_t)ceil_div(s->cdim[2], kf::ZS);
+    const kf::BrickShape& gs = kf::BRICK_SHAPES[kf::KIND_GEOM][shape[kf::KIND_GEOM]];
+    const kf::BrickShape& cs = kf::BRICK_SHAPES[kf::KIND_COLOUR][shape[kf::KIND_COLOUR]];
+    s->gshape[0] = gs.bx;
+    s->gshape[1] = gs.by;
+    s->gshape[2] = gs.bz;
+    s->cshape[0] = cs.bx;
+    s->cshape[1] = cs.by;
+    s->cshape[2] = cs.bz;
+    for (int a = 0; a < 3; ++a) {
+        s->gbricks[a] = (int32_t)ceil_div(s->gdim[a], s->gshape[a]);
+        s->cbricks[a] = (int32_t)ceil_div(s->cdim[a], s->cshape[a]);
+    }
     s->geom_items = (uint32_t)s->gbricks[0] * (uint32_t)s->gbricks[1] * (uint32_t)s->gbricks[2];
     s->colour_items = (uint32_t)s->cbricks[0] * (uint32_t)s->cbricks[1] * (uint32_t)s->cbricks[2];
     for (int a = 0; a < 3; ++a) {
@@ -379,7 +386,11 @@ constexpr int32_t kMaxFramesPerPass = 64;
 // queue head of each kind.
 constexpr size_t kPassCounters = 6;
 
-kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchPlan* plan)
+// The default brick shapes (entry 0 of each kind).
+const int kDefaultShapes[2] = {0, 0};
+
+kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, const int shape[2],
+                     BatchPlan* plan)
 {
     if (!scenes && n_scenes > 0) return fail(KF_E_ARG, "scenes is NULL");
     if (n_scenes < 0) return fail(KF_E_ARG, "n_scenes < 0");
@@ -424,7 +435,7 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, BatchP
             const int32_t nf = scenes[s].n_frames - f0;
             if (nf <= 0) continue;
             kf::SceneDev d;
-            scene_dev(scenes[s].vol, scenes[s].fmt, &d);
+            scene_dev(scenes[s].vol, scenes[s].fmt, shape, &d);
             d.frame_begin = first[s] + f0;
             d.n_frames = nf < K ? nf : K;
             d.item_begin = (uint32_t)items;
@@ -503,12 +514,12 @@ void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
 }
 
 // Resident blocks of the geometry ([0]) and colour ([1]) persistent launches.
-kf_status resident_grid(int mode, uint32_t grid[2])
+kf_status resident_grid(int mode, const int shape[2], uint32_t grid[2])
 {
     int device = 0;
     KF_HIP(hipGetDevice(&device), "hipGetDevice");
-    KF_HIP(kf::persistent_grid(mode, kf::KIND_GEOM, device, &grid[0]), "occupancy query");
-    KF_HIP(kf::persistent_grid(mode, kf::KIND_COLOUR, device, &grid[1]), "occupancy query");
+    KF_HIP(kf::persistent_grid(mode, kf::KIND_GEOM, shape[0], device, &grid[0]), "occupancy query");
+    KF_HIP(kf::persistent_grid(mode, kf::KIND_COLOUR, shape[1], device, &grid[1]), "occupancy query");
     return KF_OK;
 }
 
@@ -523,8 +534,8 @@ struct PassEvents {
 // Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`:
 // blocks of the geometry and colour persistent launches (resident_grid).
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
-                         unsigned long long* counters, const uint32_t grid[2], hipStream_t stream,
-                         const PassEvents& ev = PassEvents())
+                         const int shape[2], unsigned long long* counters, const uint32_t grid[2],
+                         hipStream_t stream, const PassEvents& ev = PassEvents())
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
@@ -562,9 +573,9 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         a.counters = counters;
         const bool timed = (int32_t)q < ev.n;
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.start[q], stream), "hipEventRecord");
-        KF_HIP(kf::launch_integrate(mode, kf::KIND_GEOM, a, grid[0], stream), "integrate launch");
+        KF_HIP(kf::launch_integrate(mode, kf::KIND_GEOM, shape[0], a, grid[0], stream), "integrate launch");
         if (timed && ev.mid) KF_HIP(hipEventRecord((hipEvent_t)ev.mid[q], stream), "hipEventRecord");
-        KF_HIP(kf::launch_integrate(mode, kf::KIND_COLOUR, a, grid[1], stream), "integrate launch");
+        KF_HIP(kf::launch_integrate(mode, kf::KIND_COLOUR, shape[1], a, grid[1], stream), "integrate launch");
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.end[q], stream), "hipEventRecord");
     }
     return KF_OK;
@@ -576,22 +587,31 @@ struct GraphEntry {
     std::string key;
     int device = 0;
     unsigned char* dev = nullptr;
+    size_t bytes = 0;
     hipGraphExec_t exec = nullptr;
 };
 
+// Recorded batches, most recently used first.  Each entry owns its graph and the workspace
+// the graph's kernels use (tables, live lists, pyramids and weight maps of every frame), so
+// the cache is bounded by entries and by workspace bytes; the least recently used entries
+// go first (the newest is always kept).
 struct GraphCache {
     std::mutex mu;
     std::list<GraphEntry> lru;
+    size_t bytes = 0;
     hipStream_t capture[64] = {};
 };
 GraphCache g_graphs;
 constexpr size_t kMaxGraphs = 64;
+constexpr size_t kMaxGraphBytes = size_t(4) << 30;
 
-std::string batch_key(const kf_scene* scenes, int32_t n_scenes, int32_t K, int device)
+std::string batch_key(const kf_scene* scenes, int32_t n_scenes, int32_t K, const int shape[2],
+                      int device)
 {
     std::string k;
     auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
     put(&device, sizeof device);
+    put(shape, 2 * sizeof(int));
     put(&n_scenes, sizeof n_scenes);
     put(&K, sizeof K);
     for (int s = 0; s < n_scenes; ++s) {
@@ -615,6 +635,8 @@ std::string batch_key(const kf_scene* scenes, int32_t n_scenes, int32_t K, int d
     return k;
 }
 
+// Destroys an entry's graph and frees its workspace (hipFree waits for the device, so a
+// replay still in flight finishes first).
 void drop_entry(GraphEntry& e)
 {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
@@ -623,12 +645,13 @@ void drop_entry(GraphEntry& e)
     e.dev = nullptr;
 }
 
-kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStream_t stream)
+kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, const int shape[2],
+                    hipStream_t stream)
 {
     int device = 0;
     KF_HIP(hipGetDevice(&device), "hipGetDevice");
     if (device < 0 || device >= 64) return fail(KF_E_UNSUPPORTED, "device index above 63");
-    const std::string key = batch_key(scenes, n_scenes, K, device);
+    const std::string key = batch_key(scenes, n_scenes, K, shape, device);
     std::lock_guard<std::mutex> lock(g_graphs.mu);
     for (auto it = g_graphs.lru.begin(); it != g_graphs.lru.end(); ++it) {
         if (it->key == key) {
@@ -638,19 +661,20 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
         }
     }
     BatchPlan plan;
-    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    kf_status st = plan_batch(scenes, n_scenes, K, shape, &plan);
     if (st != KF_OK) return st;
     DeviceTables t;
     layout_tables(plan, &t);
     GraphEntry e;
     e.key = key;
     e.device = device;
+    e.bytes = t.bytes;
     KF_HIP(hipMalloc(&e.dev, t.bytes), "hipMalloc");
     fill_tables(plan, e.dev, &t);
     hipError_t he = hipMemcpy(e.dev, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipMemcpy"); }
     uint32_t grid[2] = {0, 0};
-    if ((st = resident_grid(kf::MODE_INTEGRATE, grid)) != KF_OK) { drop_entry(e); return st; }
+    if ((st = resident_grid(kf::MODE_INTEGRATE, shape, grid)) != KF_OK) { drop_entry(e); return st; }
     hipStream_t& cs = g_graphs.capture[device];
     if (!cs) {
         he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -658,7 +682,7 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
     }
     he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamBeginCapture"); }
-    st = enqueue_passes(plan, t, e.dev, kf::MODE_INTEGRATE, nullptr, grid, cs);
+    st = enqueue_passes(plan, t, e.dev, kf::MODE_INTEGRATE, shape, nullptr, grid, cs);
     hipGraph_t graph = nullptr;
     he = hipStreamEndCapture(cs, &graph);
     if (st != KF_OK) { if (graph) (void)hipGraphDestroy(graph); drop_entry(e); return st; }
@@ -669,7 +693,10 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
     he = hipGraphLaunch(e.exec, stream);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipGraphLaunch"); }
     g_graphs.lru.push_front(e);
-    while (g_graphs.lru.size() > kMaxGraphs) {
+    g_graphs.bytes += e.bytes;
+    while (g_graphs.lru.size() > 1 &&
+           (g_graphs.lru.size() > kMaxGraphs || g_graphs.bytes > kMaxGraphBytes)) {
+        g_graphs.bytes -= g_graphs.lru.back().bytes;
         drop_entry(g_graphs.lru.back());
         g_graphs.lru.pop_back();
     }
@@ -677,11 +704,11 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStre
 }
 
 kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mode,
-                    unsigned long long* counters, hipStream_t stream,
+                    const int shape[2], unsigned long long* counters, hipStream_t stream,
                     const PassEvents& ev = PassEvents())
 {
     BatchPlan plan;
-    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    kf_status st = plan_batch(scenes, n_scenes, K, shape, &plan);
     if (st != KF_OK) return st;
     if (plan.passes.empty()) return KF_OK;
     if (ev.n > 0 && (size_t)ev.n < plan.passes.size())
@@ -690,12 +717,12 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     DeviceTables t;
     layout_tables(plan, &t);
     uint32_t grid[2] = {0, 0};
-    if ((st = resident_grid(mode, grid)) != KF_OK) return st;
+    if ((st = resident_grid(mode, shape, grid)) != KF_OK) return st;
     unsigned char* dev = nullptr;
     KF_HIP(workspace_alloc((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
-    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, counters, grid, stream, ev);
+    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, shape, counters, grid, stream, ev);
     hipError_t he = hipFreeAsync(dev, stream);
     if (st != KF_OK) return st;
     if (he != hipSuccess) return hip_fail(he, "hipFreeAsync");
@@ -768,7 +795,7 @@ kf_status upload(unsigned char* dst, const unsigned char* src, size_t bytes, hip
 kf_status run_batch_noalloc(const kf_scene* scenes, int32_t n_scenes, int32_t K, hipStream_t stream)
 {
     BatchPlan plan;
-    kf_status st = plan_batch(scenes, n_scenes, K, &plan);
+    kf_status st = plan_batch(scenes, n_scenes, K, kDefaultShapes, &plan);
     if (st != KF_OK) return st;
     if (plan.passes.empty()) return KF_OK;
     DeviceTables t;
@@ -778,12 +805,12 @@ kf_status run_batch_noalloc(const kf_scene* scenes, int32_t n_scenes, int32_t K,
                                 "entry point holds %zu (fewer frames per call or smaller volumes)",
                     t.bytes, kScratchBytes);
     uint32_t grid[2] = {0, 0};
-    if ((st = resident_grid(kf::MODE_INTEGRATE, grid)) != KF_OK) return st;
+    if ((st = resident_grid(kf::MODE_INTEGRATE, kDefaultShapes, grid)) != KF_OK) return st;
     unsigned char* dev = nullptr;
     if ((st = scratch_base(&dev)) != KF_OK) return st;
     fill_tables(plan, dev, &t);
     if ((st = upload(dev, t.host.data(), t.host.size(), stream)) != KF_OK) return st;
-    return enqueue_passes(plan, t, dev, kf::MODE_INTEGRATE, nullptr, grid, stream);
+    return enqueue_passes(plan, t, dev, kf::MODE_INTEGRATE, kDefaultShapes, nullptr, grid, stream);
 }
 
 }  // namespace
@@ -885,7 +912,7 @@ kf_status kf_integrate(kf_volume* vol, const float* depth, int32_t dw, int32_t d
     if (s != KF_OK) return s;
     const kf_scene sc = single_scene(vol, depth, dw, dh, rgb, fmt, cw, ch, K_d, K_rgb,
                                      T_rgb_from_d, T_world_from_cam, trunc_m, w_max);
-    return run_batch(&sc, 1, 1, kf::MODE_INTEGRATE, nullptr, (hipStream_t)stream);
+    return run_batch(&sc, 1, 1, kf::MODE_INTEGRATE, kDefaultShapes, nullptr, (hipStream_t)stream);
 }
 
 kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_t dh,
@@ -901,7 +928,7 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
     if (!geom_status || !colour_status) return fail(KF_E_ARG, "status output is NULL");
     kf::StatusArgs a;
     memset(&a, 0, sizeof a);
-    scene_dev(vol, fmt, &a.scene);
+    scene_dev(vol, fmt, kDefaultShapes, &a.scene);
     a.scene.n_frames = 1;
     frame_consts(vol->desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc_m, w_max, depth,
                  dw, dh, rgb, cw, ch, &a.frame);
@@ -935,19 +962,79 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
     return KF_OK;
 }
 
-kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t frames_per_pass,
-                             int32_t use_graph, void* stream)
+kf_status kf_brick_shapes(int32_t kind, int32_t* shapes, int32_t capacity, int32_t* n_shapes)
 {
+    if (kind != kf::KIND_GEOM && kind != kf::KIND_COLOUR) return fail(KF_E_ARG, "kind must be 0 or 1");
+    if (!n_shapes || capacity < 0 || (capacity > 0 && !shapes)) return fail(KF_E_ARG, "NULL pointer");
+    *n_shapes = kf::N_BRICK_SHAPES;
+    for (int q = 0; q < kf::N_BRICK_SHAPES && q < capacity; ++q) {
+        shapes[3 * q + 0] = kf::BRICK_SHAPES[kind][q].bx;
+        shapes[3 * q + 1] = kf::BRICK_SHAPES[kind][q].by;
+        shapes[3 * q + 2] = kf::BRICK_SHAPES[kind][q].bz;
+    }
+    return KF_OK;
+}
+
+// Shape indices of kf_bricks (NULL: the defaults).
+static kf_status resolve_bricks(const kf_bricks* b, int shape[2])
+{
+    shape[0] = shape[1] = 0;
+    if (!b) return KF_OK;
+    const int32_t* want[2] = {b->geom, b->colour};
+    for (int kind = 0; kind < 2; ++kind) {
+        int found = -1;
+        for (int q = 0; q < kf::N_BRICK_SHAPES && found < 0; ++q) {
+            const kf::BrickShape& s = kf::BRICK_SHAPES[kind][q];
+            if (s.bx == want[kind][0] && s.by == want[kind][1] && s.bz == want[kind][2]) found = q;
+        }
+        if (found < 0)
+            return fail(KF_E_UNSUPPORTED, "%s brick %d x %d x %d is not one of the compiled shapes (kf_brick_shapes)",
+                        kind ? "colour" : "geometry", (int)want[kind][0], (int)want[kind][1], (int)want[kind][2]);
+        shape[kind] = found;
+    }
+    return KF_OK;
+}
+
+kf_status kf_integrate_batch_bricks(const kf_scene* scenes, int32_t n_scenes, int32_t frames_per_pass,
+                                    int32_t use_graph, const kf_bricks* bricks, void* stream)
+{
+    int shape[2];
+    kf_status s = resolve_bricks(bricks, shape);
+    if (s != KF_OK) return s;
     if (use_graph) {
         // validate before looking at the cache, so errors never depend on its state
         BatchPlan probe;
-        kf_status s = plan_batch(scenes, n_scenes, frames_per_pass, &probe);
+        s = plan_batch(scenes, n_scenes, frames_per_pass, shape, &probe);
         if (s != KF_OK) return s;
         if (probe.passes.empty()) return KF_OK;
-        return run_graph(scenes, n_scenes, frames_per_pass, (hipStream_t)stream);
+        return run_graph(scenes, n_scenes, frames_per_pass, shape, (hipStream_t)stream);
     }
-    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, shape, nullptr,
                      (hipStream_t)stream);
+}
+
+kf_status kf_integrate_batch(const kf_scene* scenes, int32_t n_scenes, int32_t frames_per_pass,
+                             int32_t use_graph, void* stream)
+{
+    return kf_integrate_batch_bricks(scenes, n_scenes, frames_per_pass, use_graph, nullptr, stream);
+}
+
+kf_status kf_release_graphs(int32_t* n_released, size_t* bytes_released)
+{
+    std::lock_guard<std::mutex> lock(g_graphs.mu);
+    if (n_released) *n_released = (int32_t)g_graphs.lru.size();
+    if (bytes_released) *bytes_released = g_graphs.bytes;
+    int device = 0;
+    KF_HIP(hipGetDevice(&device), "hipGetDevice");
+    for (GraphEntry& e : g_graphs.lru) {
+        // free each workspace on the device it was allocated on
+        if (e.device != device) (void)hipSetDevice(e.device);
+        drop_entry(e);
+        if (e.device != device) (void)hipSetDevice(device);
+    }
+    g_graphs.lru.clear();
+    g_graphs.bytes = 0;
+    return KF_OK;
 }
 
 kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
@@ -957,10 +1044,13 @@ kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
 }
 
 kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
-                                   int32_t frames_per_pass, void* const* start_events,
-                                   void* const* mid_events, void* const* end_events,
-                                   int32_t n_events, void* stream)
+                                   int32_t frames_per_pass, const kf_bricks* bricks,
+                                   void* const* start_events, void* const* mid_events,
+                                   void* const* end_events, int32_t n_events, void* stream)
 {
+    int shape[2];
+    kf_status s = resolve_bricks(bricks, shape);
+    if (s != KF_OK) return s;
     if (n_events < 1 || !start_events || !end_events) return fail(KF_E_ARG, "events missing");
     for (int32_t q = 0; q < n_events; ++q)
         if (!start_events[q] || !end_events[q] || (mid_events && !mid_events[q]))
@@ -970,16 +1060,19 @@ kf_status kf_integrate_batch_timed(const kf_scene* scenes, int32_t n_scenes,
     ev.mid = mid_events;
     ev.end = end_events;
     ev.n = n_events;
-    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, nullptr,
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_INTEGRATE, shape, nullptr,
                      (hipStream_t)stream, ev);
 }
 
 kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
-                                     int32_t frames_per_pass, unsigned long long* counters,
-                                     void* stream)
+                                     int32_t frames_per_pass, const kf_bricks* bricks,
+                                     unsigned long long* counters, void* stream)
 {
+    int shape[2];
+    kf_status s = resolve_bricks(bricks, shape);
+    if (s != KF_OK) return s;
     if (!counters) return fail(KF_E_ARG, "counters is NULL");
-    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_COUNT, counters,
+    return run_batch(scenes, n_scenes, frames_per_pass, kf::MODE_COUNT, shape, counters,
                      (hipStream_t)stream);
 }
 
@@ -1286,6 +1379,124 @@ kf_status kf_mesh_extract(kf_volume* vol, float* vertices, int64_t vertex_capaci
     if (emit && (counts[0] > vertex_capacity || counts[1] > triangle_capacity))
         return fail(KF_E_RANGE, "mesh of %lld vertices and %lld triangles exceeds the capacities",
                     (long long)counts[0], (long long)counts[1]);
+    return KF_OK;
+}
+
+kf_status kf_mesh_decimate(const float* vertices, int64_t n_vertices, const int32_t* triangles,
+                           int64_t n_triangles, double rate, float* out_vertices,
+                           int64_t* out_n_vertices, int32_t* out_triangles,
+                           int64_t* out_n_triangles)
+{
+    if (!out_n_vertices || !out_n_triangles) return fail(KF_E_ARG, "count outputs are NULL");
+    *out_n_vertices = *out_n_triangles = 0;
+    if (n_vertices < 0 || n_triangles < 0) return fail(KF_E_ARG, "negative mesh size");
+    if (n_vertices > 2147483647LL || n_triangles > 2147483647LL / 3)
+        return fail(KF_E_RANGE, "mesh too large for int32 indices");
+    if ((n_vertices > 0 && !vertices) || (n_triangles > 0 && !triangles))
+        return fail(KF_E_ARG, "input mesh is NULL");
+    if (!out_vertices || !out_triangles) return fail(KF_E_ARG, "output mesh is NULL");
+    if (!isfinite(rate) || rate < 0.0 || rate > 1.0) return fail(KF_E_ARG, "rate must lie in [0, 1]");
+    for (int64_t t = 0; t < n_triangles; ++t) {
+        const int32_t* q = triangles + 3 * t;
+        for (int k = 0; k < 3; ++k)
+            if (q[k] < 0 || q[k] >= n_vertices)
+                return fail(KF_E_ARG, "triangle %lld: vertex index out of range", (long long)t);
+        if (q[0] == q[1] || q[1] == q[2] || q[0] == q[2])
+            return fail(KF_E_ARG, "triangle %lld repeats a vertex", (long long)t);
+    }
+    for (int64_t q = 0; q < 3 * n_vertices; ++q)
+        if (!isfinite(vertices[q])) return fail(KF_E_ARG, "vertex %lld is not finite", (long long)(q / 3));
+    kf::decimate_mesh(vertices, n_vertices, triangles, n_triangles, rate, out_vertices,
+                      out_n_vertices, out_triangles, out_n_triangles);
+    return KF_OK;
+}
+
+// ------------------------------------------------------------------- se(3) helpers
+
+// Power series of a square matrix A (n x n, row-major): sum_k coeff[k] A^k, k < terms.
+static void matrix_series(const double* A, int n, const double* coeff, int terms, double* out)
+{
+    double P[36], Q[36];
+    for (int i = 0; i < n * n; ++i) {
+        P[i] = (i % (n + 1) == 0) ? 1.0 : 0.0;
+        out[i] = 0.0;
+    }
+    for (int k = 0; k < terms; ++k) {
+        for (int i = 0; i < n * n; ++i) out[i] += coeff[k] * P[i];
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+                double acc = 0.0;
+                for (int m = 0; m < n; ++m) acc += P[r * n + m] * A[m * n + c];
+                Q[r * n + c] = acc;
+            }
+        memcpy(P, Q, sizeof(double) * (size_t)(n * n));
+    }
+}
+
+static bool xi_valid(const double* xi)
+{
+    if (!xi || !finite_all(xi, 6)) return false;
+    const double th2 = xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5];
+    return th2 <= 100.0;   // |phi| <= 10 rad: the 40-term series converges to rounding
+}
+
+static void hat3(const double* w, double* M, int ld, int r0, int c0)
+{
+    M[(r0 + 0) * ld + c0 + 1] = -w[2];
+    M[(r0 + 0) * ld + c0 + 2] = w[1];
+    M[(r0 + 1) * ld + c0 + 0] = w[2];
+    M[(r0 + 1) * ld + c0 + 2] = -w[0];
+    M[(r0 + 2) * ld + c0 + 0] = -w[1];
+    M[(r0 + 2) * ld + c0 + 1] = w[0];
+}
+
+constexpr int kSeriesTerms = 40;
+
+kf_status kf_se3_compose(const double xi[6], const double T_in[16], double T_out[16])
+{
+    if (!xi_valid(xi)) return fail(KF_E_ARG, "xi must be finite with |phi| <= 10");
+    kf_status s = check_rigid(T_in, "T_in");
+    if (s != KF_OK) return s;
+    if (!T_out) return fail(KF_E_ARG, "T_out is NULL");
+    // exp of the twist [[phi^, rho], [0, 0]]
+    double A[16] = {0}, E[16], coeff[kSeriesTerms];
+    hat3(xi + 3, A, 4, 0, 0);
+    for (int r = 0; r < 3; ++r) A[r * 4 + 3] = xi[r];
+    coeff[0] = 1.0;
+    for (int k = 1; k < kSeriesTerms; ++k) coeff[k] = coeff[k - 1] / k;
+    matrix_series(A, 4, coeff, kSeriesTerms, E);
+    double out[16];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double acc = 0.0;
+            for (int m = 0; m < 4; ++m) acc += E[r * 4 + m] * T_in[m * 4 + c];
+            out[r * 4 + c] = acc;
+        }
+    out[12] = out[13] = out[14] = 0.0;
+    out[15] = 1.0;
+    memcpy(T_out, out, sizeof out);
+    return KF_OK;
+}
+
+kf_status kf_se3_pullback(const double xi[6], const double d_eps[6], double d_xi[6])
+{
+    if (!xi_valid(xi)) return fail(KF_E_ARG, "xi must be finite with |phi| <= 10");
+    if (!d_eps || !d_xi) return fail(KF_E_ARG, "NULL gradient");
+    // left Jacobian J = sum_k ad^k / (k+1)!, ad = [[phi^, rho^], [0, phi^]]; d_xi = J^T d_eps
+    double ad[36] = {0}, J[36], coeff[kSeriesTerms];
+    hat3(xi + 3, ad, 6, 0, 0);
+    hat3(xi, ad, 6, 0, 3);
+    hat3(xi + 3, ad, 6, 3, 3);
+    coeff[0] = 1.0;
+    for (int k = 1; k < kSeriesTerms; ++k) coeff[k] = coeff[k - 1] / (k + 1);
+    matrix_series(ad, 6, coeff, kSeriesTerms, J);
+    double out[6];
+    for (int c = 0; c < 6; ++c) {
+        double acc = 0.0;
+        for (int r = 0; r < 6; ++r) acc += J[r * 6 + c] * d_eps[r];
+        out[c] = acc;
+    }
+    memcpy(d_xi, out, sizeof out);
     return KF_OK;
 }
 

@@ -7,14 +7,25 @@
 
 namespace kf {
 
-// A brick is the work of one wave64: 64 voxel columns by ZS voxels along z.  Each lane
-// owns one column and keeps the state of its ZS voxels for every frame of a pass.
-// Geometry bricks are 16 x 4 columns (64-byte rows of each state array); colour bricks
-// are 8 x 8 columns, compact enough that most of them are far from the observed surface
-// in a given frame and can be skipped whole.
-constexpr int ZS = 8;
-constexpr int GBX = 16, GBY = 4;
-constexpr int CBX = 8, CBY = 8;
+// A brick is the work of one wave64 in the forward integration: 64 voxel columns (bx x by)
+// of bz voxels along z.  Each lane owns one column and keeps the state of its bz voxels
+// for every frame of a pass.  The integration kernels are compiled for a few shapes per
+// kind (BRICK_SHAPES); results do not depend on the shape, only the work does: longer
+// columns share the per-column part of Eq. 5 among more voxels and hold more state per
+// lane, smaller bricks are culled more finely.  Shape 0 of each kind is the default:
+// geometry 16 x 4 x 8 (64-byte rows of each state array), colour 8 x 8 x 8 (compact, so
+// most bricks are far from the observed surface in a given frame and skipped whole).
+struct BrickShape {
+    int32_t bx, by, bz;
+};
+constexpr int N_BRICK_SHAPES = 5;
+constexpr BrickShape BRICK_SHAPES[2][N_BRICK_SHAPES] = {
+    {{16, 4, 8}, {16, 4, 16}, {32, 2, 8}, {8, 8, 8}, {16, 4, 4}},   // geometry
+    {{8, 8, 8}, {8, 8, 4}, {16, 4, 4}, {16, 4, 8}, {8, 8, 16}},     // colour
+};
+constexpr int MAX_BZ = 16;
+// The adjoint's colour bricks (its own launch and culling): 8 x 8 x 8.
+constexpr int CBX = 8, CBY = 8, ZS = 8;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
 constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
@@ -55,6 +66,7 @@ enum PixFmt : int32_t { FMT_RGB8 = 0, FMT_RGBF32 = 1 };
 struct SceneDev {
     float *tsdf, *wg, *r, *g, *b, *wc;
     int32_t gdim[3], cdim[3];
+    int32_t gshape[3], cshape[3];     // brick shapes (voxels per axis) of the pass
     int32_t gbricks[3], cbricks[3];   // bricks per axis
     uint32_t item_begin;              // first global brick index of this scene in the pass
     uint32_t geom_items;              // geometry bricks; colour bricks follow them

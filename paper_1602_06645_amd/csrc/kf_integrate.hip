@@ -10,7 +10,7 @@
 //      list by the number of frames in the mask;
 //   3. integrate kernels (one launch for geometry bricks, one for colour bricks):
 //      persistent waves take live bricks from the lists, heavy ones first; each lane
-//      keeps its column's ZS voxels in registers for all frames of the pass, reads a
+//      keeps its column's voxels in registers for all frames of the pass, reads a
 //      voxel's state only when a frame first needs it and writes it back only if it was
 //      read.
 // Culling never changes a result: a brick is dropped for a frame only if every voxel in
@@ -20,6 +20,8 @@
 // division and square root, rintf for the nearest depth pixel, floorf for the HD cell.
 // The library is compiled with -ffp-contract=off, so nothing else is fused.
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "kf_cull.h"
 #include "kf_device.h"
@@ -69,8 +71,8 @@ struct Counts {
     unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (same in every lane)
 };
 
-// Voxel column of a lane in brick li of a volume with brick shape BX x BY x ZS.  The
-// brick's z slab (ZS slices from k0) is wave-uniform: state arrays are read through a
+// Voxel column of a lane in brick li of a volume with brick shape BX x BY x BZ.  The
+// brick's z slab (BZ slices from k0) is wave-uniform: state arrays are read through a
 // buffer resource based at the slab, with per-lane byte offsets off + kk * zstride.
 struct Column {
     int i, j, k0, kn;
@@ -79,7 +81,7 @@ struct Column {
     bool active;
 };
 
-template <int BX, int BY, class Dims>
+template <int BX, int BY, int BZ, class Dims>
 __device__ __forceinline__ Column column(const Dims& dim, const Dims& bricks, uint32_t li)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -90,8 +92,8 @@ __device__ __forceinline__ Column column(const Dims& dim, const Dims& bricks, ui
     Column c;
     c.i = (int)bx * BX + lane % BX;
     c.j = (int)by * BY + lane / BX;
-    c.k0 = (int)bz * ZS;
-    c.kn = min(ZS, dim[2] - c.k0);
+    c.k0 = (int)bz * BZ;
+    c.kn = min(BZ, dim[2] - c.k0);
     c.active = c.i < dim[0] && c.j < dim[1];
     c.slice = (size_t)dim[0] * (size_t)dim[1];
     c.slab = (size_t)c.k0 * c.slice;
@@ -154,16 +156,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slab_rsrc(float* p, const Colu
 // frame first updates a voxel, written back at the end if it was read.  Per frame, the
 // eight depth samples of the column are fetched before any of them is used.  MODE_STATUS
 // writes the outcome code of the (single) frame instead.
-template <int MODE, class Scene, class FramePtr>
+template <int MODE, int BX, int BY, int BZ, class Scene, class FramePtr>
 __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
                                            uint32_t li, uint8_t* status, Counts& cnt)
 {
-    const Column col = column<GBX, GBY>(sc.gdim, sc.gbricks, li);
+    static_assert(BX * BY == WAVE && BZ <= MAX_BZ, "one lane per column, masks of 32 bits");
+    const Column col = column<BX, BY, BZ>(sc.gdim, sc.gbricks, li);
     if (!col.active) return;
     const float fi = (float)col.i, fj = (float)col.j;
-    float F[ZS], W[ZS];
+    float F[BZ], W[BZ];
 #pragma unroll
-    for (int kk = 0; kk < ZS; ++kk) F[kk] = W[kk] = 0.0f;
+    for (int kk = 0; kk < BZ; ++kk) F[kk] = W[kk] = 0.0f;
     uint32_t loaded = 0;
     unsigned long long n_upd = 0;
     for (unsigned long long m = mask; m; m &= m - 1) {
@@ -173,11 +176,11 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
         const float cY = fmaf(c.Ag[4], fj, fmaf(c.Ag[3], fi, c.bg[1]));
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
-        float sdf[ZS];
+        float sdf[BZ];
         uint32_t upd = 0;
         auto sweep = [&](auto exact) {
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
+            for (int kk = 0; kk < BZ; ++kk) {
                 const float fk = (float)(col.k0 + kk);
                 const float Zc = fmaf(c.Ag[8], fk, cZ);
                 const Pixel px = project<decltype(exact)::value>(c, fmaf(c.Ag[2], fk, cX),
@@ -196,7 +199,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         };
         // the per-voxel range test of the reciprocal, once per column and frame (a branch
         // every lane takes the same way unless a column reaches the camera plane)
-        if (column_recip_exact(fmaf(c.Ag[8], (float)col.k0, cZ), fmaf(c.Ag[8], (float)(col.k0 + ZS - 1), cZ)))
+        if (column_recip_exact(fmaf(c.Ag[8], (float)col.k0, cZ), fmaf(c.Ag[8], (float)(col.k0 + BZ - 1), cZ)))
             sweep(std::true_type{});
         else
             sweep(std::false_type{});
@@ -205,7 +208,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
             if (need) {
                 const __amdgpu_buffer_rsrc_t tr = slab_rsrc(sc.tsdf, col), wr = slab_rsrc(sc.wg, col);
 #pragma unroll
-                for (int kk = 0; kk < ZS; ++kk) {
+                for (int kk = 0; kk < BZ; ++kk) {
                     const bool nk = (need >> kk) & 1u;
                     const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
                     const float f = load_f32(tr, o), w = load_f32(wr, o);
@@ -215,7 +218,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
                 loaded |= need;
             }
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
+            for (int kk = 0; kk < BZ; ++kk) {
                 if ((upd >> kk) & 1u) {
                     const float t = fminf(1.0f, sdf[kk] * c.inv_trunc);
                     const float wn = W[kk] + 1.0f;
@@ -233,7 +236,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
     }
     if constexpr (MODE != MODE_STATUS) {
 #pragma unroll
-        for (int kk = 0; kk < ZS; ++kk) {
+        for (int kk = 0; kk < BZ; ++kk) {
             if ((loaded >> kk) & 1u) {
                 sc.tsdf[col.base + (size_t)kk * col.slice] = F[kk];
                 sc.wg[col.base + (size_t)kk * col.slice] = W[kk];
@@ -281,16 +284,17 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
 // the voxels in the band; (3) normals and weights, and the first read of the colour
 // weight of the voxels that reach the gate; (4) gate, HD pixel, Eq. 9 and Eq. 10.  The
 // column's colour state lives in registers for the whole pass.
-template <int MODE, class Scene, class FramePtr>
+template <int MODE, int BX, int BY, int BZ, class Scene, class FramePtr>
 __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
                                              uint32_t li, uint8_t* status, Counts& cnt)
 {
-    const Column col = column<CBX, CBY>(sc.cdim, sc.cbricks, li);
+    static_assert(BX * BY == WAVE && BZ <= MAX_BZ, "one lane per column, masks of 32 bits");
+    const Column col = column<BX, BY, BZ>(sc.cdim, sc.cbricks, li);
     if (!col.active) return;
     const float fi = (float)col.i, fj = (float)col.j;
-    float R[ZS], G[ZS], B[ZS], Wt[ZS];
+    float R[BZ], G[BZ], B[BZ], Wt[BZ];
 #pragma unroll
-    for (int kk = 0; kk < ZS; ++kk) R[kk] = G[kk] = B[kk] = Wt[kk] = 0.0f;
+    for (int kk = 0; kk < BZ; ++kk) R[kk] = G[kk] = B[kk] = Wt[kk] = 0.0f;
     uint32_t wl = 0;   // colour weight read
     uint32_t cl = 0;   // colour read and updated (stored at the end)
     unsigned long long n_eval = 0, n_upd = 0;
@@ -300,13 +304,13 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
-        int st[ZS];
+        int st[BZ];
         // (1) Eq. 5-7 and the distance test against sigma.
-        uint32_t poff[ZS];   // byte offset of the depth pixel of voxels in the band
+        uint32_t poff[BZ];   // byte offset of the depth pixel of voxels in the band
         uint32_t band = 0;
         auto sweep = [&](auto exact) {
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
+            for (int kk = 0; kk < BZ; ++kk) {
                 const float fk = (float)(col.k0 + kk);
                 const float Xc = fmaf(c.Ac[2], fk, cX);
                 const float Yc = fmaf(c.Ac[5], fk, cY);
@@ -327,7 +331,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         };
         // the per-voxel range test of the reciprocal, once per column and frame (a branch
         // every lane takes the same way unless a column reaches the camera plane)
-        if (column_recip_exact(fmaf(c.Ac[8], (float)col.k0, cZ), fmaf(c.Ac[8], (float)(col.k0 + ZS - 1), cZ)))
+        if (column_recip_exact(fmaf(c.Ac[8], (float)col.k0, cZ), fmaf(c.Ac[8], (float)(col.k0 + BZ - 1), cZ)))
             sweep(std::true_type{});
         else
             sweep(std::false_type{});
@@ -336,10 +340,10 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             // (u+1, v) and (u, v+1); unit normal . unit viewing direction), computed once
             // per pixel by weight_map_kernel in the same operations.
             const __amdgpu_buffer_rsrc_t wmap = image_rsrc(c.wmap, (uint32_t)(c.dw * c.dh) * 4u);
-            float wv[ZS];
+            float wv[BZ];
             uint32_t reach = 0;
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
+            for (int kk = 0; kk < BZ; ++kk) {
                 wv[kk] = load_f32(wmap, poff[kk]);
                 const bool ok = ((band >> kk) & 1u) & (__builtin_bit_cast(uint32_t, wv[kk]) != kNoNormal);
                 reach |= (uint32_t)ok << kk;
@@ -348,7 +352,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             if (needw) {
                 const __amdgpu_buffer_rsrc_t wr = slab_rsrc(sc.wc, col);
 #pragma unroll
-                for (int kk = 0; kk < ZS; ++kk) {
+                for (int kk = 0; kk < BZ; ++kk) {
                     const bool nk = (needw >> kk) & 1u;
                     const float w = load_f32(wr, nk ? col.off + (uint32_t)kk * col.zstride : kOutside);
                     Wt[kk] = nk ? w : Wt[kk];
@@ -358,10 +362,10 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             n_eval += (unsigned)__builtin_popcount(reach);
             // (4) gate, HD pixel of the voxel centre (Eq. 3-5), bilinear cell inside the image.
             uint32_t upd = 0;
-            int cell[ZS];
-            float ax[ZS], ay[ZS];
+            int cell[BZ];
+            float ax[BZ], ay[BZ];
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk) {
+            for (int kk = 0; kk < BZ; ++kk) {
                 cell[kk] = 0;
                 ax[kk] = ay[kk] = 0.0f;
                 if ((reach >> kk) & 1u) {
@@ -385,7 +389,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                     const __amdgpu_buffer_rsrc_t rr = slab_rsrc(sc.r, col), gr = slab_rsrc(sc.g, col),
                                                  br = slab_rsrc(sc.b, col);
 #pragma unroll
-                    for (int kk = 0; kk < ZS; ++kk) {
+                    for (int kk = 0; kk < BZ; ++kk) {
                         const bool nk = (needc >> kk) & 1u;
                         const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
                         const float r = load_f32(rr, o), g = load_f32(gr, o), b = load_f32(br, o);
@@ -398,7 +402,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 const int row = c.cw * 3;
                 const bool nearest = c.hd_nearest != 0;
 #pragma unroll
-                for (int kk = 0; kk < ZS; ++kk) {
+                for (int kk = 0; kk < BZ; ++kk) {
                     if ((upd >> kk) & 1u) {
                         const float s0 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 0, ax[kk], ay[kk]);
                         const float s1 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 1, ax[kk], ay[kk]);
@@ -415,13 +419,13 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         }
         if constexpr (MODE == MODE_STATUS) {
 #pragma unroll
-            for (int kk = 0; kk < ZS; ++kk)
+            for (int kk = 0; kk < BZ; ++kk)
                 if (kk < col.kn) status[col.base + (size_t)kk * col.slice] = (uint8_t)st[kk];
         }
     }
     if constexpr (MODE != MODE_STATUS) {
 #pragma unroll
-        for (int kk = 0; kk < ZS; ++kk) {
+        for (int kk = 0; kk < BZ; ++kk) {
             if ((cl >> kk) & 1u) {
                 const size_t idx = col.base + (size_t)kk * col.slice;
                 sc.r[idx] = R[kk];
@@ -474,7 +478,8 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
     const int32_t* dim = colour ? sc.cdim : sc.gdim;
     const int32_t* nb = colour ? sc.cbricks : sc.gbricks;
     const int32_t* nc = colour ? sc.cchunks : sc.gchunks;
-    const int BX = colour ? CBX : GBX, BY = colour ? CBY : GBY;
+    const int32_t* shape = colour ? sc.cshape : sc.gshape;
+    const int BX = shape[0], BY = shape[1], BZ = shape[2];
     const int bx0 = (int)(lc % (uint32_t)nc[0]) * CHUNK;
     const int by0 = (int)((lc / (uint32_t)nc[0]) % (uint32_t)nc[1]) * CHUNK;
     const int bz0 = (int)(lc / ((uint32_t)nc[0] * (uint32_t)nc[1])) * CHUNK;
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
         if (lane < sc.n_frames) {
             const int i0 = bx0 * BX, i1 = min(dim[0], (bx0 + nbx) * BX) - 1;
             const int j0 = by0 * BY, j1 = min(dim[1], (by0 + nby) * BY) - 1;
-            const int k0 = bz0 * ZS, k1 = min(dim[2], (bz0 + nbz) * ZS) - 1;
+            const int k0 = bz0 * BZ, k1 = min(dim[2], (bz0 + nbz) * BZ) - 1;
             live = a.disable || brick_live(frames[lane], colour, i0, i1, j0, j1, k0, k1);
         }
         const unsigned long long m = __ballot(live);
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
         const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
         const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
         const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
-        const int k0 = bz * ZS, k1 = min(dim[2], k0 + ZS) - 1;
+        const int k0 = bz * BZ, k1 = min(dim[2], k0 + BZ) - 1;
         if (a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1))
             atomicOr(&s_mask[q], 1ull << f);
     }
@@ -634,10 +639,12 @@ __global__ __launch_bounds__(BLOCK) void weight_map_kernel(const FrameConsts* fr
 
 // ------------------------------------------------------------------------ integration
 
-// Persistent waves: each takes (brick, frame mask) entries of one kind from the live list.
-template <int MODE, int KIND>
+// Persistent waves: each takes (brick, frame mask) entries of one kind from the live list;
+// bricks have shape BRICK_SHAPES[KIND][SHAPE].
+template <int MODE, int KIND, int SHAPE>
 __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
+    constexpr BrickShape S = BRICK_SHAPES[KIND][SHAPE];
     const int lane = threadIdx.x & (WAVE - 1);
     Counts cnt;
     // the heavy list first, then the light one
@@ -659,18 +666,20 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
         const const_ptr<FrameConsts> frames = as_const(a.frames) + sc.frame_begin;
         const uint32_t li = item - sc.item_begin;
         if constexpr (KIND == KIND_GEOM) {
-            geom_brick<MODE>(sc, frames, fmask, li, nullptr, cnt);
+            geom_brick<MODE, S.bx, S.by, S.bz>(sc, frames, fmask, li, nullptr, cnt);
             if constexpr (MODE == MODE_COUNT) cnt.g_bricks += (unsigned)__builtin_popcountll(fmask);
         } else {
-            colour_brick<MODE>(sc, frames, fmask, li - sc.geom_items, nullptr, cnt);
+            colour_brick<MODE, S.bx, S.by, S.bz>(sc, frames, fmask, li - sc.geom_items, nullptr, cnt);
             if constexpr (MODE == MODE_COUNT) cnt.c_bricks += (unsigned)__builtin_popcountll(fmask);
         }
     }
     if constexpr (MODE == MODE_COUNT) {
+        // brick-frames in units of 512 voxels, whatever the brick's size
+        constexpr unsigned long long vox = (unsigned long long)WAVE * S.bz;
         const unsigned long long v[8] = {wave_sum(cnt.g_upd), wave_sum(cnt.g_touch),
                                          wave_sum(cnt.c_eval), wave_sum(cnt.c_read),
                                          wave_sum(cnt.c_upd), wave_sum(cnt.c_touch),
-                                         cnt.g_bricks, cnt.c_bricks};
+                                         cnt.g_bricks * vox, cnt.c_bricks * vox};
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < 8; ++q)
@@ -679,7 +688,8 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
     }
 }
 
-// Outcome codes of one frame for every brick of one kind (no culling, no update).
+// Outcome codes of one frame for every brick of one kind (no culling, no update), with
+// the default brick shapes.
 template <bool COLOUR>
 __global__ __launch_bounds__(BLOCK) void status_kernel(StatusArgs a)
 {
@@ -687,10 +697,11 @@ __global__ __launch_bounds__(BLOCK) void status_kernel(StatusArgs a)
     if (li >= a.n_items) return;
     Counts cnt;
     const FrameConsts* frames = &a.frame;
+    constexpr BrickShape S = BRICK_SHAPES[COLOUR ? KIND_COLOUR : KIND_GEOM][0];
     if constexpr (COLOUR)
-        colour_brick<MODE_STATUS>(a.scene, frames, 1u, li, a.status, cnt);
+        colour_brick<MODE_STATUS, S.bx, S.by, S.bz>(a.scene, frames, 1u, li, a.status, cnt);
     else
-        geom_brick<MODE_STATUS>(a.scene, frames, 1u, li, a.status, cnt);
+        geom_brick<MODE_STATUS, S.bx, S.by, S.bz>(a.scene, frames, 1u, li, a.status, cnt);
 }
 
 __global__ void fill_f32_kernel(float* p, size_t n, float v)
@@ -739,21 +750,49 @@ hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(int mode, int kind, const IntegrateArgs& a, uint32_t grid,
+// Launch and occupancy query of each integration kernel, by (mode, kind, shape).
+template <int MODE, int KIND, int SHAPE>
+static hipError_t launch_one(const IntegrateArgs& a, uint32_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((integrate_kernel<MODE, KIND, SHAPE>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int MODE, int KIND, int SHAPE>
+static hipError_t occupancy_one(int* per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, integrate_kernel<MODE, KIND, SHAPE>, BLOCK, 0);
+}
+
+struct IntegrateEntry {
+    hipError_t (*launch)(const IntegrateArgs&, uint32_t, hipStream_t);
+    hipError_t (*occupancy)(int*);
+};
+
+template <int MODE, int KIND, int... SH>
+static const IntegrateEntry* entry_row(std::integer_sequence<int, SH...>)
+{
+    static const IntegrateEntry row[] = {{launch_one<MODE, KIND, SH>, occupancy_one<MODE, KIND, SH>}...};
+    return row;
+}
+
+static const IntegrateEntry* integrate_entry(int mode, int kind, int shape)
+{
+    if (shape < 0 || shape >= N_BRICK_SHAPES) return nullptr;
+    using Seq = std::make_integer_sequence<int, N_BRICK_SHAPES>;
+    if (mode == MODE_INTEGRATE && kind == KIND_GEOM) return entry_row<MODE_INTEGRATE, KIND_GEOM>(Seq{}) + shape;
+    if (mode == MODE_INTEGRATE && kind == KIND_COLOUR) return entry_row<MODE_INTEGRATE, KIND_COLOUR>(Seq{}) + shape;
+    if (mode == MODE_COUNT && kind == KIND_GEOM) return entry_row<MODE_COUNT, KIND_GEOM>(Seq{}) + shape;
+    if (mode == MODE_COUNT && kind == KIND_COLOUR) return entry_row<MODE_COUNT, KIND_COLOUR>(Seq{}) + shape;
+    return nullptr;
+}
+
+hipError_t launch_integrate(int mode, int kind, int shape, const IntegrateArgs& a, uint32_t grid,
                             hipStream_t stream)
 {
     if (grid == 0) return hipSuccess;
-    if (mode == MODE_INTEGRATE && kind == KIND_GEOM)
-        hipLaunchKernelGGL((integrate_kernel<MODE_INTEGRATE, KIND_GEOM>), dim3(grid), dim3(BLOCK), 0, stream, a);
-    else if (mode == MODE_INTEGRATE && kind == KIND_COLOUR)
-        hipLaunchKernelGGL((integrate_kernel<MODE_INTEGRATE, KIND_COLOUR>), dim3(grid), dim3(BLOCK), 0, stream, a);
-    else if (mode == MODE_COUNT && kind == KIND_GEOM)
-        hipLaunchKernelGGL((integrate_kernel<MODE_COUNT, KIND_GEOM>), dim3(grid), dim3(BLOCK), 0, stream, a);
-    else if (mode == MODE_COUNT && kind == KIND_COLOUR)
-        hipLaunchKernelGGL((integrate_kernel<MODE_COUNT, KIND_COLOUR>), dim3(grid), dim3(BLOCK), 0, stream, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    const IntegrateEntry* e = integrate_entry(mode, kind, shape);
+    return e ? e->launch(a, grid, stream) : hipErrorInvalidValue;
 }
 
 hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream)
@@ -767,19 +806,14 @@ hipError_t launch_status(bool colour, const StatusArgs& a, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t persistent_grid(int mode, int kind, int device, uint32_t* blocks)
+hipError_t persistent_grid(int mode, int kind, int shape, int device, uint32_t* blocks)
 {
     int n_cu = 0, per_cu = 0;
     hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    const void* fn = nullptr;
-    if (mode == MODE_INTEGRATE && kind == KIND_GEOM) fn = (const void*)integrate_kernel<MODE_INTEGRATE, KIND_GEOM>;
-    else if (mode == MODE_INTEGRATE && kind == KIND_COLOUR) fn = (const void*)integrate_kernel<MODE_INTEGRATE, KIND_COLOUR>;
-    else if (mode == MODE_COUNT && kind == KIND_GEOM) fn = (const void*)integrate_kernel<MODE_COUNT, KIND_GEOM>;
-    else if (mode == MODE_COUNT && kind == KIND_COLOUR) fn = (const void*)integrate_kernel<MODE_COUNT, KIND_COLOUR>;
-    else return hipErrorInvalidValue;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BLOCK, 0);
-    if (e != hipSuccess) return e;
+    const IntegrateEntry* k = integrate_entry(mode, kind, shape);
+    if (!k) return hipErrorInvalidValue;
+    if ((e = k->occupancy(&per_cu)) != hipSuccess) return e;
     *blocks = (uint32_t)(n_cu * (per_cu > 0 ? per_cu : 1));
     return hipSuccess;
 }

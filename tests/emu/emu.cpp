@@ -54,6 +54,7 @@ thread_local dim3 threadIdx, blockIdx, blockDim, gridDim;
 #include "kf_texture.hip"
 #include "kf_mesh.hip"
 #include "kf_capi.hip"
+#include "kf_decimate.cpp"
 
 namespace emu {
 
@@ -197,17 +198,25 @@ static void run_block_fibers(Block& B, unsigned n, const std::function<void()>& 
     g_blk = nullptr;
 }
 
+template <int MODE, int KIND, int... SH>
+static bool is_integrate(const void* k, std::integer_sequence<int, SH...>)
+{
+    return ((k == (const void*)kf::integrate_kernel<MODE, KIND, SH>) || ...);
+}
+
 static bool needs_fibers(const void* k)
 {
+    using Seq = std::make_integer_sequence<int, kf::N_BRICK_SHAPES>;
+    if (is_integrate<kf::MODE_INTEGRATE, kf::KIND_GEOM>(k, Seq{}) ||
+        is_integrate<kf::MODE_INTEGRATE, kf::KIND_COLOUR>(k, Seq{}) ||
+        is_integrate<kf::MODE_COUNT, kf::KIND_GEOM>(k, Seq{}) ||
+        is_integrate<kf::MODE_COUNT, kf::KIND_COLOUR>(k, Seq{}))
+        return true;
     static const void* list[] = {
         (const void*)kf::pyramid_up_kernel,
         (const void*)kf::cull_kernel,
         (const void*)kf::backward_cull_kernel,
         (const void*)kf::reduce_xi_kernel,
-        (const void*)kf::integrate_kernel<kf::MODE_INTEGRATE, kf::KIND_GEOM>,
-        (const void*)kf::integrate_kernel<kf::MODE_INTEGRATE, kf::KIND_COLOUR>,
-        (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_GEOM>,
-        (const void*)kf::integrate_kernel<kf::MODE_COUNT, kf::KIND_COLOUR>,
         (const void*)kf::texture_kernel,
         (const void*)kf::mc_classify_kernel,
         (const void*)kf::mc_block_sums_kernel,
@@ -270,6 +279,7 @@ void run_grid(const void* kernel, dim3 grid, dim3 block, const std::function<voi
 
 // ---------------------------------------------------------------- runtime API
 hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidDevice; }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 8; return hipSuccess; }
 hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) { *n = 1; return hipSuccess; }
 hipError_t hipMallocAsync(void** p, size_t n, hipStream_t) { *p = malloc(n ? n : 1); return *p ? hipSuccess : 2; }

@@ -190,7 +190,7 @@ inline float emu_rcpf(float x) { return 1.0f / x; }
 
 // ---------------------------------------------------------------- runtime API
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorNotSupported = 801 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101, hipErrorNotSupported = 801 };
 typedef struct emu_stream* hipStream_t;
 typedef struct emu_event* hipEvent_t;
 typedef struct emu_graph* hipGraph_t;
@@ -201,6 +201,7 @@ enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipHostMallocDefault
 enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal = 1 };
 
 hipError_t hipGetDevice(int* d);
+hipError_t hipSetDevice(int d);
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int d);
 hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* f, int block, size_t sh);
 template <class F>

@@ -55,11 +55,15 @@ def scene(vol, fr, keep):
     return s
 
 
-def forward_case(pairs, K, specs=None, noalloc=False):
+def forward_case(pairs, K, specs=None, noalloc=False, bricks=None):
     keep = []
     arr = (L.Scene * len(pairs))(*[scene(v, f, keep) for v, f in pairs])
     if noalloc:
         check(lib.kf_integrate_batch_noalloc(arr, len(pairs), K, None))
+    elif bricks is not None:
+        b = L.Bricks()
+        b.geom[:], b.colour[:] = bricks
+        check(lib.kf_integrate_batch_bricks(arr, len(pairs), K, 0, C.byref(b), None))
     else:
         check(lib.kf_integrate_batch(arr, len(pairs), K, 0, None))
     worst = 0
@@ -268,6 +272,21 @@ out["noalloc_mismatches"] = (
                  noalloc=True)
     + forward_case([(Vol(spec6), fr6)], 4, [spec6], noalloc=True))
 tick("no-alloc")
+# every compiled brick shape (paired by list position) on the odd-sized volume and the
+# 6-frame scan: partial bricks on every axis, bit for bit with the oracle
+n = C.c_int32(0)
+shapes = []
+for kind in (0, 1):
+    check(lib.kf_brick_shapes(kind, None, 0, C.byref(n)))
+    buf = np.zeros((n.value, 3), np.int32)
+    check(lib.kf_brick_shapes(kind, buf.ctypes.data, n.value, C.byref(n)))
+    shapes.append([tuple(int(x) for x in r) for r in buf])
+out["shape_mismatches"] = 0
+for q in range(1, max(len(shapes[0]), len(shapes[1]))):
+    pair = (shapes[0][min(q, len(shapes[0]) - 1)], shapes[1][min(q, len(shapes[1]) - 1)])
+    out["shape_mismatches"] += forward_case([(Vol(spec6), fr6), (Vol(spec_odd), fr32)], 8,
+                                            [spec6, spec_odd], bricks=pair)
+tick("brick shapes")
 out["status_mismatches"] = status_case(spec6, fr6)
 tick("status")
 # nearest-pixel HD sampling: an 8-bit scan and a float one on the odd volume
@@ -283,6 +302,25 @@ out["texture_mismatches"] = texture_case(spec6, fr6)
 tick("texture")
 out["mesh_mismatches"] = mesh_case(spec6, fr6, spec_odd)
 tick("mesh")
+# quadric-error decimation (host code of the library) of the oracle's marching-cubes mesh
+# of the 6-frame scan, against the oracle's decimation, bit for bit
+st = O.State(spec6, np.float32)
+O.integrate(spec6, fr6, st)
+V, T = O.marching_cubes(spec6, st.tsdf, st.wg, "f32")
+out["decimate_mismatches"] = 0
+for rate in (0.3, 0.05):
+    ov = np.zeros_like(V)
+    ot = np.zeros_like(T)
+    nv, nt = C.c_int64(), C.c_int64()
+    check(lib.kf_mesh_decimate(V.ctypes.data, len(V), T.ctypes.data, len(T), rate, ov.ctypes.data,
+                               C.byref(nv), ot.ctypes.data, C.byref(nt)))
+    wv, wt = O.decimate(V, T, rate)
+    if (nv.value, nt.value) != (len(wv), len(wt)):
+        out["decimate_mismatches"] += 1_000_000
+    else:
+        out["decimate_mismatches"] += int(np.count_nonzero(ov[:nv.value].view(np.uint32) != wv.view(np.uint32)))
+        out["decimate_mismatches"] += int(np.count_nonzero(ot[:nt.value] != wt))
+tick("decimation")
 out["backward_6"] = backward_case(spec6, fr6, pose=True)
 tick("backward 6")
 out["backward_32"] = backward_case(spec32, fr32)

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "kf.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(kf_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -148,7 +148,7 @@ def test_batch_rejects_bad_arguments():
         assert lib.kf_integrate_batch(sc, 1, 0, 0, None) == L.KF_E_ARG   # K < 1
         sc[0].n_frames = -1
         assert lib.kf_integrate_batch(sc, 1, 1, 0, None) == L.KF_E_ARG
-        assert lib.kf_integrate_batch_counted(sc, 1, 1, None, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_counted(sc, 1, 1, None, None, None) == L.KF_E_ARG
     finally:
         lib.kf_volume_destroy(h)
 
@@ -183,6 +183,51 @@ def test_noalloc_batch_refuses_workspace_above_its_array():
         lib.kf_volume_destroy(h)
 
 
+def test_brick_shapes_are_listed_and_checked():
+    """kf_brick_shapes lists the compiled shapes (default first, 64 columns each); a shape
+    outside the list is KF_E_UNSUPPORTED before any device work (fake buffers)."""
+    lib = L.load()
+    for kind in (0, 1):
+        n = C.c_int32(0)
+        assert lib.kf_brick_shapes(kind, None, 0, C.byref(n)) == L.KF_OK and n.value >= 2
+        buf = np.zeros((n.value, 3), np.int32)
+        assert lib.kf_brick_shapes(kind, buf.ctypes.data, n.value, C.byref(n)) == L.KF_OK
+        assert all(x * y == 64 for x, y, _ in buf)
+        assert len({tuple(r) for r in buf}) == n.value
+    assert tuple(buf[0]) == (8, 8, 8)
+    assert lib.kf_brick_shapes(2, None, 0, C.byref(n)) == L.KF_E_ARG
+    h = _volume()
+    try:
+        sc = (L.Scene * 1)()
+        sc[0].vol = h.value
+        sc[0].n_frames = 0
+        b = L.Bricks()
+        b.geom[:] = (16, 4, 8)
+        b.colour[:] = (4, 4, 4)
+        assert lib.kf_integrate_batch_bricks(sc, 1, 1, 0, C.byref(b), None) == L.KF_E_UNSUPPORTED
+        assert b"not one of the compiled shapes" in lib.kf_last_error()
+        b.colour[:] = (8, 8, 8)
+        b.geom[:] = (8, 8, 32)
+        assert lib.kf_integrate_batch_bricks(sc, 1, 1, 0, C.byref(b), None) == L.KF_E_UNSUPPORTED
+        assert lib.kf_integrate_batch_counted(sc, 1, 1, C.byref(b), None, None) == L.KF_E_UNSUPPORTED
+    finally:
+        lib.kf_volume_destroy(h)
+
+
+def test_autotune_entries_are_keyed_by_architecture(tmp_path):
+    import json
+    from paper_1602_06645_amd import autotune
+    path = tmp_path / "tuning.json"
+    path.write_text(json.dumps({"gfx950": {"fused": {"frames_per_pass": 48, "bricks": {
+        "geometry": [32, 2, 8], "colour": [8, 8, 4]}}}}))
+    assert autotune.frames_per_pass("fused", arch="gfx950", path=str(path)) == 48
+    assert autotune.bricks("fused", arch="gfx950", path=str(path)) == {"geometry": (32, 2, 8),
+                                                                      "colour": (8, 8, 4)}
+    assert autotune.frames_per_pass("fused", default=7, arch="gfx942", path=str(path)) == 7
+    assert autotune.bricks("fused", arch="gfx942", path=str(path)) is None
+    assert autotune.bricks("kinect", arch="gfx950", path=str(path)) is None
+
+
 def test_timed_batch_rejects_bad_arguments():
     """Event arrays are checked, and too few events for the passes is an argument error
     returned before any device work (the volume buffers here are fake addresses)."""
@@ -202,13 +247,13 @@ def test_timed_batch_rejects_bad_arguments():
         sc[0].T_rgb_from_d, sc[0].T_world_from_cam = T.ctypes.data, poses.ctypes.data
         sc[0].trunc_m, sc[0].w_max = 0.01, 128.0
         ev = (C.c_void_p * 3)(0x10, 0x20, 0x30)
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, None, ev, 3, None) == L.KF_E_ARG
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, None, ev, 0, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, None, None, ev, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, None, ev, 0, None) == L.KF_E_ARG
         holey = (C.c_void_p * 3)(0x10, None, 0x30)
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, None, holey, 3, None) == L.KF_E_ARG
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, holey, ev, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, None, holey, 3, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, holey, ev, 3, None) == L.KF_E_ARG
         # K = 1 makes three passes; two events are too few
-        assert lib.kf_integrate_batch_timed(sc, 1, 1, ev, ev, ev, 2, None) == L.KF_E_ARG
+        assert lib.kf_integrate_batch_timed(sc, 1, 1, None, ev, ev, ev, 2, None) == L.KF_E_ARG
         assert b"below the number of passes" in lib.kf_last_error()
     finally:
         lib.kf_volume_destroy(h)
@@ -389,3 +434,37 @@ def test_binding_rejects_rgb_without_three_interleaved_channels(shape):
     with pytest.raises(ValueError, match="CUDA/HIP tensor"):
         api.Scan(depth, torch.zeros((2, 24, 32, 3), dtype=torch.uint8), eye, eye, np.eye(4),
                  np.stack([np.eye(4)] * 2), 0.01, 64)
+
+
+def test_se3_helpers_against_expm_and_differences():
+    """kf_se3_compose equals scipy's matrix exponential of the twist times T; kf_se3_pullback
+    maps the gradient for a left perturbation at exp(xi^) T to the gradient in xi, checked
+    by central differences of a linear function of the composed transform."""
+    from scipy.linalg import expm
+    from paper_1602_06645_amd.autograd import se3_exp_times, se3_pullback
+
+    def twist(x):
+        M = np.zeros((4, 4))
+        M[:3, :3] = [[0, -x[5], x[4]], [x[5], 0, -x[3]], [-x[4], x[3], 0]]
+        M[:3, 3] = x[:3]
+        return M
+    rng = np.random.default_rng(7)
+    T = expm(twist(rng.normal(size=6)))
+    W = rng.normal(size=(4, 4))
+    f = lambda M: float((W * M).sum())                      # noqa: E731
+    for scale in (1e-3, 0.3, 2.0):
+        xi = rng.normal(size=6) * scale
+        np.testing.assert_allclose(se3_exp_times(xi, T), expm(twist(xi)) @ T, atol=1e-12)
+        base = expm(twist(xi)) @ T
+        h = 1e-6
+        d_eps = np.array([(f(expm(twist(h * e)) @ base) - f(expm(twist(-h * e)) @ base)) / (2 * h)
+                          for e in np.eye(6)])
+        d_xi = np.array([(f(expm(twist(xi + h * e)) @ T) - f(expm(twist(xi - h * e)) @ T)) / (2 * h)
+                         for e in np.eye(6)])
+        np.testing.assert_allclose(se3_pullback(xi, d_eps), d_xi, rtol=1e-6, atol=1e-6)
+    lib = L.load()
+    bad = np.array([0, 0, 0, 20.0, 0, 0])
+    out = np.zeros(16)
+    assert lib.kf_se3_compose(bad.ctypes.data, np.eye(4).ctypes.data, out.ctypes.data) == L.KF_E_ARG
+    assert lib.kf_se3_compose(np.zeros(6).ctypes.data, np.diag([1.0, 1, 2, 1]).ctypes.data,
+                              out.ctypes.data) == L.KF_E_ARG

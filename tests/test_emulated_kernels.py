@@ -5,11 +5,12 @@ without a GPU that the kernels' logic equals the oracle (bit for bit in the forw
 the adjoint tolerance in the backward) and touches no memory outside its buffers: two
 scans and an odd-sized volume (partial bricks and culling chunks) in one batch (RGB8 and
 float images, 6 and 32 frames, 8 frames per pass), passes of more than 32 frames (40
-frames at 36 per pass), the allocation-free entry point on two batches in a row, the
-per-voxel outcome codes of every frame of a scan, the ray cast of an integrated volume, and
-the adjoint over 6 and 32 frames (a
-live frame in bit 31 of a brick's frame mask), with its image gradient added per HD tile
-from records, scattered with atomics, and both (a record buffer that runs out)."""
+frames at 36 per pass), every compiled brick shape on the odd-sized volume, the
+allocation-free entry point on two batches in a row, the per-voxel outcome codes of every
+frame of a scan, the ray cast of an integrated volume, the quadric-error decimation of its
+marching-cubes mesh, and the adjoint over 6 and 32 frames (a live frame in bit 31 of a
+brick's frame mask), with its image gradient added per HD tile from records, scattered
+with atomics, and both (a record buffer that runs out)."""
 import json
 import os
 import subprocess
@@ -49,11 +50,13 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert res["forward_mismatches"] == 0
     assert res["wide_pass_mismatches"] == 0
     assert res["noalloc_mismatches"] == 0
+    assert res["shape_mismatches"] == 0
     assert res["status_mismatches"] == 0
     assert res["raycast_mismatches"] == 0
     assert res["texture_mismatches"] == 0
     assert res["nearest_mismatches"] == 0 and res["nearest_status_mismatches"] == 0
     assert res["mesh_mismatches"] == 0
+    assert res["decimate_mismatches"] == 0
     for case in ("backward_6", "backward_32", "backward_odd", "backward_direct", "backward_overflow"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
     for case in ("backward_6", "backward_odd", "backward_direct", "backward_overflow"):

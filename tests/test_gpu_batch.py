@@ -72,6 +72,23 @@ def test_graph_replays_match_eager():
         assert_bitwise(to_host(vol), want, f"replay {rep}: ")
 
 
+def test_release_graphs_and_record_again():
+    """kf_release_graphs empties the graph cache (at least the graph just recorded, with its
+    workspace); the next call records the batch again and gives the same volume."""
+    spec, fr = configs.tiny(n_frames=5)
+    scan = kf.Scan.from_frames(fr.to(DEV))
+    say("graph cache release")
+    vol = kf.Volume(spec)
+    kf.integrate_batch([(vol, scan)], frames_per_pass=3, use_graph=True)
+    want = to_host(vol)
+    n, nbytes = kf.release_graphs()
+    assert n >= 1 and nbytes > 0
+    assert kf.release_graphs() == (0, 0)
+    vol.reset()
+    kf.integrate_batch([(vol, scan)], frames_per_pass=3, use_graph=True)
+    assert_bitwise(to_host(vol), want, "recorded again: ")
+
+
 @pytest.fixture(scope="module")
 def kinect8():
     """The Kinect-like workload at full size (256^3 / 512^3, 640x480 depth, 1920x1080

@@ -82,7 +82,7 @@ def test_counters_match_oracle(oracle, tiny, K):
     cnt = kf.integrate_batch_counted([(vol, kf.Scan.from_frames(fr.to(DEV)))], frames_per_pass=K)
     want_state, want = _oracle_state(oracle, spec, fr, K)
     assert list(cnt[:6]) == list(want)
-    assert 0 < cnt[7] and cnt[6] <= 64 ** 3 // 512 * fr.n and cnt[7] <= 128 ** 3 // 512 * fr.n
+    assert 0 < cnt[7] and cnt[6] <= 64 ** 3 * fr.n and cnt[7] <= 128 ** 3 * fr.n
     assert_bitwise(to_host(vol), want_state, "counted: ")
 
 
