@@ -8,7 +8,7 @@ depth (noisy, 1 % holes) and 1920x1080 RGB8 images of 4 spheres and 4 boxes on a
 trunc = 4 geometry voxels, w_max = 128.
 
 One step = one whole scan: reset the volume, then integrate all 256 frames in passes of
-K frames (K from the autotuner; one call: depth pyramids and weight maps for all frames,
+K frames (K from the autotuner; one call: depth pyramids and pixel maps for all frames,
 then per pass a culling launch and two persistent integration launches, geometry bricks
 then colour bricks).  The metric counts every voxel of both volumes once per frame (the
 swept voxel updates of KinectFusion-style integration).
@@ -55,17 +55,18 @@ OPS = {
     # a geometry update: min(1, sdf / trunc) (2), W + 1, F + (t - F) / (W + 1) (3), min
     "geom_update": 7,
     # a colour voxel-frame in a live brick: as the geometry one up to the depth sample,
-    # then Eq. 7 (6), the difference to the voxel (3), its squared norm (3), comparison
-    "colour_voxel_frame": 32,
+    # then the difference to Eq. 7's P (3), its squared norm (3), comparison (P itself
+    # depends only on the depth pixel and is counted with the pixel map)
+    "colour_voxel_frame": 26,
     # a colour gate evaluation (Eq. 10's W against gate * W_pre): mul + comparison
     "colour_gate": 2,
     # a colour update: HD pixel (Eq. 2-4 as 9 FMA, 1/q_z, 2 mul + 2 FMA, 2 floor, 5
     # comparisons, cell index 3), bilinear sample of 3 channels of 8-bit pixels (12
     # conversions, 12 scalings, 9 lerps of 2), Eq. 9 (alpha: 2, 3 x 2) and Eq. 10 (2)
     "colour_update": 24 + 12 + 12 + 18 + 2 + 6 + 2,
-    # a depth pixel of the weight map (Eq. 7 at the pixel and 2 neighbours, Eq. 8 cross
+    # a depth pixel of the pixel map (Eq. 7 at the pixel and 2 neighbours, Eq. 8 cross
     # product, norms, dot product, square root and division): its own launch
-    "weight_map_pixel": 59,
+    "pixel_map_pixel": 59,
 }
 WORKLOAD = ("fused multi-frame scan: geometry 512^3 + colour 1024^3 (2x per axis) over 1.0 m, "
             "256 frames of 640x480 float32 depth + 1920x1080 RGB8, 4 spheres + 4 boxes")

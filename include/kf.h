@@ -102,7 +102,7 @@ void kf_volume_destroy(kf_volume* vol);
 /*
  * Integrate one frame (Sec. III and Sec. IV.B).
  *   depth: [dh][dw] float32 metres; 0, negative, NaN or infinite = no measurement;
- *          dw, dh <= 65535 and dw * dh < 2^29 - 4 (KF_E_RANGE otherwise).
+ *          dw, dh <= 65535 and dw * dh < 2^27 - 1 (KF_E_RANGE otherwise).
  *   rgb:   [ch][cw][3] in `fmt`; cw, ch >= 2; cw * ch * 3 < 2^31.
  *   K_d, K_rgb: 3x3 intrinsics (K_c, K_hd of Eq. 1-4), zero skew, last row (0,0,1),
  *          positive focal lengths.
@@ -180,17 +180,18 @@ kf_status kf_integrate_batch_bricks(const kf_scene* scenes, int32_t n_scenes,
  * For callers that cannot allocate device memory (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc): kf_integrate_batch without a graph, with the
  * same arguments and the same result, whose workspace (frame constants, per-pass tables,
- * queue counters, live lists, depth pyramids and colour weight maps) lives in a fixed
- * 64 MiB device array inside the library instead of the stream-ordered allocator.  Calls
+ * queue counters, live lists, depth pyramids and pixel maps) lives in a fixed
+ * 256 MiB device array inside the library instead of the stream-ordered allocator.  Calls
  * nothing that allocates device or pinned host memory: the tables reach the device in
  * kernel arguments, the counters are cleared by a kernel.  The array exists once per GPU
  * (held until the process ends) and every call on that GPU uses it, so calls that overlap
  * on one GPU (other streams, other threads) race and must be serialised by the caller; a
  * call's workspace is re-initialised by the call itself.  KF_E_RANGE if the batch needs
- * more than 64 MiB of workspace: about 32 bytes per brick of the largest pass's volumes
- * (a brick is 16 x 4 x 8 geometry or 8 x 8 x 8 colour voxels) plus about 1.3 MB per
+ * more than 256 MiB of workspace: about 32 bytes per brick of the largest pass's volumes
+ * (a brick is 16 x 4 x 8 geometry or 8 x 8 x 8 colour voxels) plus about 5 MB per
  * 640 x 480 depth frame of the batch (a 256^3 / 512^3 pair of volumes takes 9.4 MB plus
- * its frames; a 512^3 / 1024^3 pair does not fit).  Other errors as kf_integrate_batch.
+ * its frames, a 512^3 / 1024^3 pair 75 MB plus its frames).  Other errors as
+ * kf_integrate_batch.
  */
 kf_status kf_integrate_batch_noalloc(const kf_scene* scenes, int32_t n_scenes,
                                      int32_t frames_per_pass, void* stream);
@@ -254,7 +255,11 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
  *          changes); the pose then moves only where each update samples the HD image, and
  *          d_pose[n] = -Ad(T_hd_from_world[n])^T of frame n's extrinsic contribution.
  * The per-frame blending weights are recomputed from the depth maps (nothing from the
- * forward is stored).  The geometry volume and the colour weights do not depend on the
+ * forward is stored).  Any number of frames: the kernels replay at most 64 per launch
+ * sequence, so a longer scan is taken in chunks of 64 (KF_BWD_CHUNK in the environment, 1
+ * to 64, sets another size): a first sweep stores the colour weights at the start of
+ * every chunk (prod(colour_dim) floats per chunk after the first), then the chunks are
+ * replayed from the last with the gradient carried across chunk boundaries.  The geometry volume and the colour weights do not depend on the
  * HD images or the extrinsic (except where a sample leaves the HD image), so they have no
  * adjoint here.  Uses a workspace allocated on `stream` with the stream-ordered allocator.
  */

@@ -6,8 +6,8 @@ images `rgb` [n,CH,CW,3] with the extrinsic exp(xi^) T_rgb_from_d (xi = (rho, ph
 se(3), float64, 6).  Gradients flow to `rgb` and `xi`; both come from the library's
 backward kernel, which returns the gradient for a left perturbation at the current
 extrinsic; kf_se3_pullback maps it to xi itself (the SE(3) left Jacobian) and
-kf_se3_compose forms the perturbed extrinsic.  The library's adjoint replays at most 64
-frames per call, so `rgb` may hold at most 64 frames (the forward alone takes any number).
+kf_se3_compose forms the perturbed extrinsic.  Any number of frames: the library takes
+a longer scan in chunks of 64 frames.
 """
 from __future__ import annotations
 

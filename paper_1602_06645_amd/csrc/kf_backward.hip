@@ -44,20 +44,23 @@ namespace {
 // the image reads 0, so a voxel outside the frustum needs no branch around its reads.
 constexpr uint32_t kOffImage = 0x7FFFFFF0u;
 
-__device__ __forceinline__ float image_load(const void* p, uint32_t bytes, uint32_t byte_off)
+__device__ __forceinline__ float4 image_load4(const void* p, uint32_t bytes, uint32_t byte_off)
 {
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    float4 f;
+    __builtin_memcpy(&f, &v, sizeof f);
+    return f;
 }
 
 // The forward decision of one colour voxel for one frame, split so that several frames'
 // image reads can be in flight together: weight_fetch projects the voxel centre into the
-// depth camera (Eq. 5-6) and reads its depth and weight-map entries; weight_test applies
+// depth camera (Eq. 5-6) and reads its pixel-map entry (depth, P of Eq. 7, W); weight_test applies
 // every test of Sec. IV.B except the gate (which needs the running weight) and returns the
 // weight-map W if they all pass, else 0.  Same single-precision operations as the forward.
 struct WeightFetch {
-    float Xc, Yc, Zc, u, v, d, w;
+    float Xc, Yc, Zc, d, Px, Py, w;
     bool in;
 };
 
@@ -69,13 +72,15 @@ __device__ __forceinline__ WeightFetch weight_fetch(const C& c, float fi, float 
     r.Yc = fmaf(c.Ac[5], fk, fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1])));
     r.Zc = fmaf(c.Ac[8], fk, fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2])));
     const float iz = recip(r.Zc);
-    r.u = rintf(fmaf(c.fx, r.Xc * iz, c.cx));
-    r.v = rintf(fmaf(c.fy, r.Yc * iz, c.cy));
-    r.in = (r.Zc > 0.0f) & (r.u >= 0.0f) & (r.u <= c.wm1) & (r.v >= 0.0f) & (r.v <= c.hm1);
-    const uint32_t off = r.in ? ((uint32_t)(int)r.v * (uint32_t)c.dw + (uint32_t)(int)r.u) * 4u : kOffImage;
-    const uint32_t bytes = (uint32_t)(c.dw * c.dh) * 4u;
-    r.d = image_load(c.depth, bytes, off);
-    r.w = image_load(c.wmap, bytes, off);
+    const float u = rintf(fmaf(c.fx, r.Xc * iz, c.cx));
+    const float v = rintf(fmaf(c.fy, r.Yc * iz, c.cy));
+    r.in = (r.Zc > 0.0f) & (u >= 0.0f) & (u <= c.wm1) & (v >= 0.0f) & (v <= c.hm1);
+    const uint32_t off = r.in ? ((uint32_t)(int)v * (uint32_t)c.dw + (uint32_t)(int)u) * 16u : kOffImage;
+    const float4 pm = image_load4(c.pmap, (uint32_t)(c.dw * c.dh) * 16u, off);
+    r.d = pm.x;
+    r.Px = pm.y;
+    r.Py = pm.z;
+    r.w = pm.w;
     return r;
 }
 
@@ -83,9 +88,7 @@ template <class C>
 __device__ __forceinline__ float weight_test(const C& c, const WeightFetch& r, float fi, float fj,
                                              float fk)
 {
-    const float Px = ((r.u - c.cx) * c.inv_fx) * r.d;
-    const float Py = ((r.v - c.cy) * c.inv_fy) * r.d;
-    const float dx = r.Xc - Px, dy = r.Yc - Py, dz = r.Zc - r.d;
+    const float dx = r.Xc - r.Px, dy = r.Yc - r.Py, dz = r.Zc - r.d;
     const bool valid = valid_depth(r.d);
     const bool band = r.in & valid & !(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) > c.sigma2) &
                       (__builtin_bit_cast(uint32_t, r.w) != kNoNormal);
@@ -104,13 +107,6 @@ __device__ __forceinline__ double wave_sum_d(double x)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     return x;
-}
-
-// Rank of this lane among the set lanes of `ballot` below it.
-__device__ __forceinline__ uint32_t lane_rank(unsigned long long ballot)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
 // HD tiles that the bilinear cells of a brick's voxels can touch in one frame: the
@@ -266,11 +262,17 @@ __global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
         const bool inside = i < a.cdim[0] && j < a.cdim[1] && k < a.cdim[2];
         const float fi = (float)i, fj = (float)j, fk = (float)k;
         const size_t idx = ((size_t)k * (size_t)a.cdim[1] + (size_t)j) * (size_t)a.cdim[0] + (size_t)i;
-        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-        if (inside) {
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, tail0 = 1.0f;
+        if (inside && !a.wc_out) {
             g0 = a.grad[idx];
             g1 = a.grad[nvox + idx];
             g2 = a.grad[2 * nvox + idx];
+            if (a.tail_in) {
+                tail0 = a.tail_in[idx];
+                g0 *= tail0;
+                g1 *= tail0;
+                g2 *= tail0;
+            }
         }
         // the frames' tile ranges (one thread per rank), and a clear per-frame pose table
         if (t < n_r) {
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
         // forward replay over the live frames, by rank among them: first the
         // weight-independent tests, four frames at a time with their image reads in flight
         // together (W or 0 into the history) ...
-        const bool active = inside && (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f);
+        const bool active = inside && (a.wc_out || g0 != 0.0f || g1 != 0.0f || g2 != 0.0f);
         unsigned long long upd = 0;   // bit r: rank r updates this voxel
         if (active) {
             int r = 0;
@@ -324,6 +326,11 @@ __global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
                 }
                 hist[r * BWD_BLOCK] = alpha;
             }
+            if (a.wc_out) a.wc_out[idx] = Wc;
+        }
+        if (a.wc_out) {
+            __syncthreads();   // every thread has read the ticket
+            continue;
         }
         __syncthreads();   // s_tiles, s_cnt (direct marks) and s_pose are set
         // records per wave and rank (direct ranks have none)
@@ -459,6 +466,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
                 }
             }
         }
+        if (a.tail_out && active) a.tail_out[idx] = tail0 * tail;
         // the brick's extrinsic partial: per wave a fixed butterfly, then the waves in order
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -671,6 +679,14 @@ __global__ __launch_bounds__(256) void reduce_xi_kernel(const double* partials, 
         __syncthreads();
     }
     if (threadIdx.x < 6) out[(size_t)blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+hipError_t launch_sum_rows(const double* rows, uint32_t n_rows, uint32_t width, double* out,
+                           hipStream_t stream)
+{
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(256), 0, stream, rows, n_rows, width,
+                       n_rows, out);
+    return hipGetLastError();
 }
 
 template <int HIST, bool POSE>

@@ -140,7 +140,9 @@ kf_status check_images(const float* depth, int32_t dw, int32_t dh, const void* r
 {
     if (dw < 1 || dh < 1) return fail(KF_E_SHAPE, "depth image must be at least 1x1");
     if (cw < 2 || ch < 2) return fail(KF_E_SHAPE, "HD image must be at least 2x2");
-    if (dw > 65535 || dh > 65535 || (double)dw * dh * 4.0 >= 2147483632.0 ||
+    // the 16-byte pixel map of a depth image is read through a buffer resource whose
+    // byte offsets stay below 2^31 - 16 (the out-of-image marker)
+    if (dw > 65535 || dh > 65535 || (double)dw * dh * 16.0 >= 2147483632.0 ||
         (double)cw * ch * 3.0 > 2147483647.0)
         return fail(KF_E_RANGE, "image too large");
     if (fmt != KF_RGB8 && fmt != KF_RGBF32) return fail(KF_E_ARG, "unknown pixel format");
@@ -244,7 +246,7 @@ void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_r
     out->ch = ch;
     out->depth = depth;
     out->rgb = rgb;
-    // the depth pyramid: 8x8-pixel tiles, halved until one tile covers the image
+    // the depth pyramid: 4x4-pixel tiles, halved until one tile covers the image
     out->pyr = nullptr;
     out->pyr_w0 = (dw + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
     out->pyr_h0 = (dh + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
@@ -454,11 +456,11 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, const 
 
 // Device image of a plan:
 //   [frame table][scene table of each pass][kPassCounters counters per pass][live lists:
-//   heavy and light][pyramids][weight maps]
+//   heavy and light][pyramids][pixel maps]
 struct DeviceTables {
     std::vector<unsigned char> host;
     size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
-    std::vector<size_t> pass_off, frame_pyr_off, frame_wmap_off;
+    std::vector<size_t> pass_off, frame_pyr_off, frame_pmap_off;
     int32_t max_tiles0 = 0, max_pixels = 0;
 };
 
@@ -487,8 +489,8 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
     }
     off = align(off);
     for (const auto& fc : p.frames) {
-        t->frame_wmap_off.push_back(off);
-        off = align(off + (size_t)fc.dw * fc.dh * sizeof(float));
+        t->frame_pmap_off.push_back(off);
+        off = align(off + (size_t)fc.dw * fc.dh * sizeof(float4));
         const int32_t pixels = fc.dw * fc.dh;
         t->max_pixels = pixels > t->max_pixels ? pixels : t->max_pixels;
     }
@@ -498,13 +500,13 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
 // Fill the host image for device base address `dev` (the frames point at their pyramids).
 void fill_tables(const BatchPlan& p, unsigned char* dev, DeviceTables* t)
 {
-    // the tables and counters; the live lists, pyramids and weight maps are written on
+    // the tables and counters; the live lists, pyramids and pixel maps are written on
     // the device (the counters are cleared there too)
     t->host.assign(t->live_off, 0);
     std::vector<kf::FrameConsts> frames = p.frames;
     for (size_t f = 0; f < frames.size(); ++f) {
         frames[f].pyr = (float2*)(dev + t->frame_pyr_off[f]);
-        frames[f].wmap = (float*)(dev + t->frame_wmap_off[f]);
+        frames[f].pmap = (float4*)(dev + t->frame_pmap_off[f]);
     }
     if (!frames.empty())
         memcpy(t->host.data() + t->frames_off, frames.data(), frames.size() * sizeof(kf::FrameConsts));
@@ -539,8 +541,8 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
-    KF_HIP(kf::launch_weight_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
-           "weight map launch");
+    KF_HIP(kf::launch_pixel_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
+           "pixel map launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
     KF_HIP(kf::launch_fill_u32(cnt, kPassCounters * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint4* live = (uint4*)(dev + t.live_off);
@@ -592,7 +594,7 @@ struct GraphEntry {
 };
 
 // Recorded batches, most recently used first.  Each entry owns its graph and the workspace
-// the graph's kernels use (tables, live lists, pyramids and weight maps of every frame), so
+// the graph's kernels use (tables, live lists, pyramids and pixel maps of every frame), so
 // the cache is bounded by entries and by workspace bytes; the least recently used entries
 // go first (the newest is always kept).
 struct GraphCache {
@@ -736,7 +738,7 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
 // stand-in for the device symbol, never a device address: each GPU's copy is looked up
 // once per device with hipGetSymbolAddress (scratch_base) and that address is what the
 // launches receive.  Calls that overlap on one GPU share the array and race.
-constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchBytes = size_t(256) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct ScratchBases {
@@ -933,17 +935,17 @@ kf_status kf_debug_status(kf_volume* vol, const float* depth, int32_t dw, int32_
     frame_consts(vol->desc, K_d, K_rgb, T_rgb_from_d, T_world_from_cam, trunc_m, w_max, depth,
                  dw, dh, rgb, cw, ch, &a.frame);
     hipStream_t st = (hipStream_t)stream;
-    // workspace: [frame constants][weight map]
+    // workspace: [frame constants][pixel map]
     const size_t map_off = (sizeof(kf::FrameConsts) + 255) / 256 * 256;
     unsigned char* ws = nullptr;
-    KF_HIP(workspace_alloc((void**)&ws, map_off + (size_t)dw * dh * sizeof(float), st), "hipMallocAsync");
-    a.frame.wmap = (float*)(ws + map_off);
+    KF_HIP(workspace_alloc((void**)&ws, map_off + (size_t)dw * dh * sizeof(float4), st), "hipMallocAsync");
+    a.frame.pmap = (float4*)(ws + map_off);
     s = staged_copy(ws, &a.frame, sizeof a.frame, st);
     hipError_t e = hipSuccess;
     const char* what = nullptr;
     if (s == KF_OK) {
-        if ((e = kf::launch_weight_maps((const kf::FrameConsts*)ws, 1, dw * dh, st)) != hipSuccess)
-            what = "weight map launch";
+        if ((e = kf::launch_pixel_maps((const kf::FrameConsts*)ws, 1, dw * dh, st)) != hipSuccess)
+            what = "pixel map launch";
         if (!what) {
             a.n_items = a.scene.geom_items;
             a.status = geom_status;
@@ -1076,31 +1078,18 @@ kf_status kf_integrate_batch_counted(const kf_scene* scenes, int32_t n_scenes,
                      (hipStream_t)stream);
 }
 
-kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
-                                int32_t n_frames, const float* depth, const float* rgb_f32,
-                                int32_t dw, int32_t dh, int32_t cw, int32_t ch,
-                                const double K_d[9], const double K_rgb[9],
-                                const double T_rgb_from_d[16], const double* T_world_from_cam,
-                                const float* grad_rgb_vol, float* d_rgb, double* d_xi,
-                                double* d_pose, void* stream)
+namespace {
+
+// One call of the adjoint kernels over n_frames <= 64 frames (arguments checked by the
+// caller).  tail_in / tail_out / wc_out: see BackwardArgs (chunks of a longer scan).
+kf_status backward_call(const kf_volume_desc* desc, const float* w_col0, int32_t n_frames,
+                        const float* depth, const float* rgb_f32, int32_t dw, int32_t dh,
+                        int32_t cw, int32_t ch, const double K_d[9], const double K_rgb[9],
+                        const double T_rgb_from_d[16], const double* T_world_from_cam,
+                        const float* grad_rgb_vol, const float* tail_in, float* tail_out,
+                        float* wc_out, float* d_rgb, double* d_xi, double* d_pose, void* stream)
 {
-    kf_status s = check_desc(desc);
-    if (s != KF_OK) return s;
-    if (desc->hd_sampling != KF_HD_BILINEAR)
-        return fail(KF_E_UNSUPPORTED, "the adjoint is defined for bilinear HD sampling");
-    if (n_frames < 0) return fail(KF_E_ARG, "n_frames < 0");
-    if (n_frames > 64) return fail(KF_E_UNSUPPORTED, "the adjoint replays at most 64 frames per call");
-    if (!grad_rgb_vol || !d_xi || (n_frames > 0 && !d_rgb))
-        return fail(KF_E_ARG, "gradient pointer is NULL");
-    if (n_frames > 0) {
-        if ((s = check_images(depth, dw, dh, rgb_f32, KF_RGBF32, cw, ch)) != KF_OK) return s;
-        if ((s = check_K(K_d, "K_d")) != KF_OK) return s;
-        if ((s = check_K(K_rgb, "K_rgb")) != KF_OK) return s;
-        if ((s = check_rigid(T_rgb_from_d, "T_rgb_from_d")) != KF_OK) return s;
-        if (!T_world_from_cam) return fail(KF_E_ARG, "T_world_from_cam is NULL");
-        for (int f = 0; f < n_frames; ++f)
-            if ((s = check_rigid(T_world_from_cam + 16 * (size_t)f, "T_world_from_cam")) != KF_OK) return s;
-    }
+    kf_status s = KF_OK;
     hipStream_t st = (hipStream_t)stream;
     kf::BackwardArgs a;
     memset(&a, 0, sizeof a);
@@ -1113,8 +1102,11 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     a.disable_cull = cull_disabled() ? 1 : 0;
     a.wc0 = w_col0;
     a.grad = grad_rgb_vol;
+    a.tail_in = tail_in;
+    a.tail_out = tail_out;
+    a.wc_out = wc_out;
     a.d_rgb = d_rgb;
-    // workspace: [frames][n_live, queue][live list][partials][pyramids][weight maps]
+    // workspace: [frames][n_live, queue][live list][partials][pyramids][pixel maps]
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     std::vector<kf::FrameConsts> fc((size_t)(n_frames > 0 ? n_frames : 1));
     memset(fc.data(), 0, fc.size() * sizeof(kf::FrameConsts));
@@ -1138,7 +1130,7 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     // atomics instead), one segment per live brick and frame, four bins per segment
     a.tiles_x = (int32_t)ceil_div(cw, kf::BWD_TILE_W);
     a.tiles_y = (int32_t)ceil_div(ch, kf::BWD_TILE_H);
-    const bool binned = n_frames > 0 && a.tiles_x <= 65535 && a.tiles_y <= 65535;
+    const bool binned = n_frames > 0 && !wc_out && a.tiles_x <= 65535 && a.tiles_y <= 65535;
     uint64_t rec_cap = binned ? (uint64_t)n_frames * (uint64_t)cw * (uint64_t)ch / 2 : 0;
     if (binned && rec_cap < (1u << 20)) rec_cap = 1u << 20;
     if (rec_cap > 0x7FFFFFFFull) rec_cap = 0x7FFFFFFFull;
@@ -1164,17 +1156,17 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
         max_tiles0 = tiles > max_tiles0 ? tiles : max_tiles0;
     }
     off = align(off);
-    std::vector<size_t> wmap(fc.size(), 0);
+    std::vector<size_t> pmap(fc.size(), 0);
     for (int f = 0; f < n_frames; ++f) {
-        wmap[f] = off;
-        off = align(off + dpix * sizeof(float));
+        pmap[f] = off;
+        off = align(off + dpix * sizeof(float4));
     }
     const size_t bytes = align(off);
     unsigned char* ws = nullptr;
     KF_HIP(workspace_alloc((void**)&ws, bytes, st), "hipMallocAsync");
     for (int f = 0; f < n_frames; ++f) {
         fc[f].pyr = (float2*)(ws + pyr[f]);
-        fc[f].wmap = (float*)(ws + wmap[f]);
+        fc[f].pmap = (float4*)(ws + pmap[f]);
     }
     a.frames = (const kf::FrameConsts*)(ws + frames_off);
     a.n_live = (uint32_t*)(ws + counters_off);
@@ -1216,7 +1208,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     hipError_t e = hipSuccess;
     const char* what = nullptr;
     if (s == KF_OK && n_frames > 0) {
-        if ((e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st)) != hipSuccess) what = "gradient reset";
+        if (d_rgb && (e = kf::launch_fill_f32(d_rgb, cvals * (size_t)n_frames, 0.0f, st)) != hipSuccess)
+            what = "gradient reset";
         else if ((e = kf::launch_fill_u32((uint32_t*)(ws + counters_off), 2, 0u, st)) != hipSuccess) what = "counter reset";
         else if ((e = kf::launch_fill_u32((uint32_t*)(ws + recn_off), 4, 0u, st)) != hipSuccess) what = "record counter reset";
         else if (n_bins > 0 && (e = kf::launch_fill_u32((uint32_t*)(ws + bins_off), n_bins + 1, 0u, st)) != hipSuccess)
@@ -1229,8 +1222,8 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
                                                   st)) != hipSuccess)
             what = "pose partial reset";
         else if ((e = kf::launch_pyramids(a.frames, n_frames, max_tiles0, st)) != hipSuccess) what = "pyramid launch";
-        else if ((e = kf::launch_weight_maps(a.frames, n_frames, dw * dh, st)) != hipSuccess)
-            what = "weight map launch";
+        else if ((e = kf::launch_pixel_maps(a.frames, n_frames, dw * dh, st)) != hipSuccess)
+            what = "pixel map launch";
     }
     if (s == KF_OK && !what) {
         int device = 0;
@@ -1240,6 +1233,101 @@ kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
     }
     if (s == KF_OK && what) s = hip_fail(e, what);
     hipError_t fe = hipFreeAsync(ws, st);
+    if (s != KF_OK) return s;
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
+    return KF_OK;
+}
+
+// Frames per adjoint call: 64 (the kernel's alpha history), or KF_BWD_CHUNK in [1, 64]
+// from the environment (smaller chunks give the same gradients up to rounding).
+int32_t backward_chunk_frames()
+{
+    const char* v = getenv("KF_BWD_CHUNK");
+    const long n = v ? strtol(v, nullptr, 10) : 64;
+    return n >= 1 && n <= 64 ? (int32_t)n : 64;
+}
+
+}  // namespace
+
+kf_status kf_integrate_backward(const kf_volume_desc* desc, const float* w_col0,
+                                int32_t n_frames, const float* depth, const float* rgb_f32,
+                                int32_t dw, int32_t dh, int32_t cw, int32_t ch,
+                                const double K_d[9], const double K_rgb[9],
+                                const double T_rgb_from_d[16], const double* T_world_from_cam,
+                                const float* grad_rgb_vol, float* d_rgb, double* d_xi,
+                                double* d_pose, void* stream)
+{
+    kf_status s = check_desc(desc);
+    if (s != KF_OK) return s;
+    if (desc->hd_sampling != KF_HD_BILINEAR)
+        return fail(KF_E_UNSUPPORTED, "the adjoint is defined for bilinear HD sampling");
+    if (n_frames < 0) return fail(KF_E_ARG, "n_frames < 0");
+    if (!grad_rgb_vol || !d_xi || (n_frames > 0 && !d_rgb))
+        return fail(KF_E_ARG, "gradient pointer is NULL");
+    if (n_frames > 0) {
+        if ((s = check_images(depth, dw, dh, rgb_f32, KF_RGBF32, cw, ch)) != KF_OK) return s;
+        if ((s = check_K(K_d, "K_d")) != KF_OK) return s;
+        if ((s = check_K(K_rgb, "K_rgb")) != KF_OK) return s;
+        if ((s = check_rigid(T_rgb_from_d, "T_rgb_from_d")) != KF_OK) return s;
+        if (!T_world_from_cam) return fail(KF_E_ARG, "T_world_from_cam is NULL");
+        for (int f = 0; f < n_frames; ++f)
+            if ((s = check_rigid(T_world_from_cam + 16 * (size_t)f, "T_world_from_cam")) != KF_OK) return s;
+    }
+    const int32_t chunk = backward_chunk_frames();
+    if (n_frames <= chunk)
+        return backward_call(desc, w_col0, n_frames, depth, rgb_f32, dw, dh, cw, ch, K_d, K_rgb,
+                             T_rgb_from_d, T_world_from_cam, grad_rgb_vol, nullptr, nullptr, nullptr,
+                             d_rgb, d_xi, d_pose, stream);
+    // Longer scans in chunks of `chunk` frames.  C_N depends on a chunk's samples through
+    // that chunk's alphas and the product of (1 - alpha) over every later frame, so: a
+    // forward sweep stores the colour weights at the start of every chunk (the replay's
+    // own weight recurrence, bit-identical to the forward integration's); then the chunks
+    // from the last, each with the gradient at its end (grad times the running product of
+    // (1 - alpha) over the later chunks, updated in place by each call); d_xi is the sum of
+    // the chunks' in chunk order.
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n_chunks = (n_frames + chunk - 1) / chunk;
+    const size_t nvox = (size_t)desc->colour_dim[0] * desc->colour_dim[1] * desc->colour_dim[2];
+    const size_t dpix = (size_t)dw * dh, cvals = (size_t)cw * ch * 3;
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ckpt_off = 0;
+    const size_t tail_off = align(ckpt_off + (size_t)(n_chunks - 1) * nvox * sizeof(float));
+    const size_t xi_off = align(tail_off + nvox * sizeof(float));
+    unsigned char* ws = nullptr;
+    KF_HIP(workspace_alloc((void**)&ws, align(xi_off + (size_t)n_chunks * 6 * sizeof(double)), st),
+           "hipMallocAsync");
+    float* ckpt = (float*)(ws + ckpt_off);
+    float* tail = (float*)(ws + tail_off);
+    double* xi_rows = (double*)(ws + xi_off);
+    hipError_t e = hipSuccess;
+    for (int32_t c = 0; s == KF_OK && c + 1 < n_chunks; ++c) {
+        const size_t f0 = (size_t)c * chunk;
+        const float* w_in = c == 0 ? w_col0 : ckpt + (size_t)(c - 1) * nvox;
+        float* w_out = ckpt + (size_t)c * nvox;
+        e = w_in ? hipMemcpyAsync(w_out, w_in, nvox * sizeof(float), hipMemcpyDeviceToDevice, st)
+                 : kf::launch_fill_f32(w_out, nvox, 0.0f, st);
+        if (e != hipSuccess) {
+            s = hip_fail(e, "checkpoint copy");
+            break;
+        }
+        s = backward_call(desc, w_in, chunk, depth + dpix * f0, rgb_f32 + cvals * f0, dw, dh, cw, ch,
+                          K_d, K_rgb, T_rgb_from_d, T_world_from_cam + 16 * f0, grad_rgb_vol,
+                          nullptr, nullptr, w_out, nullptr, xi_rows + 6 * (size_t)c, nullptr, stream);
+    }
+    if (s == KF_OK && (e = kf::launch_fill_f32(tail, nvox, 1.0f, st)) != hipSuccess)
+        s = hip_fail(e, "tail reset");
+    for (int32_t c = n_chunks - 1; s == KF_OK && c >= 0; --c) {
+        const size_t f0 = (size_t)c * chunk;
+        const int32_t nf = (int32_t)((size_t)n_frames - f0 < (size_t)chunk ? (size_t)n_frames - f0 : (size_t)chunk);
+        const float* w_in = c == 0 ? w_col0 : ckpt + (size_t)(c - 1) * nvox;
+        s = backward_call(desc, w_in, nf, depth + dpix * f0, rgb_f32 + cvals * f0, dw, dh, cw, ch,
+                          K_d, K_rgb, T_rgb_from_d, T_world_from_cam + 16 * f0, grad_rgb_vol, tail,
+                          c > 0 ? tail : nullptr, nullptr, d_rgb + cvals * f0, xi_rows + 6 * (size_t)c,
+                          d_pose ? d_pose + 6 * f0 : nullptr, stream);
+    }
+    if (s == KF_OK && (e = kf::launch_sum_rows(xi_rows, (uint32_t)n_chunks, 6u, d_xi, st)) != hipSuccess)
+        s = hip_fail(e, "d_xi sum");
+    const hipError_t fe = hipFreeAsync(ws, st);
     if (s != KF_OK) return s;
     if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync");
     return KF_OK;

@@ -43,8 +43,11 @@ __device__ inline float2 depth_range(const FrameConsts& c, int u0, int u1, int v
 // Can any voxel of the index box [i0,i1] x [j0,j1] x [k0,k1] pass the depth tests of this
 // frame?  Its voxel centres form a parallelepiped (Eq. 5 is affine in the index), so
 // their depths lie between the corners' and, when all corners are in front of the
-// camera, their projections lie in the corners' bounding box (widened by a pixel for
-// rounding and the approximate reciprocal).  A colour voxel needs a depth within sigma of
+// camera, their projections lie in the corners' bounding box; a voxel's pixel is the
+// nearest integer to its projection, so the pixels lie in [ceil(min - 1/2), floor(max +
+// 1/2)], taken with 1/16 pixel to spare for the rounding of the voxel and corner
+// coordinates and the hardware reciprocal (together below 1e-3 pixel at image
+// coordinates up to a few thousand).  A colour voxel needs a depth within sigma of
 // its own z (|p - P| >= |z - d|); a geometry voxel needs a depth no more than trunc in
 // front of it.  1 mm of slack covers the single-precision rounding of z and d.
 __device__ inline bool brick_live(const FrameConsts& c, bool colour, int i0, int i1, int j0, int j1,
@@ -82,8 +85,8 @@ __device__ inline bool brick_live(const FrameConsts& c, bool colour, int i0, int
     if (!(zmax > -1e-4f)) return false;                  // entirely behind the camera
     int u0 = 0, u1 = c.dw - 1, v0 = 0, v1 = c.dh - 1;
     if (!near) {
-        const float fu0 = floorf(xmin) - 1.0f, fu1 = ceilf(xmax) + 1.0f;
-        const float fv0 = floorf(ymin) - 1.0f, fv1 = ceilf(ymax) + 1.0f;
+        const float fu0 = ceilf(xmin - 0.5625f), fu1 = floorf(xmax + 0.5625f);
+        const float fv0 = ceilf(ymin - 0.5625f), fv1 = floorf(ymax + 0.5625f);
         if (fu1 < 0.0f || fu0 > c.wm1 || fv1 < 0.0f || fv0 > c.hm1) return false;
         u0 = (int)fmaxf(fu0, 0.0f);
         u1 = (int)fminf(fu1, c.wm1);

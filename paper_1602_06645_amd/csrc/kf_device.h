@@ -28,7 +28,7 @@ constexpr int MAX_BZ = 16;
 constexpr int CBX = 8, CBY = 8, ZS = 8;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
-constexpr int PYR_SHIFT = 3;            // level-0 tiles of the depth pyramid: 8 x 8 pixels
+constexpr int PYR_SHIFT = 2;            // level-0 tiles of the depth pyramid: 4 x 4 pixels
 constexpr int XI_BLOCKS = 256;          // first-stage blocks of the adjoint's dxi reduction
 constexpr int CHUNK = 4;                // culling chunks: CHUNK^3 bricks of one kind
 
@@ -48,8 +48,9 @@ struct FrameConsts {
     const float* depth;   // [dh][dw]
     const void* rgb;      // [ch][cw][3], uint8 or float
     float2* pyr;          // min/max depth pyramid of this frame, levels back to back
-    float* wmap;          // [dh][dw] colour weight W of each depth pixel (Eq. 8 normal and
-                          // the viewing ray), or kNoNormal
+    float4* pmap;         // [dh][dw] per depth pixel: its depth, the x and y of its
+                          // back-projection P (Eq. 7) and the colour weight W (Eq. 8
+                          // normal and the viewing ray) or kNoNormal
     int32_t pyr_w0, pyr_h0, pyr_levels;
     int32_t hd_nearest;   // 1: Eq. 9 reads the nearest HD pixel; 0: the bilinear sample
 };
@@ -130,6 +131,16 @@ struct BackwardArgs {
     const FrameConsts* frames;        // [n_frames], with their depth pyramids
     const float* wc0;                 // initial colour weights or NULL
     const float* grad;                // [3][Nc]
+    // chunks of a longer scan (the frames of the call are one chunk of it):
+    const float* tail_in;             // NULL, or [Nc] prod (1 - alpha) over the later chunks'
+                                      // frames; the gradient of C at the chunk's end is
+                                      // grad * tail_in
+    float* tail_out;                  // NULL, or [Nc] tail_in times this chunk's prod
+                                      // (1 - alpha) (may be tail_in; voxels with a zero
+                                      // gradient are left as they are)
+    float* wc_out;                    // non-NULL: advance only, the colour weights after the
+                                      // call's frames into wc_out (voxels of live bricks; the
+                                      // others must hold wc0 already), no adjoint
     float* d_rgb;                     // [n][ch][cw][3]
     double* partials;                 // [n_items][6] (zero for bricks never live), then
                                       // [XI_BLOCKS][6] block sums of the reduction
@@ -198,6 +209,13 @@ __device__ __forceinline__ bool column_recip_exact(float z_first, float z_last)
 __device__ __forceinline__ uint32_t first_lane_u32(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Rank of this lane among the set lanes of `ballot` below it.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long ballot)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
 // Per-launch tables are read-only for the whole launch: reading them through the

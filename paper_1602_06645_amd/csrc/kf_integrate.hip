@@ -2,7 +2,7 @@
 // colour volume (Sec. IV.B, Eq. 5-10, with the depth-to-HD mapping of Eq. 1-4).
 //
 // A pass applies up to 64 consecutive frames of every scan in the launch:
-//   1. pyramid kernels: per frame, min/max of the valid depths over 8x8-pixel tiles and
+//   1. pyramid kernels: per frame, min/max of the valid depths over 4x4-pixel tiles and
 //      their 2x2 reductions (built once per batch call for all frames);
 //   2. cull kernel: one thread per (brick, frame) decides whether any voxel of the
 //      brick can pass the depth tests (conservatively, from the brick's corners and the
@@ -66,6 +66,32 @@ __device__ __forceinline__ float hd_sample(const void* rgb, int fmt, bool neares
     return lerp(lerp(p00, p10, ax), lerp(p01, p11, ax), ay);
 }
 
+// The three channels of the HD sample (hd_sample's values).  An 8-bit bilinear sample
+// reads each of its two rows as one 4-byte and one 2-byte load: the six bytes of the cell's
+// two pixels, at byte addresses (unaligned loads).
+__device__ __forceinline__ void hd_sample3(const void* rgb, int fmt, bool nearest, int cell, int row,
+                                           float ax, float ay, float* s)
+{
+    if (fmt == FMT_RGB8 && !nearest) {
+        const uint8_t* p = (const uint8_t*)rgb + cell;
+        uint32_t a0, a1;
+        uint16_t b0, b1;
+        __builtin_memcpy(&a0, p, 4);
+        __builtin_memcpy(&b0, p + 4, 2);
+        __builtin_memcpy(&a1, p + row, 4);
+        __builtin_memcpy(&b1, p + row + 4, 2);
+        const float k = (float)(1.0 / 255.0);
+        auto px = [k](uint32_t w, int n) { return (float)((w >> (8 * n)) & 0xFFu) * k; };
+        // channel ch of the left pixel is byte ch of the row, of the right pixel byte 3 + ch
+        s[0] = lerp(lerp(px(a0, 0), px(a0, 3), ax), lerp(px(a1, 0), px(a1, 3), ax), ay);
+        s[1] = lerp(lerp(px(a0, 1), px(b0, 0), ax), lerp(px(a1, 1), px(b1, 0), ax), ay);
+        s[2] = lerp(lerp(px(a0, 2), px(b0, 1), ax), lerp(px(a1, 2), px(b1, 1), ax), ay);
+        return;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) s[ch] = hd_sample(rgb, fmt, nearest, cell, row, ch, ax, ay);
+}
+
 struct Counts {
     unsigned long long g_upd = 0, g_touch = 0, c_eval = 0, c_read = 0, c_upd = 0, c_touch = 0;
     unsigned long long g_bricks = 0, c_bricks = 0;   // brick-frames (same in every lane)
@@ -121,25 +147,57 @@ __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byt
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
+__device__ __forceinline__ float4 load_f32x4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    float4 f;
+    __builtin_memcpy(&f, &v, sizeof f);
+    return f;
+}
+
 // Nearest depth pixel of camera point (X, Y, Z) (Eq. 6 with the perspective division):
-// the pixel as floats, whether it lies inside the image, and its byte offset (kOutside
-// when it does not).
+// the pixel as floats, whether it lies inside the image, and its index (valid only when it
+// does).
 struct Pixel {
     float u, v;
     bool inside;
-    uint32_t off;
+    uint32_t pix;   // v * width + u
 };
 
-template <bool EXACT = false, class C>
-__device__ __forceinline__ Pixel project(const C& c, float X, float Y, float Z)
+// A uniform value copied into a VGPR once, so that an operation with another uniform
+// operand (the VOP3 forms read at most one SGPR) does not re-copy it per voxel.
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Frame constants of the projection held per lane for a frame's sweep.
+struct ProjRegs {
+    float cx, cy;
+};
+
+template <class C>
+__device__ __forceinline__ ProjRegs proj_regs(const C& c)
+{
+    return {in_vgpr(c.cx), in_vgpr(c.cy)};
+}
+
+// EXACT: the caller has established recip_exact(Z) for the whole column, and zpos is
+// whether its depths are positive (one sign for the column).
+template <bool EXACT, class C>
+__device__ __forceinline__ Pixel project(const C& c, const ProjRegs& pr, float X, float Y, float Z,
+                                         bool zpos)
 {
     Pixel p;
-    // EXACT: the caller has established recip_exact(Z)
     const float iz = EXACT ? recip_newton(Z) : recip(Z);
-    p.u = rintf(fmaf(c.fx, X * iz, c.cx));
-    p.v = rintf(fmaf(c.fy, Y * iz, c.cy));
-    p.inside = (Z > 0.0f) & (p.u >= 0.0f) & (p.u <= c.wm1) & (p.v >= 0.0f) & (p.v <= c.hm1);
-    p.off = p.inside ? ((uint32_t)(int)p.v * (uint32_t)c.dw + (uint32_t)(int)p.u) * 4u : kOutside;
+    p.u = rintf(fmaf(c.fx, X * iz, pr.cx));
+    p.v = rintf(fmaf(c.fy, Y * iz, pr.cy));
+    const bool front = EXACT ? zpos : (Z > 0.0f);
+    p.inside = front & (p.u >= 0.0f) & (p.u <= c.wm1) & (p.v >= 0.0f) & (p.v <= c.hm1);
+    // the pixel's index, meaningful only when inside (then the pixel is below 2^24 and the
+    // 24-bit multiply exact); callers select it with their own conditions
+    p.pix = __umul24((uint32_t)(int)p.v, (uint32_t)c.dw) + (uint32_t)(int)p.u;
     return p;
 }
 
@@ -176,6 +234,9 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         const float cX = fmaf(c.Ag[1], fj, fmaf(c.Ag[0], fi, c.bg[0]));
         const float cY = fmaf(c.Ag[4], fj, fmaf(c.Ag[3], fi, c.bg[1]));
         const float cZ = fmaf(c.Ag[7], fj, fmaf(c.Ag[6], fi, c.bg[2]));
+        const ProjRegs pr = proj_regs(c);
+        const float z_first = fmaf(c.Ag[8], (float)col.k0, cZ);
+        const bool zpos = z_first > 0.0f;
         float sdf[BZ];
         uint32_t upd = 0;
         auto sweep = [&](auto exact) {
@@ -183,10 +244,10 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
             for (int kk = 0; kk < BZ; ++kk) {
                 const float fk = (float)(col.k0 + kk);
                 const float Zc = fmaf(c.Ag[8], fk, cZ);
-                const Pixel px = project<decltype(exact)::value>(c, fmaf(c.Ag[2], fk, cX),
-                                                                 fmaf(c.Ag[5], fk, cY), Zc);
+                const Pixel px = project<decltype(exact)::value>(c, pr, fmaf(c.Ag[2], fk, cX),
+                                                                 fmaf(c.Ag[5], fk, cY), Zc, zpos);
                 const bool in = px.inside & (kk < col.kn);
-                const float d = load_f32(depth, in ? px.off : kOutside);
+                const float d = load_f32(depth, in ? px.pix * 4u : kOutside);
                 const bool valid = in & valid_depth(d);
                 sdf[kk] = d - Zc;
                 const bool u = valid & !(sdf[kk] < -c.trunc);
@@ -199,7 +260,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         };
         // the per-voxel range test of the reciprocal, once per column and frame (a branch
         // every lane takes the same way unless a column reaches the camera plane)
-        if (column_recip_exact(fmaf(c.Ag[8], (float)col.k0, cZ), fmaf(c.Ag[8], (float)(col.k0 + BZ - 1), cZ)))
+        if (column_recip_exact(z_first, fmaf(c.Ag[8], (float)(col.k0 + BZ - 1), cZ)))
             sweep(std::true_type{});
         else
             sweep(std::false_type{});
@@ -286,11 +347,13 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
 // column's colour state lives in registers for the whole pass.
 template <int MODE, int BX, int BY, int BZ, class Scene, class FramePtr>
 __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
-                                             uint32_t li, uint8_t* status, Counts& cnt)
+                                             uint32_t li, uint8_t* status, float4* slots, Counts& cnt)
 {
-    static_assert(BX * BY == WAVE && BZ <= MAX_BZ, "one lane per column, masks of 32 bits");
+    static_assert(BX * BY == WAVE && BZ <= MAX_BZ && BZ <= 64, "one lane per column, masks of 32 bits");
     const Column col = column<BX, BY, BZ>(sc.cdim, sc.cbricks, li);
-    if (!col.active) return;
+    // a column outside the volume (a partial brick) stays with the wave, touching nothing:
+    // its voxels never pass the first test, and its lane takes sampling jobs in stage 4
+    const int lane = threadIdx.x & (WAVE - 1);
     const float fi = (float)col.i, fj = (float)col.j;
     float R[BZ], G[BZ], B[BZ], Wt[BZ];
 #pragma unroll
@@ -300,13 +363,18 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
     unsigned long long n_eval = 0, n_upd = 0;
     for (unsigned long long m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctzll(m)];
-        const __amdgpu_buffer_rsrc_t depth = image_rsrc(c.depth, (uint32_t)(c.dw * c.dh) * 4u);
+        const __amdgpu_buffer_rsrc_t pmap = image_rsrc(c.pmap, (uint32_t)(c.dw * c.dh) * 16u);
         const float cX = fmaf(c.Ac[1], fj, fmaf(c.Ac[0], fi, c.bc[0]));
         const float cY = fmaf(c.Ac[4], fj, fmaf(c.Ac[3], fi, c.bc[1]));
         const float cZ = fmaf(c.Ac[7], fj, fmaf(c.Ac[6], fi, c.bc[2]));
+        const ProjRegs pr = proj_regs(c);
+        const float z_first = fmaf(c.Ac[8], (float)col.k0, cZ);
+        const bool zpos = z_first > 0.0f;
         int st[BZ];
-        // (1) Eq. 5-7 and the distance test against sigma.
-        uint32_t poff[BZ];   // byte offset of the depth pixel of voxels in the band
+        // (1) Eq. 5-7 and the distance test against sigma: the voxel's depth pixel gives its
+        // depth, P (Eq. 7) and W from the frame's pixel map in one read; W is kept for the
+        // voxels in the band.
+        float wv[BZ];
         uint32_t band = 0;
         auto sweep = [&](auto exact) {
 #pragma unroll
@@ -315,36 +383,34 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 const float Xc = fmaf(c.Ac[2], fk, cX);
                 const float Yc = fmaf(c.Ac[5], fk, cY);
                 const float Zc = fmaf(c.Ac[8], fk, cZ);
-                const Pixel px = project<decltype(exact)::value>(c, Xc, Yc, Zc);
-                const bool in = px.inside & (kk < col.kn);
-                const float d = load_f32(depth, in ? px.off : kOutside);
+                const Pixel px = project<decltype(exact)::value>(c, pr, Xc, Yc, Zc, zpos);
+                const bool in = px.inside & (kk < col.kn) & col.active;
+                const float4 pm = load_f32x4(pmap, in ? px.pix * 16u : kOutside);
+                const float d = pm.x;
                 const bool valid = in & valid_depth(d);
-                const float Px = ((px.u - c.cx) * c.inv_fx) * d;
-                const float Py = ((px.v - c.cy) * c.inv_fy) * d;
-                const float dx = Xc - Px, dy = Yc - Py, dz = Zc - d;
+                const float dx = Xc - pm.y, dy = Yc - pm.z, dz = Zc - d;
                 const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 const bool bd = valid & !(dist2 > c.sigma2);
                 band |= (uint32_t)bd << kk;
-                poff[kk] = bd ? px.off : kOutside;
+                wv[kk] = bd ? pm.w : 0.0f;
                 if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
             }
         };
         // the per-voxel range test of the reciprocal, once per column and frame (a branch
         // every lane takes the same way unless a column reaches the camera plane)
-        if (column_recip_exact(fmaf(c.Ac[8], (float)col.k0, cZ), fmaf(c.Ac[8], (float)(col.k0 + BZ - 1), cZ)))
+        if (column_recip_exact(z_first, fmaf(c.Ac[8], (float)(col.k0 + BZ - 1), cZ)))
             sweep(std::true_type{});
         else
             sweep(std::false_type{});
+        // (2)-(3) the voxels in the band whose pixel has a normal (W of the pixel map: the
+        // Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dotted with the unit
+        // viewing direction), the first read of their colour weight, and the gate against
+        // the running weight.
+        uint32_t gate = 0;
         if (band) {
-            // (2)-(3) W of the voxel's depth pixel (Eq. 8 normal from the neighbours
-            // (u+1, v) and (u, v+1); unit normal . unit viewing direction), computed once
-            // per pixel by weight_map_kernel in the same operations.
-            const __amdgpu_buffer_rsrc_t wmap = image_rsrc(c.wmap, (uint32_t)(c.dw * c.dh) * 4u);
-            float wv[BZ];
             uint32_t reach = 0;
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
-                wv[kk] = load_f32(wmap, poff[kk]);
                 const bool ok = ((band >> kk) & 1u) & (__builtin_bit_cast(uint32_t, wv[kk]) != kNoNormal);
                 reach |= (uint32_t)ok << kk;
             }
@@ -360,31 +426,25 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 wl |= needw;
             }
             n_eval += (unsigned)__builtin_popcount(reach);
-            // (4) gate, HD pixel of the voxel centre (Eq. 3-5), bilinear cell inside the image.
-            uint32_t upd = 0;
-            int cell[BZ];
-            float ax[BZ], ay[BZ];
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
-                cell[kk] = 0;
-                ax[kk] = ay[kk] = 0.0f;
-                if ((reach >> kk) & 1u) {
-                    if constexpr (MODE == MODE_STATUS) st[kk] = 4;
-                    if (wv[kk] > c.gate * Wt[kk]) {
-                        if constexpr (MODE == MODE_STATUS) st[kk] = 5;
-                        const HdCell h = hd_cell(c, fi, fj, (float)(col.k0 + kk));
-                        if (h.inside) {
-                            if constexpr (MODE == MODE_STATUS) st[kk] = 6;
-                            cell[kk] = h.cell;
-                            ax[kk] = h.ax;
-                            ay[kk] = h.ay;
-                            upd |= 1u << kk;
-                        }
-                    }
-                }
+                const bool rk = (reach >> kk) & 1u;
+                const bool gk = rk & (wv[kk] > c.gate * Wt[kk]);
+                gate |= (uint32_t)gk << kk;
+                if constexpr (MODE == MODE_STATUS)
+                    if (rk) st[kk] = gk ? 5 : 4;
             }
+        }
+        // (4) for every gated voxel of the wave: the HD pixel of its centre (Eq. 3-5), the
+        // bilinear cell inside the image, the HD sample (Eq. 9's HD(x, y)) and
+        // alpha = W / (W_c + W) (Eq. 10's update as a blend).  Gated voxels are few and
+        // scattered over the wave's lanes, so they are numbered (z slice by z slice, lanes
+        // in order) and handed out to the active lanes in turn through LDS: a lane computes
+        // the sample of another lane's voxel, and the owner blends the result into its
+        // registers.  Same operations on the same values as in the owner's lane.
+        if (__ballot(gate != 0)) {
             if constexpr (MODE != MODE_STATUS) {
-                const uint32_t needc = upd & ~cl;
+                const uint32_t needc = gate & ~cl;
                 if (needc) {
                     const __amdgpu_buffer_rsrc_t rr = slab_rsrc(sc.r, col), gr = slab_rsrc(sc.g, col),
                                                  br = slab_rsrc(sc.b, col);
@@ -397,30 +457,86 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                         G[kk] = nk ? g : G[kk];
                         B[kk] = nk ? b : B[kk];
                     }
-                    cl |= needc;
                 }
-                const int row = c.cw * 3;
-                const bool nearest = c.hd_nearest != 0;
+            }
+            const unsigned long long act = __ballot(1);
+            const uint32_t n_act = (uint32_t)__builtin_popcountll(act);
+            const uint32_t wrank = lane_rank(act);
+            uint32_t total = 0;
+#pragma unroll
+            for (int kk = 0; kk < BZ; ++kk) total += (uint32_t)__builtin_popcountll(__ballot((gate >> kk) & 1u));
+            const int i0 = col.i - lane % BX, j0 = col.j - lane / BX;   // the brick's first column
+            const int row = c.cw * 3;
+            const bool nearest = c.hd_nearest != 0;
+            uint32_t upd = 0;
+            for (uint32_t r0 = 0; r0 < total; r0 += n_act) {
+                // jobs r0 .. r0 + n_act - 1: each owner puts (voxel, W, W_c) into the slot
+                // of the lane that takes the job
+                uint32_t first = 0;
 #pragma unroll
                 for (int kk = 0; kk < BZ; ++kk) {
-                    if ((upd >> kk) & 1u) {
-                        const float s0 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 0, ax[kk], ay[kk]);
-                        const float s1 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 1, ax[kk], ay[kk]);
-                        const float s2 = hd_sample(c.rgb, sc.fmt, nearest, cell[kk], row, 2, ax[kk], ay[kk]);
-                        const float alpha = wv[kk] / (Wt[kk] + wv[kk]);
-                        R[kk] = fmaf(alpha, s0 - R[kk], R[kk]);
-                        G[kk] = fmaf(alpha, s1 - G[kk], G[kk]);
-                        B[kk] = fmaf(alpha, s2 - B[kk], B[kk]);
-                        Wt[kk] = fmaf(wv[kk], 1.0f - Wt[kk], Wt[kk]);
-                    }
+                    const bool gk = (gate >> kk) & 1u;
+                    const unsigned long long b = __ballot(gk);
+                    const uint32_t q = first + lane_rank(b) - r0;
+                    if (gk && q < n_act)
+                        slots[q] = make_float4(__builtin_bit_cast(float, (uint32_t)(lane | kk << 6)), wv[kk],
+                                               Wt[kk], 0.0f);
+                    first += (uint32_t)__builtin_popcountll(b);
                 }
+                __builtin_amdgcn_wave_barrier();
+                if (r0 + wrank < total) {
+                    const float4 job = slots[wrank];
+                    const uint32_t code = __builtin_bit_cast(uint32_t, job.x);
+                    const int l = (int)(code & 63u), kk = (int)(code >> 6);
+                    const HdCell h = hd_cell(c, (float)(i0 + l % BX), (float)(j0 + l / BX), (float)(col.k0 + kk));
+                    float4 res = make_float4(-1.0f, 0.0f, 0.0f, 0.0f);   // alpha < 0: outside the image
+                    if (h.inside) {
+                        res.x = job.y / (job.z + job.y);
+                        if constexpr (MODE != MODE_STATUS) {
+                            float smp[3];
+                            hd_sample3(c.rgb, sc.fmt, nearest, h.cell, row, h.ax, h.ay, smp);
+                            res.y = smp[0];
+                            res.z = smp[1];
+                            res.w = smp[2];
+                        }
+                    }
+                    slots[wrank] = res;
+                }
+                __builtin_amdgcn_wave_barrier();
+                // each owner blends its results (Eq. 9 and Eq. 10 as running averages)
+                first = 0;
+#pragma unroll
+                for (int kk = 0; kk < BZ; ++kk) {
+                    const bool gk = (gate >> kk) & 1u;
+                    const unsigned long long b = __ballot(gk);
+                    const uint32_t q = first + lane_rank(b) - r0;
+                    if (gk && q < n_act) {
+                        const float4 res = slots[q];
+                        if (res.x >= 0.0f) {
+                            if constexpr (MODE == MODE_STATUS) {
+                                st[kk] = 6;
+                            } else {
+                                R[kk] = fmaf(res.x, res.y - R[kk], R[kk]);
+                                G[kk] = fmaf(res.x, res.z - G[kk], G[kk]);
+                                B[kk] = fmaf(res.x, res.w - B[kk], B[kk]);
+                                Wt[kk] = fmaf(wv[kk], 1.0f - Wt[kk], Wt[kk]);
+                            }
+                            upd |= 1u << kk;
+                        }
+                    }
+                    first += (uint32_t)__builtin_popcountll(b);
+                }
+                __builtin_amdgcn_wave_barrier();   // the slots are free for the next round
+            }
+            if constexpr (MODE != MODE_STATUS) {
+                cl |= upd;
                 n_upd += (unsigned)__builtin_popcount(upd);
             }
         }
         if constexpr (MODE == MODE_STATUS) {
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk)
-                if (kk < col.kn) status[col.base + (size_t)kk * col.slice] = (uint8_t)st[kk];
+                if (col.active && kk < col.kn) status[col.base + (size_t)kk * col.slice] = (uint8_t)st[kk];
         }
     }
     if constexpr (MODE != MODE_STATUS) {
@@ -552,7 +668,7 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 
 // ------------------------------------------------------------------- depth pyramid
 
-// Level 0: one lane per 8x8 tile of one frame (blockIdx.y = frame).
+// Level 0: one lane per 4x4 tile of one frame (blockIdx.y = frame).
 __global__ __launch_bounds__(BLOCK) void pyramid_base_kernel(const FrameConsts* frames)
 {
     const FrameConsts& c = frames[blockIdx.y];
@@ -598,14 +714,15 @@ __global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* fr
     }
 }
 
-// ------------------------------------------------------------------- weight maps
+// -------------------------------------------------------------------- pixel maps
 
-// Colour weight W (Sec. IV.B: Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dot
-// the unit viewing direction from the camera to the back-projected pixel, Eq. 7) of every
-// pixel of one frame (blockIdx.y = frame).  W depends only on the depth pixel, so every
-// colour voxel that looks up a pixel shares it; the operations are those of the
-// per-voxel definition.
-__global__ __launch_bounds__(BLOCK) void weight_map_kernel(const FrameConsts* frames)
+// Per pixel of one frame (blockIdx.y = frame): its depth d, the x and y of its
+// back-projection P = (((u - c_x) / f_x) d, ((v - c_y) / f_y) d, d) (Eq. 7) and the colour
+// weight W (Sec. IV.B: Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dot the unit
+// viewing direction from the camera to P).  They depend only on the depth pixel, so every
+// colour voxel that looks it up shares them; the operations are those of the per-voxel
+// definition, and one 16-byte read gives a voxel all of them.
+__global__ __launch_bounds__(BLOCK) void pixel_map_kernel(const FrameConsts* frames)
 {
     const FrameConsts& c = frames[blockIdx.y];
     const int p = blockIdx.x * BLOCK + threadIdx.x;
@@ -613,11 +730,11 @@ __global__ __launch_bounds__(BLOCK) void weight_map_kernel(const FrameConsts* fr
     const int x = p % c.dw, y = p / c.dw;
     float W = __builtin_bit_cast(float, kNoNormal);
     const float d = c.depth[p];
+    const float u = (float)x, v = (float)y;
+    const float Px = ((u - c.cx) * c.inv_fx) * d;
+    const float Py = ((v - c.cy) * c.inv_fy) * d;
     if (valid_depth(d) && x + 1 < c.dw && y + 1 < c.dh) {
         const float d1 = c.depth[p + 1], d2 = c.depth[p + c.dw];
-        const float u = (float)x, v = (float)y;
-        const float Px = ((u - c.cx) * c.inv_fx) * d;
-        const float Py = ((v - c.cy) * c.inv_fy) * d;
         const float P1x = ((u + 1.0f - c.cx) * c.inv_fx) * d1;
         const float P1y = ((v - c.cy) * c.inv_fy) * d1;
         const float P2x = ((u - c.cx) * c.inv_fx) * d2;
@@ -634,7 +751,7 @@ __global__ __launch_bounds__(BLOCK) void weight_map_kernel(const FrameConsts* fr
             W = dp / sqrtf(nn * pp);
         }
     }
-    c.wmap[p] = W;
+    c.pmap[p] = make_float4(d, Px, Py, W);
 }
 
 // ------------------------------------------------------------------------ integration
@@ -646,6 +763,7 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 {
     constexpr BrickShape S = BRICK_SHAPES[KIND][SHAPE];
     const int lane = threadIdx.x & (WAVE - 1);
+    __shared__ float4 s_slots[KIND == KIND_COLOUR ? BLOCK : 1];   // colour: sampling jobs
     Counts cnt;
     // the heavy list first, then the light one
     const uint32_t n_heavy = *as_const(a.n_live + KIND);
@@ -669,7 +787,8 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
             geom_brick<MODE, S.bx, S.by, S.bz>(sc, frames, fmask, li, nullptr, cnt);
             if constexpr (MODE == MODE_COUNT) cnt.g_bricks += (unsigned)__builtin_popcountll(fmask);
         } else {
-            colour_brick<MODE, S.bx, S.by, S.bz>(sc, frames, fmask, li - sc.geom_items, nullptr, cnt);
+            colour_brick<MODE, S.bx, S.by, S.bz>(sc, frames, fmask, li - sc.geom_items, nullptr,
+                                                 s_slots + (threadIdx.x & ~(WAVE - 1)), cnt);
             if constexpr (MODE == MODE_COUNT) cnt.c_bricks += (unsigned)__builtin_popcountll(fmask);
         }
     }
@@ -693,13 +812,15 @@ __global__ __launch_bounds__(BLOCK) void integrate_kernel(IntegrateArgs a)
 template <bool COLOUR>
 __global__ __launch_bounds__(BLOCK) void status_kernel(StatusArgs a)
 {
+    __shared__ float4 s_slots[COLOUR ? BLOCK : 1];   // colour: sampling jobs
     const uint32_t li = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
     if (li >= a.n_items) return;
     Counts cnt;
     const FrameConsts* frames = &a.frame;
     constexpr BrickShape S = BRICK_SHAPES[COLOUR ? KIND_COLOUR : KIND_GEOM][0];
     if constexpr (COLOUR)
-        colour_brick<MODE_STATUS, S.bx, S.by, S.bz>(a.scene, frames, 1u, li, a.status, cnt);
+        colour_brick<MODE_STATUS, S.bx, S.by, S.bz>(a.scene, frames, 1u, li, a.status,
+                                                    s_slots + (threadIdx.x & ~(WAVE - 1)), cnt);
     else
         geom_brick<MODE_STATUS, S.bx, S.by, S.bz>(a.scene, frames, 1u, li, a.status, cnt);
 }
@@ -732,12 +853,12 @@ hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int3
     return hipGetLastError();
 }
 
-hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
+hipError_t launch_pixel_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
                               hipStream_t stream)
 {
     if (n_frames <= 0 || max_pixels <= 0) return hipSuccess;
     const unsigned bx = (unsigned)((max_pixels + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL(weight_map_kernel, dim3(bx, (unsigned)n_frames), dim3(BLOCK), 0, stream,
+    hipLaunchKernelGGL(pixel_map_kernel, dim3(bx, (unsigned)n_frames), dim3(BLOCK), 0, stream,
                        frames_dev);
     return hipGetLastError();
 }

@@ -10,9 +10,9 @@ namespace kf {
 // tile count among them.
 hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_tiles0,
                            hipStream_t stream);
-// Colour weight maps (FrameConsts::wmap) of frames_dev[0 .. n_frames); max_pixels: the
-// largest depth image among them.
-hipError_t launch_weight_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
+// Pixel maps (FrameConsts::pmap) of frames_dev[0 .. n_frames); max_pixels: the largest
+// depth image among them.
+hipError_t launch_pixel_maps(const FrameConsts* frames_dev, int32_t n_frames, int32_t max_pixels,
                               hipStream_t stream);
 // One lane per (brick, frame) of the pass: append (brick, live-frame mask) entries.
 hipError_t launch_cull(const CullArgs& a, hipStream_t stream);
@@ -49,6 +49,10 @@ void decimate_mesh(const float* vertices, int64_t n_vertices, const int32_t* tri
 // Adjoint: cull the colour bricks, integrate the live ones backwards (persistent grid),
 // then sum the per-brick extrinsic partials in a fixed order into d_xi.
 hipError_t launch_backward(const BackwardArgs& a, double* d_xi, double* d_pose, int device,
+                           hipStream_t stream);
+
+// Column sums of a [n_rows][width] double array, rows added in order (one block).
+hipError_t launch_sum_rows(const double* rows, uint32_t n_rows, uint32_t width, double* out,
                            hipStream_t stream);
 
 }  // namespace kf

@@ -214,6 +214,8 @@ static bool needs_fibers(const void* k)
         return true;
     static const void* list[] = {
         (const void*)kf::pyramid_up_kernel,
+        (const void*)kf::status_kernel<true>,
+        (const void*)kf::status_kernel<false>,
         (const void*)kf::cull_kernel,
         (const void*)kf::backward_cull_kernel,
         (const void*)kf::reduce_xi_kernel,

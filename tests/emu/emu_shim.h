@@ -179,6 +179,15 @@ inline uint32_t emu_raw_load_b32(emu_rsrc r, uint32_t off, int, int)
     return v;
 }
 #define __builtin_amdgcn_raw_buffer_load_b32(r, o, s, a) emu_raw_load_b32(r, o, s, a)
+struct emu_u32x4 { uint32_t v[4]; };
+inline emu_u32x4 emu_raw_load_b128(emu_rsrc r, uint32_t off, int, int)
+{
+    emu_u32x4 x{};
+    if ((uint64_t)off + 16 > r.bytes) return x;
+    memcpy(x.v, r.p + off, 16);
+    return x;
+}
+#define __builtin_amdgcn_raw_buffer_load_b128(r, o, s, a) emu_raw_load_b128(r, o, s, a)
 
 // hardware reciprocal (v_rcp_f32, within 1 ulp).  The library uses it in two ways: the
 // culling's corner projections, which allow one ulp and a pixel of slack, and recip(),
@@ -188,6 +197,9 @@ inline uint32_t emu_raw_load_b32(emu_rsrc r, uint32_t off, int, int)
 inline float emu_rcpf(float x) { return 1.0f / x; }
 #define __builtin_amdgcn_rcpf(x) emu_rcpf(x)
 
+// v_mul_u32_u24: the low 32 bits of the product of the operands' low 24 bits.
+inline unsigned __umul24(unsigned a, unsigned b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
+
 // ---------------------------------------------------------------- runtime API
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101, hipErrorNotSupported = 801 };
@@ -196,7 +208,7 @@ typedef struct emu_event* hipEvent_t;
 typedef struct emu_graph* hipGraph_t;
 typedef struct emu_graph_exec* hipGraphExec_t;
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount = 1 };
-enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 };
+enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2, hipHostMallocDefault = 0 };
 enum hipStreamCaptureMode { hipStreamCaptureModeThreadLocal = 1 };
 

@@ -335,4 +335,13 @@ for case, cap in (("backward_direct", "0"), ("backward_overflow", "3000")):
     finally:
         del os.environ["KF_BWD_RECORDS"]
 tick("backward direct / overflow")
+# scans longer than one adjoint call: chunks of 12 (3 chunks of the 32-frame scan) and of 2
+# (3 chunks of the 6-frame scan, every chunk after the first starting from stored weights)
+for case, chunk, sp, f in (("backward_chunked", "12", spec32, fr32), ("backward_chunked_6", "2", spec6, fr6)):
+    os.environ["KF_BWD_CHUNK"] = chunk
+    try:
+        out[case] = backward_case(sp, f, pose=True)
+    finally:
+        del os.environ["KF_BWD_CHUNK"]
+tick("backward chunked")
 print("JSON:" + json.dumps(out), flush=True)

@@ -156,8 +156,8 @@ def test_batch_rejects_bad_arguments():
 def test_noalloc_batch_refuses_workspace_above_its_array():
     """kf_integrate_batch_noalloc checks its arguments like kf_integrate_batch and returns
     KF_E_RANGE, before any device work, when the batch's workspace exceeds the library's
-    64 MiB array (a 512^3 / 1024^3 pair of volumes needs 75 MB of live lists alone; the
-    buffers here are fake addresses)."""
+    256 MiB array (a 512^3 / 1024^3 pair of volumes needs 75 MB of live lists, and 64
+    frames of 640x480 take 5 MB each; the buffers here are fake addresses)."""
     lib = L.load()
     spec = VolumeSpec.cube(512, 2, 1.0)
     bufs = L.VolumeBuffers(*([0x1000] * 6))
@@ -166,12 +166,13 @@ def test_noalloc_batch_refuses_workspace_above_its_array():
     K = np.ascontiguousarray([[525.0, 0, 319.5], [0, 525.0, 239.5], [0, 0, 1]])
     Kr = np.ascontiguousarray([[1050.0, 0, 959.5], [0, 1050.0, 539.5], [0, 0, 1]])
     T = np.ascontiguousarray(np.eye(4))
+    Tw = np.ascontiguousarray(np.tile(np.eye(4), (64, 1, 1)))
     try:
         sc = (L.Scene * 1)()
-        sc[0].vol, sc[0].n_frames, sc[0].depth, sc[0].rgb = h.value, 1, 0x2000, 0x3000
+        sc[0].vol, sc[0].n_frames, sc[0].depth, sc[0].rgb = h.value, 64, 0x2000, 0x3000
         sc[0].fmt, sc[0].dw, sc[0].dh, sc[0].cw, sc[0].ch = L.KF_RGB8, 640, 480, 1920, 1080
         sc[0].K_d, sc[0].K_rgb = K.ctypes.data, Kr.ctypes.data
-        sc[0].T_rgb_from_d = sc[0].T_world_from_cam = T.ctypes.data
+        sc[0].T_rgb_from_d, sc[0].T_world_from_cam = T.ctypes.data, Tw.ctypes.data
         sc[0].trunc_m, sc[0].w_max = 0.008, 128.0
         assert lib.kf_integrate_batch_noalloc(sc, 1, 1, None) == L.KF_E_RANGE
         assert b"workspace" in lib.kf_last_error()
@@ -402,7 +403,7 @@ def test_backward_rejects_bad_arguments():
     d = _desc()
     args = [C.byref(d), None, 65, C.c_void_p(0x1), C.c_void_p(0x1), 640, 480, 1920, 1080,
             None, None, None, None, C.c_void_p(0x1), C.c_void_p(0x1), C.c_void_p(0x1), None, None]
-    assert lib.kf_integrate_backward(*args) == L.KF_E_UNSUPPORTED
+    assert lib.kf_integrate_backward(*args) == L.KF_E_ARG     # K_d is NULL (65 frames: chunked)
     args[2] = 4
     assert lib.kf_integrate_backward(*args) == L.KF_E_ARG     # K_d is NULL
     args[2] = -1

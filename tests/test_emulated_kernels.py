@@ -57,8 +57,10 @@ def test_emulated_kernels_match_oracle(emu_build, emulated):
     assert res["nearest_mismatches"] == 0 and res["nearest_status_mismatches"] == 0
     assert res["mesh_mismatches"] == 0
     assert res["decimate_mismatches"] == 0
-    for case in ("backward_6", "backward_32", "backward_odd", "backward_direct", "backward_overflow"):
+    for case in ("backward_6", "backward_32", "backward_odd", "backward_direct", "backward_overflow",
+                 "backward_chunked", "backward_chunked_6"):
         assert res[case]["rgb"] <= 1.0 and res[case]["xi"] <= 1.0, res
-    for case in ("backward_6", "backward_odd", "backward_direct", "backward_overflow"):
+    for case in ("backward_6", "backward_odd", "backward_direct", "backward_overflow",
+                 "backward_chunked", "backward_chunked_6"):
         # with the depth-pose adjoint
         assert res[case]["pose"] <= 1.0, res

@@ -232,3 +232,46 @@ def test_backward_image_gradient_paths_agree(monkeypatch):
         assert torch.equal(d_xi, ref_xi), f"{name}: extrinsic gradient differs"
         err = float((d_rgb - ref_rgb).abs().max())
         assert err <= 1e-5 * scale, f"{name}: image gradient differs by {err} (scale {scale})"
+
+
+def test_backward_longer_than_one_call(oracle):
+    """80 frames (a call replays at most 64: chunks of 64 and 16, the second starting from
+    the colour weights the first leaves) against the oracle's FP64 adjoint, with the
+    depth-pose gradients."""
+    say("backward: tiny, 80 frames in two chunks")
+    spec, fr = configs.tiny(n_frames=80)
+    fr = fr.as_float_rgb()
+    g = configs.gradient_weights(spec.n_colour)
+    d_rgb, d_xi, d_pose = kf.integrate_backward(spec, kf.Scan.from_frames(fr.to(DEV)), g.to(DEV),
+                                                pose=True)
+    want_rgb, want_xi, want_pose = oracle.backward(spec, fr, g.numpy().astype(np.float64),
+                                                   decide_f32=True, pose=True)
+    torch.cuda.synchronize()
+    _close(d_rgb.cpu().numpy(), want_rgb)
+    _close(d_xi.cpu().numpy(), want_xi)
+    _close(d_pose.cpu().numpy(), want_pose)
+    assert np.abs(want_rgb[64:]).max() > 0 and np.abs(want_rgb[:64]).max() > 0
+
+
+def test_backward_chunks_agree_with_one_call(monkeypatch, scan):
+    """The same 40-frame adjoint in one call and in chunks of 16 and of 7 frames (forced),
+    with initial colour weights: equal up to the rounding of the products of (1 - alpha)
+    across chunk boundaries and the order of the d_xi sums."""
+    say("backward: tiny, 40 frames, one call against chunks of 16 and 7")
+    spec, fr = configs.tiny(n_frames=40)
+    fr = fr.as_float_rgb()
+    s = kf.Scan.from_frames(fr.to(DEV))
+    g = configs.gradient_weights(spec.n_colour, device=DEV)
+    w0 = torch.as_tensor(np.random.default_rng(8).uniform(0.0, 0.5, spec.n_colour).astype(np.float32),
+                         device=DEV)
+    monkeypatch.delenv("KF_BWD_CHUNK", raising=False)
+    ref = kf.integrate_backward(spec, s, g, w0, pose=True)
+    for chunk in ("16", "7"):
+        monkeypatch.setenv("KF_BWD_CHUNK", chunk)
+        got = kf.integrate_backward(spec, s, g, w0, pose=True)
+        torch.cuda.synchronize()
+        for name, x, y in zip(("d_rgb", "d_xi", "d_pose"), got, ref):
+            x, y = x.double().cpu().numpy(), y.double().cpu().numpy()
+            err = np.abs(x - y).max()
+            assert err <= 1e-5 * np.abs(y).max(), f"chunks of {chunk}: {name} differs by {err}"
+    monkeypatch.delenv("KF_BWD_CHUNK", raising=False)
