@@ -414,7 +414,7 @@ __global__ __launch_bounds__(BWD_BLOCK) void backward_kernel(BackwardArgs a)
                 } else {
                     const size_t pos = (size_t)s_seg[r] + s_wcnt[wave][r] + lane_rank(bal);
                     float2* rec = (float2*)(a.records + pos * 6);
-                    rec[0] = make_float2(__builtin_bit_cast(float, (uint32_t)pix), ax);
+                    rec[0] = make_float2(__builtin_bit_cast(float, (uint32_t)(int)x0 | (uint32_t)(int)y0 << 16), ax);
                     rec[1] = make_float2(ay, gb0);
                     rec[2] = make_float2(gb1, gb2);
                 }
@@ -549,57 +549,34 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(BackwardArgs a)
 
 // One block per (tile, frame): the records of the segments binned there, added in LDS
 // over the tile's pixels (a record adds g beta times its four bilinear weights to the
-// pixels of its cell that lie in the tile), then added to the image gradient.
+// pixels of its cell that lie in the tile), then added to the image gradient.  Each wave
+// takes whole segments in turn, its lanes reading consecutive records.
 constexpr int IMG_BLOCK = 256;
-constexpr int IMG_SEGS = 256;   // segments staged per round
 
 __global__ __launch_bounds__(IMG_BLOCK) void backward_image_kernel(BackwardArgs a)
 {
     __shared__ float s_acc[BWD_TILE_W * BWD_TILE_H * 3];
-    __shared__ uint32_t s_first[IMG_SEGS], s_off[IMG_SEGS + 1];
     const uint32_t n_tiles = (uint32_t)(a.tiles_x * a.tiles_y);
     const uint32_t tile = blockIdx.x, f = blockIdx.y;
     const size_t bin = (size_t)f * n_tiles + tile;
     const uint32_t b0 = a.bin_count[bin], b1 = a.bin_count[bin + 1];
     if (b0 == b1) return;   // the whole block
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
     const FrameConsts& c = a.frames[f];
     const int tx0 = (int)(tile % (uint32_t)a.tiles_x) * BWD_TILE_W;
     const int ty0 = (int)(tile / (uint32_t)a.tiles_x) * BWD_TILE_H;
     for (int q = t; q < BWD_TILE_W * BWD_TILE_H * 3; q += IMG_BLOCK) s_acc[q] = 0.0f;
-    for (uint32_t s0 = b0; s0 < b1; s0 += IMG_SEGS) {
-        const uint32_t ns = min((uint32_t)IMG_SEGS, b1 - s0);
-        __syncthreads();   // the previous round's tables are no longer read
-        uint32_t cnt = 0;
-        if ((uint32_t)t < ns) {
-            const uint4 sg = a.segs[a.bin_segs[s0 + t]];
-            s_first[t] = sg.x;
-            cnt = sg.y;
-        }
-        // exclusive scan of the counts over the block (IMG_SEGS == IMG_BLOCK)
-        s_off[t + 1] = cnt;
-        if (t == 0) s_off[0] = 0;
-        __syncthreads();
-        for (int off = 1; off < IMG_SEGS; off <<= 1) {
-            const uint32_t y = t + 1 > off ? s_off[t + 1 - off] : 0u;
-            __syncthreads();
-            s_off[t + 1] += y;
-            __syncthreads();
-        }
-        const uint32_t total = s_off[ns];
-        for (uint32_t q = t; q < total; q += IMG_BLOCK) {
-            // the segment holding record q of the round
-            uint32_t lo = 0, hi = ns - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) / 2;
-                if (s_off[mid] <= q) lo = mid;
-                else hi = mid - 1;
-            }
-            const float* rec = a.records + ((size_t)s_first[lo] + (q - s_off[lo])) * 6;
-            const uint32_t pix = __builtin_bit_cast(uint32_t, rec[0]);
-            const float ax = rec[1], ay = rec[2];
-            const float gv[3] = {rec[3], rec[4], rec[5]};
-            const int x0 = (int)(pix % (uint32_t)c.cw), y0 = (int)(pix / (uint32_t)c.cw);
+    __syncthreads();
+    for (uint32_t s = b0 + (uint32_t)(t / WAVE); s < b1; s += IMG_BLOCK / WAVE) {
+        const uint4 sg = a.segs[first_lane_u32(a.bin_segs[s])];
+        const uint32_t first = first_lane_u32(sg.x), cnt = first_lane_u32(sg.y);
+        for (uint32_t r = (uint32_t)lane; r < cnt; r += WAVE) {
+            const float2* rec = (const float2*)(a.records + ((size_t)first + r) * 6);
+            const float2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
+            const uint32_t cell = __builtin_bit_cast(uint32_t, r0.x);   // x | y << 16
+            const float ax = r0.y, ay = r1.x;
+            const float gv[3] = {r1.y, r2.x, r2.y};
+            const int x0 = (int)(cell & 0xFFFFu), y0 = (int)(cell >> 16);
             const float w[4] = {(1.0f - ax) * (1.0f - ay), ax * (1.0f - ay), (1.0f - ax) * ay, ax * ay};
 #pragma unroll
             for (int p = 0; p < 4; ++p) {

@@ -1130,7 +1130,8 @@ kf_status backward_call(const kf_volume_desc* desc, const float* w_col0, int32_t
     // atomics instead), one segment per live brick and frame, four bins per segment
     a.tiles_x = (int32_t)ceil_div(cw, kf::BWD_TILE_W);
     a.tiles_y = (int32_t)ceil_div(ch, kf::BWD_TILE_H);
-    const bool binned = n_frames > 0 && !wc_out && a.tiles_x <= 65535 && a.tiles_y <= 65535;
+    // a record holds its cell's x and y in 16 bits each
+    const bool binned = n_frames > 0 && !wc_out && cw <= 65536 && ch <= 65536;
     uint64_t rec_cap = binned ? (uint64_t)n_frames * (uint64_t)cw * (uint64_t)ch / 2 : 0;
     if (binned && rec_cap < (1u << 20)) rec_cap = 1u << 20;
     if (rec_cap > 0x7FFFFFFFull) rec_cap = 0x7FFFFFFFull;

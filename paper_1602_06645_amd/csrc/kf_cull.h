@@ -17,7 +17,8 @@ __device__ __forceinline__ bool valid_depth(float d)
 // Valid-depth (min, max) over pixels [u0,u1] x [v0,v1] (inclusive, inside the image),
 // read from the finest pyramid level on which the box spans at most 4 x 4 tiles.  The
 // tiles cover the box, so the range contains every depth inside it.
-__device__ inline float2 depth_range(const FrameConsts& c, int u0, int u1, int v0, int v1)
+template <class C>
+__device__ inline float2 depth_range(const C& c, int u0, int u1, int v0, int v1)
 {
     int w = c.pyr_w0, h = c.pyr_h0, off = 0, s = PYR_SHIFT;
     for (int l = 0; l < c.pyr_levels; ++l) {
@@ -50,11 +51,12 @@ __device__ inline float2 depth_range(const FrameConsts& c, int u0, int u1, int v
 // coordinates up to a few thousand).  A colour voxel needs a depth within sigma of
 // its own z (|p - P| >= |z - d|); a geometry voxel needs a depth no more than trunc in
 // front of it.  1 mm of slack covers the single-precision rounding of z and d.
-__device__ inline bool brick_live(const FrameConsts& c, bool colour, int i0, int i1, int j0, int j1,
-                           int k0, int k1)
+template <class C>
+__device__ inline bool brick_live(const C& c, bool colour, int i0, int i1, int j0, int j1, int k0,
+                                  int k1)
 {
-    const float* A = colour ? c.Ac : c.Ag;
-    const float* b = colour ? c.bc : c.bg;
+    const auto* A = colour ? c.Ac : c.Ag;
+    const auto* b = colour ? c.bc : c.bg;
     float zmin = __builtin_huge_valf(), zmax = -__builtin_huge_valf();
     float xmin = __builtin_huge_valf(), xmax = -__builtin_huge_valf();
     float ymin = __builtin_huge_valf(), ymax = -__builtin_huge_valf();

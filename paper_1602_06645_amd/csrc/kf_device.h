@@ -154,7 +154,7 @@ struct BackwardArgs {
     const double* pose_adjoint;       // [n_frames][12]: R (row-major) and t of each frame's
                                       // T_hd_from_world, for d_pose = -Ad^T (frame partial)
     // image-gradient records and their (frame, HD tile) bins (see kf_backward.hip)
-    float* records;                   // [rec_cap][6]: pixel index (bits), ax, ay, g beta (3)
+    float* records;                   // [rec_cap][6]: cell x | y << 16 (bits), ax, ay, g beta (3)
     unsigned long long* rec_next;     // records reserved so far (may pass rec_cap)
     uint32_t rec_cap;                 // 0: every update is scattered with atomics
     uint4* segs;                      // [seg_cap] (first record, count, frame | spans, tiles)

@@ -619,19 +619,21 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
     const uint32_t nf = s_nf;
     if (nf == 0) return;   // the whole block: no brick of the chunk is live
     const uint32_t nbr = (uint32_t)(nbx * nby * nbz);
-    for (uint32_t t = threadIdx.x; t < nbr * nf; t += BLOCK) {
-        // frame-major: the lanes of a wave share a frame (its constants are read once per
-        // wave) and OR into different bricks' masks
-        const uint32_t r = t / nbr;
-        const uint32_t q = t - r * nbr;               // brick within the chunk
-        const int f = s_frame[r];
+    // one lane per brick of the chunk, the waves taking the listed frames in turn: a wave's
+    // frame is uniform, so its constants come through scalar loads
+    {
+        const uint32_t q = (uint32_t)lane;
         const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
         const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
         const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
         const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
         const int k0 = bz * BZ, k1 = min(dim[2], k0 + BZ) - 1;
-        if (a.disable || brick_live(frames[f], colour, i0, i1, j0, j1, k0, k1))
-            atomicOr(&s_mask[q], 1ull << f);
+        const const_ptr<FrameConsts> cframes = as_const(frames);
+        for (uint32_t r = threadIdx.x / WAVE; r < nf; r += BLOCK / WAVE) {
+            const int f = (int)first_lane_u32(s_frame[r]);
+            if (q < nbr && (a.disable || brick_live(cframes[f], colour, i0, i1, j0, j1, k0, k1)))
+                atomicOr(&s_mask[q], 1ull << f);   // the four waves OR into the same masks
+        }
     }
     __syncthreads();
     if (threadIdx.x < WAVE) {
@@ -831,6 +833,16 @@ __global__ void fill_f32_kernel(float* p, size_t n, float v)
     for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = v;
 }
 
+// The same for a 16-byte aligned array, four elements per store (the last n % 4 by the
+// first thread).
+__global__ void fill_f32x4_kernel(float4* p, size_t n, float v)
+{
+    const size_t n4 = n / 4, stride = (size_t)gridDim.x * blockDim.x;
+    const float4 v4 = make_float4(v, v, v, v);
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) p[q] = v4;
+    if (blockIdx.x == 0 && threadIdx.x < n - 4 * n4) ((float*)(p + n4))[threadIdx.x] = v;
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -942,6 +954,12 @@ hipError_t persistent_grid(int mode, int kind, int shape, int device, uint32_t* 
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
+    if (((uintptr_t)p & 15u) == 0) {
+        const size_t want = (n / 4 + 255) / 256;
+        const unsigned blocks = (unsigned)(want < 1 ? 1 : want < 65536 ? want : 65536);
+        hipLaunchKernelGGL(fill_f32x4_kernel, dim3(blocks), dim3(256), 0, stream, (float4*)p, n, v);
+        return hipGetLastError();
+    }
     const size_t want = (n + 255) / 256;
     const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
     hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks), dim3(256), 0, stream, p, n, v);
