@@ -246,7 +246,7 @@ void frame_consts(const kf_volume_desc& vd, const double* K_d, const double* K_r
     out->ch = ch;
     out->depth = depth;
     out->rgb = rgb;
-    // the depth pyramid: 4x4-pixel tiles, halved until one tile covers the image
+    // the depth pyramid: 2x2-pixel tiles, halved until one tile covers the image
     out->pyr = nullptr;
     out->pyr_w0 = (dw + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
     out->pyr_h0 = (dh + (1 << kf::PYR_SHIFT) - 1) >> kf::PYR_SHIFT;
@@ -455,11 +455,11 @@ kf_status plan_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, const 
 }
 
 // Device image of a plan:
-//   [frame table][scene table of each pass][kPassCounters counters per pass][live lists:
-//   heavy and light][pyramids][pixel maps]
+//   [frame table][scene table of each pass][kPassCounters counters per pass][two live
+//   buffers (passes alternate), each a heavy and a light list][pyramids][pixel maps]
 struct DeviceTables {
     std::vector<unsigned char> host;
-    size_t frames_off = 0, counters_off = 0, live_off = 0, pyr_off = 0, bytes = 0;
+    size_t frames_off = 0, counters_off = 0, live_off = 0, live_entries = 0, pyr_off = 0, bytes = 0;
     std::vector<size_t> pass_off, frame_pyr_off, frame_pmap_off;
     int32_t max_tiles0 = 0, max_pixels = 0;
 };
@@ -479,7 +479,8 @@ void layout_tables(const BatchPlan& p, DeviceTables* t)
     uint32_t max_items = 0;
     for (uint32_t n : p.pass_items) max_items = n > max_items ? n : max_items;
     t->live_off = off;
-    off = align(off + 2 * (size_t)max_items * sizeof(uint4));
+    t->live_entries = 2 * (size_t)max_items;   // one buffer: heavy list, light list
+    off = align(off + 2 * t->live_entries * sizeof(uint4));   // two buffers, passes alternate
     t->pyr_off = off;
     for (const auto& fc : p.frames) {
         t->frame_pyr_off.push_back(off);
@@ -533,11 +534,35 @@ struct PassEvents {
     int32_t n = 0;
 };
 
+// A side stream per device on which the culling of pass p + 1 runs while pass p
+// integrates (the cull reads only frame data; the two live buffers alternate), with the
+// events that order the two streams.  Enqueueing on it is serialised per device.
+struct CullSide {
+    std::mutex mu;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[6] = {};   // start, cull done (2), integration done (2), end
+};
+CullSide g_side[64];
+
+kf_status cull_side(int device, CullSide** out)
+{
+    if (device < 0 || device >= 64) return fail(KF_E_UNSUPPORTED, "device index above 63");
+    CullSide& c = g_side[device];
+    if (!c.stream) KF_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking), "hipStreamCreate");
+    for (hipEvent_t& e : c.ev)
+        if (!e) KF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    *out = &c;
+    return KF_OK;
+}
+
 // Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`:
-// blocks of the geometry and colour persistent launches (resident_grid).
+// blocks of the geometry and colour persistent launches (resident_grid).  With `side`
+// (its mutex held by the caller) the culling runs one pass ahead on the side stream;
+// without it everything runs on `stream` in order.
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
                          const int shape[2], unsigned long long* counters, const uint32_t grid[2],
-                         hipStream_t stream, const PassEvents& ev = PassEvents())
+                         hipStream_t stream, const PassEvents& ev = PassEvents(),
+                         CullSide* side = nullptr)
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
@@ -547,12 +572,14 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
     KF_HIP(kf::launch_fill_u32(cnt, kPassCounters * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint4* live = (uint4*)(dev + t.live_off);
     const int disable = cull_disabled() ? 1 : 0;
-    for (size_t q = 0; q < p.passes.size(); ++q) {
-        if (p.pass_items[q] == 0) continue;
-        const kf::SceneDev* scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
+    std::vector<size_t> run;   // passes with work
+    for (size_t q = 0; q < p.passes.size(); ++q)
+        if (p.pass_items[q] != 0) run.push_back(q);
+    auto cull_args = [&](size_t r) {
+        const size_t q = run[r];
         kf::CullArgs c;
         memset(&c, 0, sizeof c);
-        c.scenes = scenes;
+        c.scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
         c.frames = frames;
         c.n_scenes = (int32_t)p.passes[q].size();
         c.n_items = p.pass_items[q];
@@ -560,16 +587,39 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         c.disable = disable;
         c.max_frames = 0;
         for (const kf::SceneDev& d : p.passes[q]) c.max_frames = d.n_frames > c.max_frames ? d.n_frames : c.max_frames;
-        c.live = live;
+        c.live = live + (r % 2) * t.live_entries;
         c.n_live = cnt + kPassCounters * q;
-        KF_HIP(kf::launch_cull(c, stream), "cull launch");
+        return c;
+    };
+    hipStream_t cs = side ? side->stream : stream;
+    if (side && !run.empty()) {
+        KF_HIP(hipEventRecord(side->ev[0], stream), "hipEventRecord");
+        KF_HIP(hipStreamWaitEvent(cs, side->ev[0], 0), "hipStreamWaitEvent");
+    }
+    for (size_t r = 0; r < run.size(); ++r) {
+        const size_t q = run[r];
+        if (!side) {
+            KF_HIP(kf::launch_cull(cull_args(r), stream), "cull launch");
+        } else {
+            if (r == 0) {
+                KF_HIP(kf::launch_cull(cull_args(0), cs), "cull launch");
+                KF_HIP(hipEventRecord(side->ev[1], cs), "hipEventRecord");
+            }
+            if (r + 1 < run.size()) {
+                // the next pass's buffer was last read by pass r - 1
+                if (r >= 1) KF_HIP(hipStreamWaitEvent(cs, side->ev[3 + (r - 1) % 2], 0), "hipStreamWaitEvent");
+                KF_HIP(kf::launch_cull(cull_args(r + 1), cs), "cull launch");
+                KF_HIP(hipEventRecord(side->ev[1 + (r + 1) % 2], cs), "hipEventRecord");
+            }
+            KF_HIP(hipStreamWaitEvent(stream, side->ev[1 + r % 2], 0), "hipStreamWaitEvent");
+        }
         kf::IntegrateArgs a;
         memset(&a, 0, sizeof a);
-        a.scenes = scenes;
+        a.scenes = (const kf::SceneDev*)(dev + t.pass_off[q]);
         a.frames = frames;
-        a.n_scenes = c.n_scenes;
-        a.live = live;
-        a.cap = c.n_items;
+        a.n_scenes = (int32_t)p.passes[q].size();
+        a.live = live + (r % 2) * t.live_entries;
+        a.cap = p.pass_items[q];
         a.n_live = cnt + kPassCounters * q;
         a.queue = cnt + kPassCounters * q + 4;
         a.counters = counters;
@@ -579,6 +629,12 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
         if (timed && ev.mid) KF_HIP(hipEventRecord((hipEvent_t)ev.mid[q], stream), "hipEventRecord");
         KF_HIP(kf::launch_integrate(mode, kf::KIND_COLOUR, shape[1], a, grid[1], stream), "integrate launch");
         if (timed) KF_HIP(hipEventRecord((hipEvent_t)ev.end[q], stream), "hipEventRecord");
+        if (side) KF_HIP(hipEventRecord(side->ev[3 + r % 2], stream), "hipEventRecord");
+    }
+    if (side && !run.empty()) {
+        // the caller's stream continues only after the side stream's last work
+        KF_HIP(hipEventRecord(side->ev[5], cs), "hipEventRecord");
+        KF_HIP(hipStreamWaitEvent(stream, side->ev[5], 0), "hipStreamWaitEvent");
     }
     return KF_OK;
 }
@@ -682,9 +738,12 @@ kf_status run_graph(const kf_scene* scenes, int32_t n_scenes, int32_t K, const i
         he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamCreate"); }
     }
+    CullSide* side = nullptr;
+    if ((st = cull_side(device, &side)) != KF_OK) { drop_entry(e); return st; }
+    std::lock_guard<std::mutex> side_lock(side->mu);
     he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he != hipSuccess) { drop_entry(e); return hip_fail(he, "hipStreamBeginCapture"); }
-    st = enqueue_passes(plan, t, e.dev, kf::MODE_INTEGRATE, shape, nullptr, grid, cs);
+    st = enqueue_passes(plan, t, e.dev, kf::MODE_INTEGRATE, shape, nullptr, grid, cs, PassEvents(), side);
     hipGraph_t graph = nullptr;
     he = hipStreamEndCapture(cs, &graph);
     if (st != KF_OK) { if (graph) (void)hipGraphDestroy(graph); drop_entry(e); return st; }
@@ -724,7 +783,16 @@ kf_status run_batch(const kf_scene* scenes, int32_t n_scenes, int32_t K, int mod
     KF_HIP(workspace_alloc((void**)&dev, t.bytes, stream), "hipMallocAsync");
     fill_tables(plan, dev, &t);
     st = staged_copy(dev, t.host.data(), t.host.size(), stream);
-    if (st == KF_OK) st = enqueue_passes(plan, t, dev, mode, shape, counters, grid, stream, ev);
+    if (st == KF_OK) {
+        int device = 0;
+        CullSide* side = nullptr;
+        if (hipGetDevice(&device) != hipSuccess) st = fail(KF_E_DEVICE, "hipGetDevice failed");
+        else st = cull_side(device, &side);
+        if (st == KF_OK) {
+            std::lock_guard<std::mutex> side_lock(side->mu);
+            st = enqueue_passes(plan, t, dev, mode, shape, counters, grid, stream, ev, side);
+        }
+    }
     hipError_t he = hipFreeAsync(dev, stream);
     if (st != KF_OK) return st;
     if (he != hipSuccess) return hip_fail(he, "hipFreeAsync");

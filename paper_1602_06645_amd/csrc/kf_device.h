@@ -28,7 +28,7 @@ constexpr int MAX_BZ = 16;
 constexpr int CBX = 8, CBY = 8, ZS = 8;
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;              // four waves that work independently
-constexpr int PYR_SHIFT = 2;            // level-0 tiles of the depth pyramid: 4 x 4 pixels
+constexpr int PYR_SHIFT = 1;            // level-0 tiles of the depth pyramid: 2 x 2 pixels
 constexpr int XI_BLOCKS = 256;          // first-stage blocks of the adjoint's dxi reduction
 constexpr int CHUNK = 4;                // culling chunks: CHUNK^3 bricks of one kind
 

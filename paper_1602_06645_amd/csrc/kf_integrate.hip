@@ -2,7 +2,7 @@
 // colour volume (Sec. IV.B, Eq. 5-10, with the depth-to-HD mapping of Eq. 1-4).
 //
 // A pass applies up to 64 consecutive frames of every scan in the launch:
-//   1. pyramid kernels: per frame, min/max of the valid depths over 4x4-pixel tiles and
+//   1. pyramid kernels: per frame, min/max of the valid depths over 2x2-pixel tiles and
 //      their 2x2 reductions (built once per batch call for all frames);
 //   2. cull kernel: one thread per (brick, frame) decides whether any voxel of the
 //      brick can pass the depth tests (conservatively, from the brick's corners and the
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 
 // ------------------------------------------------------------------- depth pyramid
 
-// Level 0: one lane per 4x4 tile of one frame (blockIdx.y = frame).
+// Level 0: one lane per 2x2 tile of one frame (blockIdx.y = frame).
 __global__ __launch_bounds__(BLOCK) void pyramid_base_kernel(const FrameConsts* frames)
 {
     const FrameConsts& c = frames[blockIdx.y];

@@ -294,6 +294,7 @@ hipError_t hipHostMalloc(void** p, size_t n, int) { *p = malloc(n ? n : 1); retu
 hipError_t hipHostFree(void* p) { free(p); return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, int) { *e = (hipEvent_t)malloc(8); return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, int) { *s = (hipStream_t)malloc(8); return hipSuccess; }
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }

@@ -233,6 +233,7 @@ hipError_t hipHostMalloc(void** p, size_t n, int f);
 hipError_t hipHostFree(void* p);
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, int f);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s);
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, int f);
 typedef struct emu_pool* hipMemPool_t;
