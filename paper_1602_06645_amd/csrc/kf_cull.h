@@ -46,49 +46,62 @@ __device__ inline float2 depth_range(const C& c, int u0, int u1, int v0, int v1)
 // their depths lie between the corners' and, when all corners are in front of the
 // camera, their projections lie in the corners' bounding box; a voxel's pixel is the
 // nearest integer to its projection, so the pixels lie in [ceil(min - 1/2), floor(max +
-// 1/2)], taken with 1/16 pixel to spare for the rounding of the voxel and corner
-// coordinates and the hardware reciprocal (together below 1e-3 pixel at image
-// coordinates up to a few thousand).  A colour voxel needs a depth within sigma of
-// its own z (|p - P| >= |z - d|); a geometry voxel needs a depth no more than trunc in
-// front of it.  1 mm of slack covers the single-precision rounding of z and d.
+// 1/2)], taken with 1/16 pixel to spare plus the rounding of the coordinates: the corners
+// are the first corner plus the box's edge vectors (additions), the voxels' own
+// coordinates are rounded too, and the projection uses the hardware reciprocal (within 1
+// ulp), all within 1e-6 of the coordinates' magnitude, which the margin converts to
+// pixels at the nearest corner; a box with a corner within 5 cm of the camera plane (or
+// behind it) takes the whole image.  A colour voxel needs a depth within sigma of its own z
+// (|p - P| >= |z - d|); a geometry voxel needs a depth no more than trunc in front of it.
+// 1 mm of slack covers the single-precision rounding of z and d.
 template <class C>
 __device__ inline bool brick_live(const C& c, bool colour, int i0, int i1, int j0, int j1, int k0,
                                   int k1)
 {
     const auto* A = colour ? c.Ac : c.Ag;
     const auto* b = colour ? c.bc : c.bg;
+    const float fi = (float)i0, fj = (float)j0, fk = (float)k0;
+    const float di = (float)(i1 - i0), dj = (float)(j1 - j0), dk = (float)(k1 - k0);
+    // corner q = first corner + (q & 1) di e_i + (q & 2) dj e_j + (q & 4) dk e_k, per coordinate
+    float P[3][8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        P[a][0] = fmaf(A[3 * a + 2], fk, fmaf(A[3 * a + 1], fj, fmaf(A[3 * a], fi, b[a])));
+        P[a][1] = P[a][0] + A[3 * a] * di;
+        const float ej = A[3 * a + 1] * dj, ek = A[3 * a + 2] * dk;
+        P[a][2] = P[a][0] + ej;
+        P[a][3] = P[a][1] + ej;
+#pragma unroll
+        for (int q = 4; q < 8; ++q) P[a][q] = P[a][q - 4] + ek;
+    }
     float zmin = __builtin_huge_valf(), zmax = -__builtin_huge_valf();
     float xmin = __builtin_huge_valf(), xmax = -__builtin_huge_valf();
     float ymin = __builtin_huge_valf(), ymax = -__builtin_huge_valf();
+    float amax = 0.0f;   // largest |X|, |Y| among the corners
     bool near = false;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const float fi = (float)((q & 1) ? i1 : i0);
-        const float fj = (float)((q & 2) ? j1 : j0);
-        const float fk = (float)((q & 4) ? k1 : k0);
-        const float X = fmaf(A[2], fk, fmaf(A[1], fj, fmaf(A[0], fi, b[0])));
-        const float Y = fmaf(A[5], fk, fmaf(A[4], fj, fmaf(A[3], fi, b[1])));
-        const float Z = fmaf(A[8], fk, fmaf(A[7], fj, fmaf(A[6], fi, b[2])));
+        const float Z = P[2][q];
         zmin = fminf(zmin, Z);
         zmax = fmaxf(zmax, Z);
-        if (Z > 1e-3f) {
-            // hardware reciprocal (within 1 ulp): its error, ~1e-7 of the pixel coordinate,
-            // is far inside the one-pixel widening of the box below
-            const float rz = __builtin_amdgcn_rcpf(Z);
-            const float x = c.fx * (X * rz) + c.cx, y = c.fy * (Y * rz) + c.cy;
-            xmin = fminf(xmin, x);
-            xmax = fmaxf(xmax, x);
-            ymin = fminf(ymin, y);
-            ymax = fmaxf(ymax, y);
-        } else {
-            near = true;
-        }
+        near |= !(Z > 0.05f);
+        amax = fmaxf(amax, fmaxf(fabsf(P[0][q]), fabsf(P[1][q])));
+        const float rz = __builtin_amdgcn_rcpf(Z);
+        const float x = P[0][q] * rz, y = P[1][q] * rz;   // X / Z, Y / Z
+        xmin = fminf(xmin, x);
+        xmax = fmaxf(xmax, x);
+        ymin = fminf(ymin, y);
+        ymax = fmaxf(ymax, y);
     }
     if (!(zmax > -1e-4f)) return false;                  // entirely behind the camera
     int u0 = 0, u1 = c.dw - 1, v0 = 0, v1 = c.dh - 1;
     if (!near) {
-        const float fu0 = ceilf(xmin - 0.5625f), fu1 = floorf(xmax + 0.5625f);
-        const float fv0 = ceilf(ymin - 0.5625f), fv1 = floorf(ymax + 0.5625f);
+        // to pixels (f > 0 keeps the order), with the margin for the coordinates' rounding
+        // (1e-6 of their magnitude, about 8 ulps) at the nearest corner
+        const float mx = 0.5625f + 1e-6f * (amax / zmin) * c.fx;
+        const float my = 0.5625f + 1e-6f * (amax / zmin) * c.fy;
+        const float fu0 = ceilf(fmaf(c.fx, xmin, c.cx) - mx), fu1 = floorf(fmaf(c.fx, xmax, c.cx) + mx);
+        const float fv0 = ceilf(fmaf(c.fy, ymin, c.cy) - my), fv1 = floorf(fmaf(c.fy, ymax, c.cy) + my);
         if (fu1 < 0.0f || fu0 > c.wm1 || fv1 < 0.0f || fv0 > c.hm1) return false;
         u0 = (int)fmaxf(fu0, 0.0f);
         u1 = (int)fminf(fu1, c.wm1);
