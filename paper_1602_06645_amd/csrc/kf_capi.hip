@@ -555,10 +555,10 @@ kf_status cull_side(int device, CullSide** out)
     return KF_OK;
 }
 
-// Enqueue the pyramids and the passes of a plan whose tables live at `dev`; `grid`:
-// blocks of the geometry and colour persistent launches (resident_grid).  With `side`
-// (its mutex held by the caller) the culling runs one pass ahead on the side stream;
-// without it everything runs on `stream` in order.
+// Enqueue the pyramids, pixel maps and passes of a plan whose tables live at `dev`;
+// `grid`: blocks of the geometry and colour persistent launches (resident_grid).  With
+// `side` (its mutex held by the caller) the culling runs one pass ahead on the side stream
+// (the first pass's beside the pixel maps); without it everything runs on `stream` in order.
 kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned char* dev, int mode,
                          const int shape[2], unsigned long long* counters, const uint32_t grid[2],
                          hipStream_t stream, const PassEvents& ev = PassEvents(),
@@ -566,8 +566,6 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
 {
     const kf::FrameConsts* frames = (const kf::FrameConsts*)(dev + t.frames_off);
     KF_HIP(kf::launch_pyramids(frames, (int32_t)p.frames.size(), t.max_tiles0, stream), "pyramid launch");
-    KF_HIP(kf::launch_pixel_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
-           "pixel map launch");
     uint32_t* cnt = (uint32_t*)(dev + t.counters_off);
     KF_HIP(kf::launch_fill_u32(cnt, kPassCounters * (p.passes.size() + 1), 0u, stream), "counter reset");
     uint4* live = (uint4*)(dev + t.live_off);
@@ -593,9 +591,13 @@ kf_status enqueue_passes(const BatchPlan& p, const DeviceTables& t, unsigned cha
     };
     hipStream_t cs = side ? side->stream : stream;
     if (side && !run.empty()) {
+        // the first cull needs the pyramids and the cleared counters, not the pixel maps:
+        // it runs beside them
         KF_HIP(hipEventRecord(side->ev[0], stream), "hipEventRecord");
         KF_HIP(hipStreamWaitEvent(cs, side->ev[0], 0), "hipStreamWaitEvent");
     }
+    KF_HIP(kf::launch_pixel_maps(frames, (int32_t)p.frames.size(), t.max_pixels, stream),
+           "pixel map launch");
     for (size_t r = 0; r < run.size(); ++r) {
         const size_t q = run[r];
         if (!side) {

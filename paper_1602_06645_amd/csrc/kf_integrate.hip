@@ -223,9 +223,17 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
     if (!col.active) return;
     const float fi = (float)col.i, fj = (float)col.j;
     float F[BZ], W[BZ];
+    // The column's state is read whole at its first update of the pass and written back
+    // whole at the end (a voxel that no frame updated gets its own value back).  Per-voxel
+    // flags are one bool per voxel, held as lane masks in scalar registers, so testing them
+    // costs no vector instruction.
+    bool loaded = false;
+    bool touched[BZ];   // counted only: voxels updated in the pass
 #pragma unroll
-    for (int kk = 0; kk < BZ; ++kk) F[kk] = W[kk] = 0.0f;
-    uint32_t loaded = 0;
+    for (int kk = 0; kk < BZ; ++kk) {
+        F[kk] = W[kk] = 0.0f;
+        touched[kk] = false;
+    }
     unsigned long long n_upd = 0;
     for (unsigned long long m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctzll(m)];
@@ -238,7 +246,7 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         const float z_first = fmaf(c.Ag[8], (float)col.k0, cZ);
         const bool zpos = z_first > 0.0f;
         float sdf[BZ];
-        uint32_t upd = 0;
+        bool upd[BZ];
         auto sweep = [&](auto exact) {
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
@@ -250,11 +258,10 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
                 const float d = load_f32(depth, in ? px.pix * 4u : kOutside);
                 const bool valid = in & valid_depth(d);
                 sdf[kk] = d - Zc;
-                const bool u = valid & !(sdf[kk] < -c.trunc);
-                upd |= (uint32_t)u << kk;
+                upd[kk] = valid & !(sdf[kk] < -c.trunc);
                 if constexpr (MODE == MODE_STATUS) {
                     if (kk < col.kn)
-                        status[col.base + (size_t)kk * col.slice] = (uint8_t)(!px.inside ? 0 : !valid ? 1 : u ? 6 : 2);
+                        status[col.base + (size_t)kk * col.slice] = (uint8_t)(!px.inside ? 0 : !valid ? 1 : upd[kk] ? 6 : 2);
                 }
             }
         };
@@ -265,48 +272,64 @@ __device__ __forceinline__ void geom_brick(const Scene& sc, FramePtr frames, uns
         else
             sweep(std::false_type{});
         if constexpr (MODE != MODE_STATUS) {
-            const uint32_t need = upd & ~loaded;
-            if (need) {
+            bool any = false;
+#pragma unroll
+            for (int kk = 0; kk < BZ; ++kk) any |= upd[kk];
+            if (any & !loaded) {
                 const __amdgpu_buffer_rsrc_t tr = slab_rsrc(sc.tsdf, col), wr = slab_rsrc(sc.wg, col);
 #pragma unroll
                 for (int kk = 0; kk < BZ; ++kk) {
-                    const bool nk = (need >> kk) & 1u;
-                    const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
-                    const float f = load_f32(tr, o), w = load_f32(wr, o);
-                    F[kk] = nk ? f : F[kk];
-                    W[kk] = nk ? w : W[kk];
+                    const uint32_t o = col.off + (uint32_t)kk * col.zstride;   // past the slab: 0
+                    F[kk] = load_f32(tr, o);
+                    W[kk] = load_f32(wr, o);
                 }
-                loaded |= need;
+                loaded = true;
             }
+            // the truncated distances, then the divisions of the voxels whose distance
+            // changes, then the weights of all voxels without branches (in_vgpr keeps
+            // min(W + 1, w_max) in that one block of code, next to its addition, where it
+            // needs no quieting of its operands)
+            float t[BZ];
+            bool dv[BZ];
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
-                if ((upd >> kk) & 1u) {
-                    const float t = fminf(1.0f, sdf[kk] * c.inv_trunc);
-                    const float wn = W[kk] + 1.0f;
-                    // F + (t - F) / wn is F itself when t and F are the same float (then
-                    // t - F = +0), except for F = -0: skip the division in that case (free
-                    // space seen again, t = F = 1).
-                    const uint32_t tb = __builtin_bit_cast(uint32_t, t);
-                    const uint32_t fb = __builtin_bit_cast(uint32_t, F[kk]);
-                    if ((tb != fb) | (fb == 0x80000000u)) F[kk] = F[kk] + (t - F[kk]) / wn;
-                    W[kk] = fminf(wn, c.w_max);
+                t[kk] = fminf(1.0f, sdf[kk] * c.inv_trunc);
+                // F + (t - F) / (W + 1) is F itself when t and F are the same float (then
+                // t - F = +0), except for F = -0: skip the division in that case (free
+                // space seen again, t = F = 1).
+                const uint32_t tb = __builtin_bit_cast(uint32_t, t[kk]);
+                const uint32_t fb = __builtin_bit_cast(uint32_t, F[kk]);
+                dv[kk] = upd[kk] & ((tb != fb) | (fb == 0x80000000u));
+                if constexpr (MODE == MODE_COUNT) {
+                    n_upd += upd[kk] ? 1u : 0u;
+                    touched[kk] |= upd[kk];
                 }
             }
-            n_upd += (unsigned)__builtin_popcount(upd);
+#pragma unroll
+            for (int kk = 0; kk < BZ; ++kk)
+                if (dv[kk]) F[kk] = F[kk] + (t[kk] - F[kk]) / (W[kk] + 1.0f);
+#pragma unroll
+            for (int kk = 0; kk < BZ; ++kk) {
+                const float wc = in_vgpr(fminf(W[kk] + 1.0f, c.w_max));
+                W[kk] = upd[kk] ? wc : W[kk];
+            }
         }
     }
     if constexpr (MODE != MODE_STATUS) {
+        if (loaded) {
 #pragma unroll
-        for (int kk = 0; kk < BZ; ++kk) {
-            if ((loaded >> kk) & 1u) {
-                sc.tsdf[col.base + (size_t)kk * col.slice] = F[kk];
-                sc.wg[col.base + (size_t)kk * col.slice] = W[kk];
+            for (int kk = 0; kk < BZ; ++kk) {
+                if (kk < col.kn) {
+                    sc.tsdf[col.base + (size_t)kk * col.slice] = F[kk];
+                    sc.wg[col.base + (size_t)kk * col.slice] = W[kk];
+                }
             }
         }
     }
     if constexpr (MODE == MODE_COUNT) {
         cnt.g_upd += n_upd;
-        cnt.g_touch += (unsigned long long)__builtin_popcount(loaded);
+#pragma unroll
+        for (int kk = 0; kk < BZ; ++kk) cnt.g_touch += touched[kk] ? 1u : 0u;
     }
 }
 
@@ -356,10 +379,17 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
     const int lane = threadIdx.x & (WAVE - 1);
     const float fi = (float)col.i, fj = (float)col.j;
     float R[BZ], G[BZ], B[BZ], Wt[BZ];
+    // The column's colour weights are read whole when a voxel of it first reaches the gate,
+    // its colours when one first passes it; the column is written back whole if its colours
+    // were read (a voxel that no frame updated gets its own values back).  Per-voxel flags
+    // are one bool per voxel, held as lane masks in scalar registers.
+    bool wl = false, cl = false;
+    bool rd[BZ], tc[BZ];   // counted only: voxels whose weight was read / that were updated
 #pragma unroll
-    for (int kk = 0; kk < BZ; ++kk) R[kk] = G[kk] = B[kk] = Wt[kk] = 0.0f;
-    uint32_t wl = 0;   // colour weight read
-    uint32_t cl = 0;   // colour read and updated (stored at the end)
+    for (int kk = 0; kk < BZ; ++kk) {
+        R[kk] = G[kk] = B[kk] = Wt[kk] = 0.0f;
+        rd[kk] = tc[kk] = false;
+    }
     unsigned long long n_eval = 0, n_upd = 0;
     for (unsigned long long m = mask; m; m &= m - 1) {
         const auto& c = frames[__builtin_ctzll(m)];
@@ -375,7 +405,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         // depth, P (Eq. 7) and W from the frame's pixel map in one read; W is kept for the
         // voxels in the band.
         float wv[BZ];
-        uint32_t band = 0;
+        bool band[BZ];
         auto sweep = [&](auto exact) {
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
@@ -391,7 +421,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 const float dx = Xc - pm.y, dy = Yc - pm.z, dz = Zc - d;
                 const float dist2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                 const bool bd = valid & !(dist2 > c.sigma2);
-                band |= (uint32_t)bd << kk;
+                band[kk] = bd;
                 wv[kk] = bd ? pm.w : 0.0f;
                 if constexpr (MODE == MODE_STATUS) st[kk] = !px.inside ? 0 : !valid ? 1 : bd ? 3 : 2;
             }
@@ -406,33 +436,36 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         // Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dotted with the unit
         // viewing direction), the first read of their colour weight, and the gate against
         // the running weight.
-        uint32_t gate = 0;
-        if (band) {
-            uint32_t reach = 0;
+        bool gate[BZ], any_band = false, any_gate = false;
+#pragma unroll
+        for (int kk = 0; kk < BZ; ++kk) {
+            gate[kk] = false;
+            any_band |= band[kk];
+        }
+        if (any_band) {
+            bool reach[BZ], any_reach = false;
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
-                const bool ok = ((band >> kk) & 1u) & (__builtin_bit_cast(uint32_t, wv[kk]) != kNoNormal);
-                reach |= (uint32_t)ok << kk;
+                reach[kk] = band[kk] & (__builtin_bit_cast(uint32_t, wv[kk]) != kNoNormal);
+                any_reach |= reach[kk];
             }
-            const uint32_t needw = reach & ~wl;
-            if (needw) {
+            if (any_reach & !wl) {
                 const __amdgpu_buffer_rsrc_t wr = slab_rsrc(sc.wc, col);
 #pragma unroll
-                for (int kk = 0; kk < BZ; ++kk) {
-                    const bool nk = (needw >> kk) & 1u;
-                    const float w = load_f32(wr, nk ? col.off + (uint32_t)kk * col.zstride : kOutside);
-                    Wt[kk] = nk ? w : Wt[kk];
-                }
-                wl |= needw;
+                for (int kk = 0; kk < BZ; ++kk) Wt[kk] = load_f32(wr, col.off + (uint32_t)kk * col.zstride);
+                wl = true;
             }
-            n_eval += (unsigned)__builtin_popcount(reach);
 #pragma unroll
             for (int kk = 0; kk < BZ; ++kk) {
-                const bool rk = (reach >> kk) & 1u;
-                const bool gk = rk & (wv[kk] > c.gate * Wt[kk]);
-                gate |= (uint32_t)gk << kk;
+                const bool gk = reach[kk] & (wv[kk] > c.gate * Wt[kk]);
+                gate[kk] = gk;
+                any_gate |= gk;
+                if constexpr (MODE == MODE_COUNT) {
+                    n_eval += reach[kk] ? 1u : 0u;
+                    rd[kk] |= reach[kk];
+                }
                 if constexpr (MODE == MODE_STATUS)
-                    if (rk) st[kk] = gk ? 5 : 4;
+                    if (reach[kk]) st[kk] = gk ? 5 : 4;
             }
         }
         // (4) for every gated voxel of the wave: the HD pixel of its centre (Eq. 3-5), the
@@ -442,21 +475,19 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         // in order) and handed out to the active lanes in turn through LDS: a lane computes
         // the sample of another lane's voxel, and the owner blends the result into its
         // registers.  Same operations on the same values as in the owner's lane.
-        if (__ballot(gate != 0)) {
+        if (__ballot(any_gate)) {
             if constexpr (MODE != MODE_STATUS) {
-                const uint32_t needc = gate & ~cl;
-                if (needc) {
+                if (any_gate & !cl) {
                     const __amdgpu_buffer_rsrc_t rr = slab_rsrc(sc.r, col), gr = slab_rsrc(sc.g, col),
                                                  br = slab_rsrc(sc.b, col);
 #pragma unroll
                     for (int kk = 0; kk < BZ; ++kk) {
-                        const bool nk = (needc >> kk) & 1u;
-                        const uint32_t o = nk ? col.off + (uint32_t)kk * col.zstride : kOutside;
-                        const float r = load_f32(rr, o), g = load_f32(gr, o), b = load_f32(br, o);
-                        R[kk] = nk ? r : R[kk];
-                        G[kk] = nk ? g : G[kk];
-                        B[kk] = nk ? b : B[kk];
+                        const uint32_t o = col.off + (uint32_t)kk * col.zstride;
+                        R[kk] = load_f32(rr, o);
+                        G[kk] = load_f32(gr, o);
+                        B[kk] = load_f32(br, o);
                     }
+                    cl = true;
                 }
             }
             const unsigned long long act = __ballot(1);
@@ -464,18 +495,20 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             const uint32_t wrank = lane_rank(act);
             uint32_t total = 0;
 #pragma unroll
-            for (int kk = 0; kk < BZ; ++kk) total += (uint32_t)__builtin_popcountll(__ballot((gate >> kk) & 1u));
+            for (int kk = 0; kk < BZ; ++kk) total += (uint32_t)__builtin_popcountll(__ballot(gate[kk]));
             const int i0 = col.i - lane % BX, j0 = col.j - lane / BX;   // the brick's first column
             const int row = c.cw * 3;
             const bool nearest = c.hd_nearest != 0;
-            uint32_t upd = 0;
+            bool upd[BZ];
+#pragma unroll
+            for (int kk = 0; kk < BZ; ++kk) upd[kk] = false;
             for (uint32_t r0 = 0; r0 < total; r0 += n_act) {
                 // jobs r0 .. r0 + n_act - 1: each owner puts (voxel, W, W_c) into the slot
                 // of the lane that takes the job
                 uint32_t first = 0;
 #pragma unroll
                 for (int kk = 0; kk < BZ; ++kk) {
-                    const bool gk = (gate >> kk) & 1u;
+                    const bool gk = gate[kk];
                     const unsigned long long b = __ballot(gk);
                     const uint32_t q = first + lane_rank(b) - r0;
                     if (gk && q < n_act)
@@ -507,7 +540,7 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                 first = 0;
 #pragma unroll
                 for (int kk = 0; kk < BZ; ++kk) {
-                    const bool gk = (gate >> kk) & 1u;
+                    const bool gk = gate[kk];
                     const unsigned long long b = __ballot(gk);
                     const uint32_t q = first + lane_rank(b) - r0;
                     if (gk && q < n_act) {
@@ -521,16 +554,19 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
                                 B[kk] = fmaf(res.x, res.w - B[kk], B[kk]);
                                 Wt[kk] = fmaf(wv[kk], 1.0f - Wt[kk], Wt[kk]);
                             }
-                            upd |= 1u << kk;
+                            upd[kk] = true;
                         }
                     }
                     first += (uint32_t)__builtin_popcountll(b);
                 }
                 __builtin_amdgcn_wave_barrier();   // the slots are free for the next round
             }
-            if constexpr (MODE != MODE_STATUS) {
-                cl |= upd;
-                n_upd += (unsigned)__builtin_popcount(upd);
+            if constexpr (MODE == MODE_COUNT) {
+#pragma unroll
+                for (int kk = 0; kk < BZ; ++kk) {
+                    n_upd += upd[kk] ? 1u : 0u;
+                    tc[kk] |= upd[kk];
+                }
             }
         }
         if constexpr (MODE == MODE_STATUS) {
@@ -540,22 +576,27 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
         }
     }
     if constexpr (MODE != MODE_STATUS) {
+        if (cl) {   // a column outside the volume never reads
 #pragma unroll
-        for (int kk = 0; kk < BZ; ++kk) {
-            if ((cl >> kk) & 1u) {
-                const size_t idx = col.base + (size_t)kk * col.slice;
-                sc.r[idx] = R[kk];
-                sc.g[idx] = G[kk];
-                sc.b[idx] = B[kk];
-                sc.wc[idx] = Wt[kk];
+            for (int kk = 0; kk < BZ; ++kk) {
+                if (kk < col.kn) {
+                    const size_t idx = col.base + (size_t)kk * col.slice;
+                    sc.r[idx] = R[kk];
+                    sc.g[idx] = G[kk];
+                    sc.b[idx] = B[kk];
+                    sc.wc[idx] = Wt[kk];
+                }
             }
         }
     }
     if constexpr (MODE == MODE_COUNT) {
         cnt.c_eval += n_eval;
-        cnt.c_read += (unsigned long long)__builtin_popcount(wl);
         cnt.c_upd += n_upd;
-        cnt.c_touch += (unsigned long long)__builtin_popcount(cl);
+#pragma unroll
+        for (int kk = 0; kk < BZ; ++kk) {
+            cnt.c_read += rd[kk] ? 1u : 0u;
+            cnt.c_touch += tc[kk] ? 1u : 0u;
+        }
     }
 }
 
