@@ -16,7 +16,10 @@ __device__ __forceinline__ bool valid_depth(float d)
 
 // Valid-depth (min, max) over pixels [u0,u1] x [v0,v1] (inclusive, inside the image),
 // read from the finest pyramid level on which the box spans at most 4 x 4 tiles.  The
-// tiles cover the box, so the range contains every depth inside it.
+// tiles cover the box, so the range contains every depth inside it.  A tile holds the
+// (min, max) of its valid depths, which are positive, or (+inf, -inf) when it has none:
+// no NaN, so the bit patterns order as signed integers exactly as the floats do, and the
+// integer min and max need no quieting of their operands.
 template <class C>
 __device__ inline float2 depth_range(const C& c, int u0, int u1, int v0, int v1)
 {
@@ -24,14 +27,14 @@ __device__ inline float2 depth_range(const C& c, int u0, int u1, int v0, int v1)
     for (int l = 0; l < c.pyr_levels; ++l) {
         const int tx0 = u0 >> s, tx1 = u1 >> s, ty0 = v0 >> s, ty1 = v1 >> s;
         if ((tx1 - tx0 <= 3 && ty1 - ty0 <= 3) || l == c.pyr_levels - 1) {
-            float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
+            int32_t lo = 0x7F800000, hi = (int32_t)0xFF800000;   // +inf, -inf
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const float2 r = c.pyr[off + ty * w + tx];
-                    dmin = fminf(dmin, r.x);
-                    dmax = fmaxf(dmax, r.y);
+                    lo = min(lo, __builtin_bit_cast(int32_t, r.x));
+                    hi = max(hi, __builtin_bit_cast(int32_t, r.y));
                 }
-            return make_float2(dmin, dmax);
+            return make_float2(__builtin_bit_cast(float, lo), __builtin_bit_cast(float, hi));
         }
         off += w * h;
         w = (w + 1) / 2;
@@ -98,8 +101,9 @@ __device__ inline bool brick_live(const C& c, bool colour, int i0, int i1, int j
     if (!near) {
         // to pixels (f > 0 keeps the order), with the margin for the coordinates' rounding
         // (1e-6 of their magnitude, about 8 ulps) at the nearest corner
-        const float mx = 0.5625f + 1e-6f * (amax / zmin) * c.fx;
-        const float my = 0.5625f + 1e-6f * (amax / zmin) * c.fy;
+        const float rel = 1e-6f * amax * __builtin_amdgcn_rcpf(zmin);   // the ratio to 1 ulp
+        const float mx = 0.5625f + rel * c.fx;
+        const float my = 0.5625f + rel * c.fy;
         const float fu0 = ceilf(fmaf(c.fx, xmin, c.cx) - mx), fu1 = floorf(fmaf(c.fx, xmax, c.cx) + mx);
         const float fv0 = ceilf(fmaf(c.fy, ymin, c.cy) - my), fv1 = floorf(fmaf(c.fy, ymax, c.cy) + my);
         if (fu1 < 0.0f || fu0 > c.wm1 || fv1 < 0.0f || fv0 > c.hm1) return false;

@@ -609,23 +609,23 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x)
 
 }  // namespace
 
-// One block per culling chunk (CHUNK^3 bricks of one kind).  The first wave tests the
-// chunk's voxel box against the frames of the pass (one lane per frame) and lists the
-// frames it passed; the block then tests the (brick, listed frame) pairs, one per thread
-// (frame-major), and ORs each live pair's frame bit into its brick's mask in LDS.
-// Skipping the other frames is exact: the chunk test is conservative for every voxel of
-// the chunk, as the brick test is for every voxel of the brick.  The first wave appends
-// the bricks with a non-empty mask to the heavy or the light list in brick order, with
-// one atomic per list and block (geometry from the front, colour from the back).
+// One wave per culling chunk (CHUNK^3 bricks of one kind), four chunks per block, each
+// wave on its own: it tests the chunk's voxel box against the frames of the pass (one lane
+// per frame), then its bricks (one lane per brick) against each frame the chunk passed in
+// turn, the frame being wave-uniform there so that its constants come through scalar
+// loads; a lane collects its brick's frame mask in a register.  Skipping the other frames
+// is exact: the chunk test is conservative for every voxel of the chunk, as the brick test
+// is for every voxel of the brick.  The wave then appends its bricks with a non-empty mask
+// to the heavy or the light list in brick order, with one atomic per list (geometry from
+// the front, colour from the back).
 constexpr int CHUNK_BRICKS = CHUNK * CHUNK * CHUNK;
-static_assert(CHUNK_BRICKS <= WAVE, "one lane per brick of a chunk in the append");
+static_assert(CHUNK_BRICKS <= WAVE, "one lane per brick of a chunk");
+constexpr int CULL_WAVES = BLOCK / WAVE;   // chunks per block
 
 __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
 {
-    __shared__ unsigned long long s_mask[CHUNK_BRICKS];
-    __shared__ uint8_t s_frame[64];
-    __shared__ uint32_t s_nf;
-    const uint32_t chunk = blockIdx.x;
+    const uint32_t chunk = first_lane_u32(blockIdx.x * (uint32_t)CULL_WAVES + threadIdx.x / WAVE);
+    if (chunk >= a.n_chunks) return;
     int s = 0;
     while (s + 1 < a.n_scenes && a.scenes[s + 1].chunk_begin <= chunk) ++s;
     const SceneDev& sc = a.scenes[s];
@@ -643,69 +643,54 @@ __global__ __launch_bounds__(BLOCK) void cull_kernel(CullArgs a)
     const int nbx = min(CHUNK, nb[0] - bx0), nby = min(CHUNK, nb[1] - by0), nbz = min(CHUNK, nb[2] - bz0);
     const FrameConsts* frames = a.frames + sc.frame_begin;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (threadIdx.x < WAVE) {
-        bool live = false;
-        if (lane < sc.n_frames) {
-            const int i0 = bx0 * BX, i1 = min(dim[0], (bx0 + nbx) * BX) - 1;
-            const int j0 = by0 * BY, j1 = min(dim[1], (by0 + nby) * BY) - 1;
-            const int k0 = bz0 * BZ, k1 = min(dim[2], (bz0 + nbz) * BZ) - 1;
-            live = a.disable || brick_live(frames[lane], colour, i0, i1, j0, j1, k0, k1);
-        }
-        const unsigned long long m = __ballot(live);
-        if (live) s_frame[__builtin_popcountll(m & ((1ull << lane) - 1ull))] = (uint8_t)lane;
-        if (lane == 0) s_nf = (uint32_t)__builtin_popcountll(m);
-        if (lane < CHUNK_BRICKS) s_mask[lane] = 0ull;
+    bool chunk_live = false;
+    if (lane < sc.n_frames) {
+        const int i0 = bx0 * BX, i1 = min(dim[0], (bx0 + nbx) * BX) - 1;
+        const int j0 = by0 * BY, j1 = min(dim[1], (by0 + nby) * BY) - 1;
+        const int k0 = bz0 * BZ, k1 = min(dim[2], (bz0 + nbz) * BZ) - 1;
+        chunk_live = a.disable || brick_live(frames[lane], colour, i0, i1, j0, j1, k0, k1);
     }
-    __syncthreads();
-    const uint32_t nf = s_nf;
-    if (nf == 0) return;   // the whole block: no brick of the chunk is live
+    const unsigned long long fm = __ballot(chunk_live);
+    if (fm == 0ull) return;   // no brick of the chunk is live
     const uint32_t nbr = (uint32_t)(nbx * nby * nbz);
-    // one lane per brick of the chunk, the waves taking the listed frames in turn: a wave's
-    // frame is uniform, so its constants come through scalar loads
+    const uint32_t q = (uint32_t)lane;
+    const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
+    const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
+    unsigned long long mask = 0ull;
     {
-        const uint32_t q = (uint32_t)lane;
-        const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
-        const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
         const int i0 = bx * BX, i1 = min(dim[0], i0 + BX) - 1;
         const int j0 = by * BY, j1 = min(dim[1], j0 + BY) - 1;
         const int k0 = bz * BZ, k1 = min(dim[2], k0 + BZ) - 1;
         const const_ptr<FrameConsts> cframes = as_const(frames);
-        for (uint32_t r = threadIdx.x / WAVE; r < nf; r += BLOCK / WAVE) {
-            const int f = (int)first_lane_u32(s_frame[r]);
+        for (unsigned long long m = fm; m; m &= m - 1) {   // wave-uniform
+            const int f = __builtin_ctzll(m);
             if (q < nbr && (a.disable || brick_live(cframes[f], colour, i0, i1, j0, j1, k0, k1)))
-                atomicOr(&s_mask[q], 1ull << f);   // the four waves OR into the same masks
+                mask |= 1ull << f;
         }
     }
-    __syncthreads();
-    if (threadIdx.x < WAVE) {
-        const uint32_t q = (uint32_t)lane;
-        const unsigned long long mask = q < nbr ? s_mask[q] : 0ull;
-        const unsigned long long has = __ballot(mask != 0ull);
-        if (has == 0ull) return;
-        // bricks live in at least half of the pass's frames go to the heavy list, which the
-        // integration drains first (longest first shortens the launch's tail)
-        const bool heavy = 2u * (uint32_t)__builtin_popcountll(mask) >= (uint32_t)a.max_frames;
-        const unsigned long long hv = __ballot(mask != 0ull && heavy), lt = has & ~hv;
-        const int kind = colour ? KIND_COLOUR : KIND_GEOM;
-        uint32_t base_h = 0, base_l = 0;
-        if (lane == 0) {
-            if (hv) base_h = atomicAdd(a.n_live + kind, (uint32_t)__builtin_popcountll(hv));
-            if (lt) base_l = atomicAdd(a.n_live + 2 + kind, (uint32_t)__builtin_popcountll(lt));
-        }
-        base_h = __shfl(base_h, 0, WAVE);
-        base_l = __shfl(base_l, 0, WAVE);
-        if (mask != 0ull) {
-            const int bx = bx0 + (int)(q % (uint32_t)nbx), by = by0 + (int)((q / (uint32_t)nbx) % (uint32_t)nby);
-            const int bz = bz0 + (int)(q / (uint32_t)(nbx * nby));
-            const uint32_t li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
-            const uint32_t item = sc.item_begin + (colour ? sc.geom_items : 0u) + li;
-            const unsigned long long below = (1ull << lane) - 1ull;
-            const bool h = (hv >> lane) & 1ull;
-            const uint32_t pos = h ? base_h + (uint32_t)__builtin_popcountll(hv & below)
-                                   : base_l + (uint32_t)__builtin_popcountll(lt & below);
-            uint4* list = a.live + (h ? 0u : a.n_items);
-            list[colour ? a.n_items - 1u - pos : pos] = make_uint4(item, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
-        }
+    const unsigned long long has = __ballot(mask != 0ull);
+    if (has == 0ull) return;
+    // bricks live in at least half of the pass's frames go to the heavy list, which the
+    // integration drains first (longest first shortens the launch's tail)
+    const bool heavy = 2u * (uint32_t)__builtin_popcountll(mask) >= (uint32_t)a.max_frames;
+    const unsigned long long hv = __ballot(mask != 0ull && heavy), lt = has & ~hv;
+    const int kind = colour ? KIND_COLOUR : KIND_GEOM;
+    uint32_t base_h = 0, base_l = 0;
+    if (lane == 0) {
+        if (hv) base_h = atomicAdd(a.n_live + kind, (uint32_t)__builtin_popcountll(hv));
+        if (lt) base_l = atomicAdd(a.n_live + 2 + kind, (uint32_t)__builtin_popcountll(lt));
+    }
+    base_h = __shfl(base_h, 0, WAVE);
+    base_l = __shfl(base_l, 0, WAVE);
+    if (mask != 0ull) {
+        const uint32_t li = (uint32_t)bx + (uint32_t)nb[0] * ((uint32_t)by + (uint32_t)nb[1] * (uint32_t)bz);
+        const uint32_t item = sc.item_begin + (colour ? sc.geom_items : 0u) + li;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const bool h = (hv >> lane) & 1ull;
+        const uint32_t pos = h ? base_h + (uint32_t)__builtin_popcountll(hv & below)
+                               : base_l + (uint32_t)__builtin_popcountll(lt & below);
+        uint4* list = a.live + (h ? 0u : a.n_items);
+        list[colour ? a.n_items - 1u - pos : pos] = make_uint4(item, (uint32_t)mask, (uint32_t)(mask >> 32), 0u);
     }
 }
 
@@ -920,7 +905,7 @@ hipError_t launch_cull(const CullArgs& a, hipStream_t stream)
 {
     if (a.n_chunks == 0) return hipSuccess;
     if (a.max_frames > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(cull_kernel, dim3(a.n_chunks), dim3(BLOCK), 0, stream, a);
+    hipLaunchKernelGGL(cull_kernel, dim3((a.n_chunks + CULL_WAVES - 1) / CULL_WAVES), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 
