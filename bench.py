@@ -77,12 +77,23 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
+    """Hash of the integration kernels' code: their sources with comments and blank space
+    taken out, so that a change of comments alone keeps the recorded traffic valid.
+    `sources`: the three files' texts (default: read from the package)."""
     import hashlib
+    import re
+    names = ("kf_integrate.hip", "kf_device.h", "kf_cull.h")
+    if sources is None:
+        sources = []
+        for name in names:
+            with open(os.path.join(ROOT, "paper_1602_06645_amd", "csrc", name)) as f:
+                sources.append(f.read())
     h = hashlib.sha256()
-    for name in ("kf_integrate.hip", "kf_device.h", "kf_cull.h"):
-        with open(os.path.join(ROOT, "paper_1602_06645_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    for text in sources:
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -363,11 +363,12 @@ __device__ __forceinline__ HdCell hd_cell(const C& c, float fi, float fj, float 
 }
 
 // Sec. IV.B in the paper's order of tests, then Eq. 9 and Eq. 10, for the frames of mask.
-// Per frame, in stages over the column's eight voxels so that the loads of a stage are in
-// flight together: (1) frustum, depth and sigma tests; (2) the Eq. 8 neighbour depths of
-// the voxels in the band; (3) normals and weights, and the first read of the colour
-// weight of the voxels that reach the gate; (4) gate, HD pixel, Eq. 9 and Eq. 10.  The
-// column's colour state lives in registers for the whole pass.
+// Per frame, in stages over the column's voxels so that the loads of a stage are in flight
+// together: (1) frustum, depth and sigma tests, each voxel reading its pixel's map entry
+// (depth, Eq. 7's P, Eq. 8's weight); (2)-(3) the voxels in the band whose pixel has a
+// normal, and the gate against the running weight; (4) HD pixel, Eq. 9 and Eq. 10 for the
+// gated voxels, shared out over the wave.  The column's colour state lives in registers
+// for the whole pass.
 template <int MODE, int BX, int BY, int BZ, class Scene, class FramePtr>
 __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, unsigned long long mask,
                                              uint32_t li, uint8_t* status, float4* slots, Counts& cnt)
@@ -434,8 +435,8 @@ __device__ __forceinline__ void colour_brick(const Scene& sc, FramePtr frames, u
             sweep(std::false_type{});
         // (2)-(3) the voxels in the band whose pixel has a normal (W of the pixel map: the
         // Eq. 8 normal from the neighbours (u+1, v) and (u, v+1), dotted with the unit
-        // viewing direction), the first read of their colour weight, and the gate against
-        // the running weight.
+        // viewing direction), the read of the column's colour weights when one of them first
+        // reaches this point, and the gate against the running weight.
         bool gate[BZ], any_band = false, any_gate = false;
 #pragma unroll
         for (int kk = 0; kk < BZ; ++kk) {
