@@ -520,20 +520,21 @@ def kinect_legs(out, legs, kf, configs, np, torch):
         scan32 = kf.Scan(fr.depth[:nb], rgbf.contiguous(), fr.K_d, fr.K_rgb, fr.T_rgb_from_d,
                          fr.T_world_from_cam[:nb], fr.trunc, fr.w_max)
         g = configs.gradient_weights(spec.n_colour, device="cuda")
+        Bb = autotune.bricks("kinect")   # the forward with the kinect scan's tuned shapes
 
         def fwd_bwd():
             vol.reset()
-            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
+            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb, bricks=Bb)
             return kf.integrate_backward(spec, scan32, g)
 
         def fwd_bwd_pose():
             vol.reset()
-            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb)
+            kf.integrate_batch([(vol, scan32)], frames_per_pass=nb, bricks=Bb)
             return kf.integrate_backward(spec, scan32, g, pose=True)
         fwd_bwd()
         res["fwd_bwd_ms"] = 1e3 * timed_reps(fwd_bwd, 3)
         res["fwd_bwd_config"] = (f"first {nb} frames, float32 RGB, full volume, g ~ N(0,1) on "
-                                 "every colour voxel")
+                                 "every colour voxel; forward with the kinect scan's tuned bricks")
         log(f"forward+backward ({nb} frames): {res['fwd_bwd_ms']:.2f} ms")
         fwd_bwd_pose()
         res["fwd_bwd_pose_ms"] = 1e3 * timed_reps(fwd_bwd_pose, 3)
