@@ -570,44 +570,23 @@ __global__ __launch_bounds__(IMG_BLOCK) void backward_image_kernel(BackwardArgs 
     for (uint32_t s = b0 + (uint32_t)(t / WAVE); s < b1; s += IMG_BLOCK / WAVE) {
         const uint4 sg = a.segs[first_lane_u32(a.bin_segs[s])];
         const uint32_t first = first_lane_u32(sg.x), cnt = first_lane_u32(sg.y);
-        // A lane's successive records (64 apart: in a brick updated throughout, the same
-        // column one z slice further) often share their bilinear cell, so the lane sums
-        // them in registers and adds to the tile only when its cell changes: far fewer LDS
-        // float atomics, which are most of this kernel's time.
-        uint32_t cur = 0;     // the cell summed in acc
-        bool have = false;    // acc holds a cell
-        float acc[4][3];
-        auto flush = [&]() {
-            const int x0 = (int)(cur & 0xFFFFu), y0 = (int)(cur >> 16);
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int lx = x0 + (p & 1) - tx0, ly = y0 + (p >> 1) - ty0;
-                if (lx < 0 || lx >= BWD_TILE_W || ly < 0 || ly >= BWD_TILE_H) continue;
-                float* dst = s_acc + (ly * BWD_TILE_W + lx) * 3;
-                for (int ch = 0; ch < 3; ++ch)
-                    if (acc[p][ch] != 0.0f) atomicAdd(dst + ch, acc[p][ch]);
-            }
-        };
         for (uint32_t r = (uint32_t)lane; r < cnt; r += WAVE) {
             const float2* rec = (const float2*)(a.records + ((size_t)first + r) * 6);
             const float2 r0 = rec[0], r1 = rec[1], r2 = rec[2];
             const uint32_t cell = __builtin_bit_cast(uint32_t, r0.x);   // x | y << 16
             const float ax = r0.y, ay = r1.x;
             const float gv[3] = {r1.y, r2.x, r2.y};
+            const int x0 = (int)(cell & 0xFFFFu), y0 = (int)(cell >> 16);
             const float w[4] = {(1.0f - ax) * (1.0f - ay), ax * (1.0f - ay), (1.0f - ax) * ay, ax * ay};
-            if (!have || cell != cur) {
-                if (have) flush();
-                cur = cell;
-                have = true;
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
-                    for (int ch = 0; ch < 3; ++ch) acc[p][ch] = 0.0f;
+            for (int p = 0; p < 4; ++p) {
+                const int lx = x0 + (p & 1) - tx0, ly = y0 + (p >> 1) - ty0;
+                if (lx < 0 || lx >= BWD_TILE_W || ly < 0 || ly >= BWD_TILE_H) continue;
+                float* acc = s_acc + (ly * BWD_TILE_W + lx) * 3;
+                for (int ch = 0; ch < 3; ++ch)
+                    if (gv[ch] != 0.0f) atomicAdd(acc + ch, gv[ch] * w[p]);
             }
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-                for (int ch = 0; ch < 3; ++ch) acc[p][ch] += gv[ch] * w[p];
         }
-        if (have) flush();
     }
     __syncthreads();
     float* dimg = a.d_rgb + (size_t)f * (size_t)c.cw * (size_t)c.ch * 3;
