@@ -718,14 +718,17 @@ __global__ __launch_bounds__(BLOCK) void pyramid_base_kernel(const FrameConsts* 
     c.pyr[t] = make_float2(dmin, dmax);
 }
 
-// Levels 1.. : one block per frame, each level the 2x2 reduction of the previous one.
-__global__ __launch_bounds__(BLOCK) void pyramid_up_kernel(const FrameConsts* frames)
+// Levels 1.. : one block of 16 waves per frame, each level the 2x2 reduction of the
+// previous one.
+constexpr int PYR_UP_BLOCK = 1024;
+
+__global__ __launch_bounds__(PYR_UP_BLOCK) void pyramid_up_kernel(const FrameConsts* frames)
 {
     const FrameConsts& c = frames[blockIdx.x];
     int w = c.pyr_w0, h = c.pyr_h0, off = 0;
     for (int l = 1; l < c.pyr_levels; ++l) {
         const int nw = (w + 1) / 2, nh = (h + 1) / 2, noff = off + w * h;
-        for (int t = threadIdx.x; t < nw * nh; t += BLOCK) {
+        for (int t = threadIdx.x; t < nw * nh; t += PYR_UP_BLOCK) {
             const int tx = t % nw, ty = t / nw;
             float dmin = __builtin_huge_valf(), dmax = -__builtin_huge_valf();
             for (int y = 2 * ty; y < min(h, 2 * ty + 2); ++y)
@@ -887,7 +890,7 @@ hipError_t launch_pyramids(const FrameConsts* frames_dev, int32_t n_frames, int3
                        frames_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pyramid_up_kernel, dim3((unsigned)n_frames), dim3(BLOCK), 0, stream,
+    hipLaunchKernelGGL(pyramid_up_kernel, dim3((unsigned)n_frames), dim3(PYR_UP_BLOCK), 0, stream,
                        frames_dev);
     return hipGetLastError();
 }
